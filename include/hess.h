@@ -1,0 +1,181 @@
+/*
+ * hess.h -- C ABI of the MI355X (gfx950) library for the exact Hessian, the
+ * Outer-Product-of-Gradients (OPG) matrix and their leading eigenpairs for the
+ * mean softmax cross-entropy cost of a dense feed-forward network.
+ *
+ * Model and notation (paper, Sec. 2): layers l = 1..L with widths T_l; weights
+ * W^(l-1) in R^{T_l x T_{l-1}}, biases b^(l) in R^{T_l}; hidden activations
+ * sigma^(l) (l = 2..L-1); softmax output; cost C = (1/N) sum_n C_n, the mean
+ * per-example cross-entropy against one-hot targets y_n.
+ *
+ * Parameter layout (paper, Sec. 2, the flatten definition): every P-vector and
+ * every P x P matrix uses the flat order W^(1) row-major (index i*T_1 + j, i the
+ * output unit, j the input unit), then b^(2), then W^(2), b^(3), ...
+ * P = T_1 T_2 + T_2 + ... + T_{L-1} T_L + T_L.
+ *
+ * Conventions for every entry point:
+ *   - All array arguments marked "device" are device pointers on the context's
+ *     device; the caller owns them.  "host" arrays are read during the call only.
+ *   - Work is issued on the context's stream.  Every call returns after its
+ *     results are in device memory (it synchronises the stream), so results can be
+ *     read on any stream afterwards.
+ *   - Scratch memory is supplied by the caller as (ws, ws_bytes); the required size
+ *     comes from hess_workspace_size.  The library allocates no device memory.
+ *   - Arguments are validated before any work is launched.  On any error the
+ *     outputs are unspecified, nothing else changes, and hess_last_error gives a
+ *     message.  A context is not thread-safe: use one context per host thread.
+ */
+#ifndef HESS_H
+#define HESS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hess_ctx hess_ctx;
+
+typedef enum {
+  HESS_OK = 0,
+  HESS_E_ARG = 1,         /* null pointer or enum out of range */
+  HESS_E_SHAPE = 2,       /* L < 2, a width < 1, N < 1, K/B out of range, P overflow */
+  HESS_E_LABEL = 3,       /* a row of Y is not exactly one-hot */
+  HESS_E_NONFINITE = 4,   /* NaN or Inf in an input array */
+  HESS_E_WORKSPACE = 5,   /* ws is NULL or ws_bytes below hess_workspace_size */
+  HESS_E_BUDGET = 6,      /* footprint above the context's HBM budget */
+  HESS_E_DEVICE = 7,      /* HIP runtime error (or the injected test fault) */
+  HESS_E_NOCONV = 8,      /* eigensolver reached max_iter; best iterate returned */
+  HESS_E_NOTPD = 9,       /* lambda_k + delta <= 0 in the damped query */
+  HESS_E_UNSUPPORTED = 10 /* precision not offered for this operation */
+} hess_status;
+
+typedef enum { HESS_TANH = 0, HESS_SIGMOID = 1, HESS_RELU = 2 } hess_act;
+
+/* Storage type of W, b, X, Y (and V, Q where stated). */
+typedef enum { HESS_F64 = 0, HESS_F32 = 1 } hess_dtype;
+
+/* Arithmetic of the P x P contractions.  The per-example forward/backward
+ * passes and curvature factors are always computed in FP64.
+ *   HESS_P_F64   FP64 MFMA, FP64 output
+ *   HESS_P_F32   FP32 MFMA with FP32 accumulation, FP32 output
+ *   HESS_P_BF16  OPG only: per-example gradient tiles rounded to BF16 (round to
+ *                nearest even), BF16 MFMA with FP32 accumulation, FP32 output */
+typedef enum { HESS_P_F64 = 0, HESS_P_F32 = 1, HESS_P_BF16 = 2 } hess_prec;
+
+typedef struct {
+  int32_t L;               /* number of layers including the input layer, L >= 2 */
+  const int64_t* T;        /* host, T[0..L-1] = T_1..T_L, each >= 1 */
+  const int32_t* act;      /* host, act[0..L-3] = sigma^(2)..sigma^(L-1) (hess_act) */
+  int32_t dtype;           /* hess_dtype of every W[k] and b[k] */
+  const void* const* W;    /* host array of L-1 device pointers: W[k] = W^(k+1), T_{k+2} x T_{k+1} row-major */
+  const void* const* b;    /* host array of L-1 device pointers: b[k] = b^(k+2), T_{k+2} entries */
+} hess_mlp;
+
+typedef struct {
+  int64_t N;               /* number of examples, >= 1 */
+  int32_t dtype;           /* hess_dtype of X and Y */
+  const void* X;           /* device, N x T_1 row-major */
+  const void* Y;           /* device, N x T_L row-major, every row exactly one-hot */
+} hess_data;
+
+/* Operation codes for hess_workspace_size. */
+typedef enum {
+  HESS_OP_EXACT = 0, HESS_OP_OPG = 1, HESS_OP_HVP = 2, HESS_OP_TOPK = 3, HESS_OP_PREDVAR = 4
+} hess_op;
+
+/* Create a context on `device`; `stream` is a hipStream_t (NULL = the null stream). */
+hess_status hess_create(hess_ctx** ctx, int device, void* stream);
+hess_status hess_destroy(hess_ctx* ctx);
+const char* hess_status_str(hess_status s);
+/* Message describing the last error on this context ("" if none). */
+const char* hess_last_error(const hess_ctx* ctx);
+
+/* Context options.  HESS_OPT_CHECK_INPUTS (default 1): run the device-side
+ * finiteness / one-hot check pass before each call.  HESS_OPT_HBM_BUDGET: bytes of
+ * outputs + workspace a call may touch (0 = unlimited); above it a call returns
+ * HESS_E_BUDGET before launching anything.  HESS_OPT_FAULT_AFTER: test hook; when
+ * >= 0, the call during which that many kernel launches have been issued on this
+ * context reports HESS_E_DEVICE (no kernel faults; the launch is skipped). */
+typedef enum { HESS_OPT_CHECK_INPUTS = 0, HESS_OPT_HBM_BUDGET = 1, HESS_OPT_FAULT_AFTER = 2 } hess_opt;
+hess_status hess_set_option(hess_ctx* ctx, int opt, int64_t value);
+
+/* P of the model (Sec. 2).  Host-only; validates the widths. */
+hess_status hess_num_params(const hess_mlp* m, int64_t* P);
+
+/* Bytes of workspace `op` needs.  `arg` is B for HESS_OP_HVP, K for HESS_OP_TOPK,
+ * the number of queries for HESS_OP_PREDVAR, unused otherwise.  For HESS_OP_TOPK
+ * `opts` is a const hess_eig_opts*, else NULL.  `data` may be NULL for
+ * HESS_OP_PREDVAR and for HESS_OP_TOPK with a dense source. */
+hess_status hess_workspace_size(hess_ctx* ctx, int op, const hess_mlp* m, const hess_data* d,
+                                int prec, int64_t arg, const void* opts, size_t* bytes);
+
+/* Exact Hessian H = (1/N) sum_n d^2 C_n / d omega d omega^T (paper, Sec. 3, the
+ * Hessian definition), assembled from forward-over-reverse Hessian-vector products
+ * (Sec. 5.1, Appendix A.1) through every layer's W, b and sigma.
+ * H: device, P x P row-major, FP64 for HESS_P_F64 else FP32; exactly symmetric
+ * (every entry below the diagonal is computed once and mirrored).
+ * prec: HESS_P_F64 or HESS_P_F32 (HESS_P_BF16 -> HESS_E_UNSUPPORTED). */
+hess_status hess_exact(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int prec,
+                       void* H, void* ws, size_t ws_bytes);
+
+/* OPG = (1/N) sum_n grad C_n grad C_n^T = J^T J / N with J[n,:] = grad C_n
+ * (paper, Sec. 3, the OPG definition and its Jacobian form; J is never stored).
+ * G: device, P x P row-major, FP64 for HESS_P_F64 else FP32, exactly symmetric. */
+hess_status hess_opg(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int prec,
+                     void* G, void* ws, size_t ws_bytes);
+
+/* Hessian-vector products for B directions (paper, Sec. 5.1 and Appendix A.1):
+ * HV[b,:] = H V[b,:].  V, HV: device, B x P row-major (direction-contiguous), FP64
+ * for HESS_P_F64 else FP32.  prec: HESS_P_F64 or HESS_P_F32. */
+hess_status hess_hvp(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int prec,
+                     int64_t B, const void* V, void* HV, void* ws, size_t ws_bytes);
+
+typedef struct {
+  int32_t which;        /* 0 = H, 1 = OPG (used when source == 0) */
+  int32_t source;       /* 0 = matrix-free operator from (m, d); 1 = dense symmetric M */
+  const void* M;        /* source == 1: device, P x P row-major symmetric */
+  int32_t M_dtype;      /* source == 1: hess_dtype of M */
+  int32_t prec;         /* source == 0: hess_prec of the operator (HESS_P_F64 / HESS_P_F32) */
+  int64_t P;            /* source == 1: order of M (m may be NULL) */
+  int64_t oversample;   /* block size b = roundup(K + oversample, 16); default 10 if < 0 */
+  int32_t max_iter;     /* cap on subspace iterations (default 200 if <= 0) */
+  double tol;           /* stop when max_k ||M q_k - theta_k q_k|| <= tol * |theta_1| */
+  uint64_t seed;        /* seed of the counter-based start block */
+} hess_eig_opts;
+
+typedef struct {
+  int32_t iters;             /* subspace iterations run */
+  int32_t applies;           /* operator applications (block products) */
+  double max_rel_residual;   /* max_k ||M q_k - theta_k q_k|| / |theta_1| at exit */
+  double shift_used;         /* spectral shift used for the algebraically-largest search */
+} hess_eig_info;
+
+/* K algebraically largest eigenpairs of H or the OPG (paper, Sec. 4.1, 5.3, 5.4:
+ * which='LA', sorted descending), by randomized subspace iteration with FP64
+ * Cholesky-QR re-orthogonalisation and FP64 Rayleigh-Ritz.
+ * lambda: device, K doubles, descending.  Q: device, K x P row-major doubles
+ * (row k = eigenvector k, orthonormal, largest-|.| component positive).
+ * Returns HESS_E_NOCONV (with the best iterate written) at max_iter. */
+hess_status hess_topk_eig(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int64_t K,
+                          const hess_eig_opts* opts, double* lambda, double* Q,
+                          hess_eig_info* info, void* ws, size_t ws_bytes);
+
+/* Damped curvature query (Laplace-style predictive variance) for nq inputs:
+ * s_q = g_q^T (Q^T diag(lambda) Q + delta I)^{-1} g_q with g_q = d z^(L)_{c_q}(x_q)/d omega,
+ * evaluated as sum_k (q_k.g)^2/(lambda_k+delta) + (|g|^2 - sum_k (q_k.g)^2)/delta
+ * (the full-rank construction of Sec. 4.2 / Appendix A.2 with the complement
+ * eigenvalue delta).  Xq: device, nq x T_1 (dtype m->dtype); cls: device int32
+ * nq entries (-1 = arg-max of the prediction, lowest index on ties) or NULL
+ * (all arg-max); lambda: device K doubles; Q: device K x P row-major doubles
+ * (orthonormal rows); s: device nq doubles.  HESS_E_NOTPD if lambda_k + delta <= 0. */
+hess_status hess_predvar(hess_ctx* ctx, const hess_mlp* m, int64_t K, const double* lambda,
+                         const double* Q, double delta, int64_t nq, const void* Xq,
+                         const int32_t* cls, double* s, void* ws, size_t ws_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HESS_H */

@@ -271,13 +271,13 @@ def hvp(model: Model, X, Y, V):
         VW[l] = V[:, ow:ob].reshape(Bn, T[l - 1], T[l - 2])
         Vb[l] = V[:, ob:ob + T[l - 1]]
     RZ = [None] * (L + 1)
-    RA = [None] * (L + 1)
-    RA[1] = np.zeros((N, Bn, T[0]))
+    RA = [None] * (L + 1)      # R{A^(1)} = 0: the input does not depend on omega
     for l in range(2, L + 1):
         # R{Z^(l)}[n, b, :] for every example n and direction b
-        RZ[l] = (RA[l - 1] @ model.W[l - 2].T
-                 + np.einsum("bij,nj->nbi", VW[l], A[l - 1])
+        RZ[l] = (np.einsum("bij,nj->nbi", VW[l], A[l - 1], optimize=True)
                  + Vb[l][None, :, :])
+        if RA[l - 1] is not None:
+            RZ[l] = RZ[l] + RA[l - 1] @ model.W[l - 2].T
         if l < L:
             RA[l] = sigma_d1(model.acts[l - 2], Z[l])[:, None, :] * RZ[l]
     yhat = A[L][:, None, :]
@@ -288,12 +288,14 @@ def hvp(model: Model, X, Y, V):
         RD[l] = (sigma_d2(act, Z[l])[:, None, :] * RZ[l] * E[l][:, None, :]
                  + sigma_d1(act, Z[l])[:, None, :]
                  * (RD[l + 1] @ model.W[l - 1]
-                    + np.einsum("bij,ni->nbj", VW[l + 1], delta[l + 1])))
+                    + np.einsum("bij,ni->nbj", VW[l + 1], delta[l + 1], optimize=True)))
     out = np.empty((Bn, P))
     for k, (ow, ob) in enumerate(layer_offsets(T)):
         l = k + 2
-        gW = (np.einsum("nbi,nj->bij", RD[l], A[l - 1])
-              + np.einsum("ni,nbj->bij", delta[l], RA[l - 1])) / N
+        gW = np.einsum("nbi,nj->bij", RD[l], A[l - 1], optimize=True)
+        if RA[l - 1] is not None:
+            gW = gW + np.einsum("ni,nbj->bij", delta[l], RA[l - 1], optimize=True)
+        gW = gW / N
         out[:, ow:ob] = gW.reshape(Bn, -1)
         out[:, ob:ob + T[l - 1]] = np.sum(RD[l], axis=0) / N
     return out

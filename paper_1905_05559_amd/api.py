@@ -1,0 +1,254 @@
+"""Python binding of the C ABI (include/hess.h) over torch device tensors.
+
+Only argument marshalling happens here: every step of the computation runs in
+the HIP kernels of libhess.so.  torch provides device memory and the stream.
+The function names follow the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+class HessError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (L.STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+        self.name = L.STATUS_NAMES.get(status, str(status))
+
+
+def _dtype_code(t: torch.dtype) -> int:
+    if t == torch.float64:
+        return 0
+    if t == torch.float32:
+        return 1
+    raise TypeError("only float32 / float64 arrays are accepted, got %s" % t)
+
+
+class Context:
+    """A library context bound to one device and one stream, plus a grow-only workspace."""
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        self.lib = L.load()
+        self.device = int(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        st = self.lib.hess_create(C.byref(h), self.device, C.c_void_p(self.stream.cuda_stream))
+        if st != L.HESS_OK:
+            raise HessError(st, "hess_create failed")
+        self.h = h
+        self._ws: Optional[torch.Tensor] = None
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8,
+                                   device="cuda:%d" % self.device)
+        return self._ws
+
+    def release_workspace(self):
+        self._ws = None
+
+    def set_option(self, name: str, value: int):
+        self._check(self.lib.hess_set_option(self.h, L.OPT[name], int(value)))
+
+    def last_error(self) -> str:
+        return self.lib.hess_last_error(self.h).decode()
+
+    def _check(self, st: int):
+        if st != L.HESS_OK:
+            raise HessError(st, self.last_error())
+
+    def close(self):
+        if self.h:
+            self.lib.hess_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_DEFAULT = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _DEFAULT:
+        _DEFAULT[device] = Context(device)
+    return _DEFAULT[device]
+
+
+class MLP:
+    """Weights W^(l-1) (T_l x T_{l-1}) and biases b^(l) as device tensors (Sec. 2)."""
+
+    def __init__(self, T: Sequence[int], acts: Sequence[str], W: List[torch.Tensor], b: List[torch.Tensor]):
+        self.T = [int(t) for t in T]
+        self.acts = list(acts)
+        self.W = [w.contiguous() for w in W]
+        self.b = [v.contiguous() for v in b]
+        assert len(self.acts) == len(self.T) - 2
+        assert len(self.W) == len(self.T) - 1 and len(self.b) == len(self.T) - 1
+        self.dtype = self.W[0].dtype
+        for k in range(len(self.T) - 1):
+            assert tuple(self.W[k].shape) == (self.T[k + 1], self.T[k])
+            assert tuple(self.b[k].shape) == (self.T[k + 1],)
+            assert self.W[k].dtype == self.dtype and self.b[k].dtype == self.dtype
+
+    @property
+    def P(self) -> int:
+        return sum(self.T[k + 1] * self.T[k] + self.T[k + 1] for k in range(len(self.T) - 1))
+
+    @classmethod
+    def from_workload(cls, w, device="cuda:0", dtype: Optional[torch.dtype] = None):
+        cv = lambda a: torch.from_numpy(a).to(device=device, dtype=dtype) if dtype else torch.from_numpy(a).to(device)
+        return cls(w.T, w.acts, [cv(x) for x in w.W], [cv(x) for x in w.b])
+
+    def struct(self):
+        n = len(self.T)
+        T = (C.c_int64 * n)(*self.T)
+        act = (C.c_int32 * max(1, n - 2))(*[L.ACT[a] for a in self.acts])
+        Wp = (C.c_void_p * (n - 1))(*[w.data_ptr() for w in self.W])
+        bp = (C.c_void_p * (n - 1))(*[v.data_ptr() for v in self.b])
+        s = L.HessMlp(n, T, act, _dtype_code(self.dtype), Wp, bp)
+        s._keep = (T, act, Wp, bp)
+        return s
+
+
+def _data(X: torch.Tensor, Y: torch.Tensor) -> L.HessData:
+    X = X.contiguous()
+    Y = Y.contiguous()
+    assert X.dtype == Y.dtype and X.shape[0] == Y.shape[0]
+    d = L.HessData(int(X.shape[0]), _dtype_code(X.dtype), X.data_ptr(), Y.data_ptr())
+    d._keep = (X, Y)
+    return d
+
+
+def _out_dtype(prec: str) -> torch.dtype:
+    return torch.float64 if prec == "f64" else torch.float32
+
+
+def workspace_size(op: str, model: MLP, X=None, Y=None, prec: str = "f32", arg: int = 0, opts=None,
+                   ctx: Optional[Context] = None) -> int:
+    ctx = ctx or default_context()
+    m = model.struct() if model is not None else None
+    d = _data(X, Y) if X is not None else None
+    nb = C.c_size_t()
+    ctx._check(ctx.lib.hess_workspace_size(ctx.h, L.OP[op], C.byref(m) if m else None,
+                                           C.byref(d) if d else None, L.PREC[prec], int(arg),
+                                           C.byref(opts) if opts is not None else None, C.byref(nb)))
+    return nb.value
+
+
+def hess_opg(model: MLP, X: torch.Tensor, Y: torch.Tensor, prec: str = "f32",
+             out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """OPG = J^T J / N (P x P), see hess_opg in include/hess.h."""
+    ctx = ctx or default_context()
+    P = model.P
+    if out is None:
+        out = torch.empty((P, P), dtype=_out_dtype(prec), device=X.device)
+    m, d = model.struct(), _data(X, Y)
+    nb = workspace_size("opg", model, X, Y, prec, ctx=ctx)
+    ws = ctx.workspace(nb)
+    ctx._check(ctx.lib.hess_opg(ctx.h, C.byref(m), C.byref(d), L.PREC[prec], out.data_ptr(),
+                                ws.data_ptr(), ws.numel()))
+    return out
+
+
+def hess_exact(model: MLP, X: torch.Tensor, Y: torch.Tensor, prec: str = "f32",
+               out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """Exact Hessian H (P x P), see hess_exact in include/hess.h."""
+    ctx = ctx or default_context()
+    P = model.P
+    if out is None:
+        out = torch.empty((P, P), dtype=_out_dtype(prec), device=X.device)
+    m, d = model.struct(), _data(X, Y)
+    nb = workspace_size("exact", model, X, Y, prec, ctx=ctx)
+    ws = ctx.workspace(nb)
+    ctx._check(ctx.lib.hess_exact(ctx.h, C.byref(m), C.byref(d), L.PREC[prec], out.data_ptr(),
+                                  ws.data_ptr(), ws.numel()))
+    return out
+
+
+def hess_hvp(model: MLP, X: torch.Tensor, Y: torch.Tensor, V: torch.Tensor, prec: str = "f32",
+             out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """H V for the rows of V (B x P), see hess_hvp in include/hess.h."""
+    ctx = ctx or default_context()
+    V = V.contiguous()
+    B = int(V.shape[0])
+    if out is None:
+        out = torch.empty_like(V)
+    m, d = model.struct(), _data(X, Y)
+    nb = workspace_size("hvp", model, X, Y, prec, arg=B, ctx=ctx)
+    ws = ctx.workspace(nb)
+    ctx._check(ctx.lib.hess_hvp(ctx.h, C.byref(m), C.byref(d), L.PREC[prec], B, V.data_ptr(),
+                                out.data_ptr(), ws.data_ptr(), ws.numel()))
+    return out
+
+
+def eig_opts(which: str = "H", source: str = "matrix_free", M: Optional[torch.Tensor] = None,
+             prec: str = "f32", oversample: int = 10, max_iter: int = 200, tol: float = 1e-5,
+             seed: int = 0) -> L.HessEigOpts:
+    o = L.HessEigOpts()
+    o.which = 0 if which == "H" else 1
+    o.source = 0 if source == "matrix_free" else 1
+    o.M = M.data_ptr() if M is not None else None
+    o.M_dtype = _dtype_code(M.dtype) if M is not None else 0
+    o.prec = L.PREC[prec]
+    o.P = int(M.shape[0]) if M is not None else 0
+    o.oversample = int(oversample)
+    o.max_iter = int(max_iter)
+    o.tol = float(tol)
+    o.seed = int(seed)
+    o._keep = M
+    return o
+
+
+def hess_topk_eig(model: Optional[MLP], X: Optional[torch.Tensor], Y: Optional[torch.Tensor], K: int,
+                  opts: L.HessEigOpts, ctx: Optional[Context] = None, device: str = "cuda:0",
+                  raise_on_noconv: bool = True):
+    """K algebraically largest eigenpairs: returns (lambda (K,), Q (K x P), info dict, status name)."""
+    ctx = ctx or default_context()
+    P = model.P if model is not None else int(opts.P)
+    lam = torch.empty(K, dtype=torch.float64, device=device)
+    Q = torch.empty((K, P), dtype=torch.float64, device=device)
+    m = model.struct() if model is not None else None
+    d = _data(X, Y) if X is not None else None
+    nb = C.c_size_t()
+    ctx._check(ctx.lib.hess_workspace_size(ctx.h, L.OP["topk"], C.byref(m) if m else None,
+                                           C.byref(d) if d else None, opts.prec, int(K), C.byref(opts),
+                                           C.byref(nb)))
+    ws = ctx.workspace(nb.value)
+    info = L.HessEigInfo()
+    st = ctx.lib.hess_topk_eig(ctx.h, C.byref(m) if m else None, C.byref(d) if d else None, int(K),
+                               C.byref(opts), lam.data_ptr(), Q.data_ptr(), C.byref(info), ws.data_ptr(),
+                               ws.numel())
+    if st != L.HESS_OK and not (st == 8 and not raise_on_noconv):
+        raise HessError(st, ctx.last_error())
+    inf = {"iters": info.iters, "applies": info.applies, "max_rel_residual": info.max_rel_residual,
+           "shift_used": info.shift_used}
+    return lam, Q, inf, L.STATUS_NAMES[st]
+
+
+def hess_predvar(model: MLP, lam: torch.Tensor, Q: torch.Tensor, delta: float, Xq: torch.Tensor,
+                 cls: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """Damped curvature query s_q for the rows of Xq, see hess_predvar in include/hess.h."""
+    ctx = ctx or default_context()
+    Xq = Xq.contiguous()
+    nq = int(Xq.shape[0])
+    K = int(lam.shape[0])
+    s = torch.empty(nq, dtype=torch.float64, device=Xq.device)
+    m = model.struct()
+    nb = C.c_size_t()
+    ctx._check(ctx.lib.hess_workspace_size(ctx.h, L.OP["predvar"], C.byref(m), None, 0, nq, None,
+                                           C.byref(nb)))
+    ws = ctx.workspace(nb.value)
+    ctx._check(ctx.lib.hess_predvar(ctx.h, C.byref(m), K, lam.data_ptr(), Q.data_ptr(), float(delta), nq,
+                                    Xq.data_ptr(), cls.data_ptr() if cls is not None else None,
+                                    s.data_ptr(), ws.data_ptr(), ws.numel()))
+    return s

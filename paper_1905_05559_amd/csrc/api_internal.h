@@ -1,0 +1,54 @@
+// Host-side helpers shared by the C-ABI translation units.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace hs {
+
+// Validated host view of a hess_mlp.
+struct Model {
+  int L = 0;
+  int dtype = 0;
+  std::vector<int64_t> T;
+  std::vector<int> act;
+  std::vector<const void*> W, b;
+  std::vector<int64_t> offW, offb;  // flat offsets of W^(k+1) and b^(k+2)
+  int64_t P = 0;
+};
+
+// FP64 per-example arrays.  Indexed by layer l (1-based); unused entries null.
+struct Prep {
+  int64_t N = 0;
+  std::vector<double*> Abar;   // l = 1..L-1: N x lda[l], column T_l holds 1 (bias)
+  std::vector<int64_t> lda;
+  std::vector<double*> D1, D2, E;  // hidden l: N x T_l (sigma', sigma'', delta^(l+1) W^(l))
+  std::vector<double*> delta;  // l = 2..L: N x T_l
+  std::vector<double*> D1T, CT;  // hidden l: T_l x N (sigma', sigma'' * E), transposed
+  std::vector<double*> W64, Wbar;  // k = 0..L-2: W^(k+1) (T x T) and [W | b]
+  double* Yhat = nullptr;      // N x T_L
+  double* PT = nullptr;        // T_L x N
+  double* Z = nullptr;         // N x max T scratch
+  int* flags = nullptr;
+};
+
+int64_t rup(int64_t x, int64_t m);
+hess_status fail(hess_ctx* ctx, hess_status s, const std::string& msg);
+hess_status validate_mlp(hess_ctx* ctx, const hess_mlp* m, Model& out, bool need_ptrs);
+hess_status validate_data(hess_ctx* ctx, const hess_data* d, bool need_ptrs);
+void plan_prep(Arena& ar, const Model& m, int64_t N, Prep& p, bool want_transposes);
+hess_status check_inputs(Exec& ex, const Model& m, const hess_data* d, Prep& p);
+void run_prep(Exec& ex, const Model& m, const hess_data* d, Prep& p, bool want_transposes);
+hess_status finish(Exec& ex, const char* what);
+hess_status begin(hess_ctx* ctx, Exec& ex);
+hess_status check_ws(hess_ctx* ctx, size_t need, void* ws, size_t ws_bytes, size_t out_bytes);
+
+// Workspace queries of the other translation units.
+hess_status hvp_workspace(hess_ctx* ctx, const Model& m, int64_t N, int prec, int64_t B, size_t* bytes);
+hess_status topk_workspace(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int64_t K,
+                           const hess_eig_opts* o, size_t* bytes);
+hess_status predvar_workspace(hess_ctx* ctx, const Model& m, int prec, int64_t nq, size_t* bytes);
+
+}  // namespace hs

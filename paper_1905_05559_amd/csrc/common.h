@@ -1,0 +1,161 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <string>
+
+#include "hess.h"
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+namespace hs {
+
+// ---------------------------------------------------------------------------
+// Workspace arena: a bump allocator over the caller's buffer.  With base ==
+// nullptr it only counts, which is how hess_workspace_size is answered with the
+// same planning code that later carves the real buffer.
+// ---------------------------------------------------------------------------
+struct Arena {
+  char* base;
+  size_t used = 0;
+  explicit Arena(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    used = (used + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += count * sizeof(T);
+    return p;
+  }
+};
+
+// Launch bookkeeping for one API call.
+struct Exec {
+  hipStream_t stream;
+  hess_ctx* ctx;
+};
+
+bool launch_ok(Exec& ex);   // fault-injection hook + hipGetLastError check
+
+// ---------------------------------------------------------------------------
+// Generic strided GEMM on MFMA:  C(m,n) = alpha * sum_k A(m,k) B(k,n) + beta * C(m,n)
+// A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn], C(m,n) = C[m*scm + n*scn],
+// optional batch over blockIdx.z with element strides sab, sbb, scb.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct GemmArgs {
+  int64_t M, N, K;
+  const T* A; int64_t sam, sak, sab;
+  const T* B; int64_t sbk, sbn, sbb;
+  T* C; int64_t scm, scn, scb;
+  T alpha, beta;
+  int64_t batch;
+};
+template <typename T>
+void gemm(Exec& ex, const GemmArgs<T>& g);
+
+// Convenience: row-major C[M x N] = alpha * op(A) op(B) + beta C with leading dims.
+template <typename T>
+void gemm_rm(Exec& ex, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha,
+             const T* A, int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc);
+
+// ---------------------------------------------------------------------------
+// Khatri-Rao Gram contraction (the H and OPG tiles).
+//
+// Compute space: a row index r = ur * r.pad + sr names unit ur and slot sr of the
+// row side (likewise for columns).  For every valid (r, c):
+//   acc(r,c) = sum_n w_n(ur,uc) * Rsrc[n, sr] * Csrc[n, sc]
+// where w_n(ur,uc) is
+//   RANK1:     rscale[n, ur] * cscale[n, uc]  (either factor may be absent = 1)
+//   PAIR_FULL: wts[(ur * c.n_units + uc) * ldw + n]
+//   PAIR_DIAG: wts[ur * ldw + n] if ur == uc, else 0
+// and the result scale * acc is stored to out[flat_r * ldo + flat_c] (and mirrored
+// to out[flat_c * ldo + flat_r]).  flat(u, s) is the flat parameter index of
+// (unit i, input j) in a layer with Tout units and Tin inputs: with perm = 0,
+// (i, j) = (u, s), with perm = 1, (i, j) = (s, u); j == Tin denotes the bias.
+// ---------------------------------------------------------------------------
+enum { KRG_RANK1 = 0, KRG_PAIR_FULL = 1, KRG_PAIR_DIAG = 2 };
+
+template <typename T>
+struct KrgSide {
+  const T* src; int64_t ld;       // N x ld source rows
+  int32_t n_units, len, pad;      // units, valid slots per unit, padded slots per unit
+  const T* scale; int64_t ld_scale;  // RANK1 per-(n, unit) factor or nullptr
+  int32_t perm; int64_t off; int32_t Tin, Tout;  // output index map
+};
+
+template <typename T, typename TOut>
+struct KrgArgs {
+  KrgSide<T> r, c;
+  int32_t wmode;
+  const T* wts; int64_t ldw;
+  TOut* out; int64_t ldo;
+  int32_t symmetric, accumulate, mirror;
+  double scale;
+  int64_t N;
+};
+template <typename T, typename TOut>
+void krg(Exec& ex, const KrgArgs<T, TOut>& a);
+// BF16 variant (RANK1 only): operands rounded to bf16 after scaling, fp32 accumulate.
+void krg_bf16(Exec& ex, const KrgArgs<float, float>& a);
+
+// ---------------------------------------------------------------------------
+// Element-wise and small kernels (k_elem.hip).
+// ---------------------------------------------------------------------------
+void check_finite(Exec& ex, const void* p, int dtype, int64_t n, int* flag);
+void check_onehot(Exec& ex, const void* Y, int dtype, int64_t N, int64_t C, int* flag);
+void check_cls(Exec& ex, const int32_t* cls, int64_t n, int64_t C, int* flag);
+// dst[n*ldd + j] = (double) src[n*lds + j] for j < cols; optional bias column of ones at j == cols
+void to_f64_rows(Exec& ex, const void* src, int dtype, int64_t rows, int64_t cols, int64_t lds,
+                 double* dst, int64_t ldd, int bias_one);
+// Wbar = [W | b] (Tout x (Tin+1)) in FP64
+void make_wbar(Exec& ex, const void* W, const void* b, int dtype, int64_t Tout, int64_t Tin,
+               double* Wbar);
+// hidden activation: from Z (N x T) write Abar (N x ldab, bias column = 1), D1, D2 (N x T)
+void activate(Exec& ex, int act, const double* Z, int64_t N, int64_t T, double* Abar,
+              int64_t ldab, double* D1, double* D2);
+// softmax rows (one wavefront per row): Yhat = softmax(Z)
+void softmax_rows(Exec& ex, const double* Z, int64_t N, int64_t T, double* Yhat);
+// delta^(L) = Yhat - Y
+void output_delta(Exec& ex, const double* Yhat, const void* Y, int dtype, int64_t N, int64_t T,
+                  double* delta);
+// c[i] = a[i] * b[i]
+void mul(Exec& ex, const double* a, const double* b, double* c, int64_t n);
+// dst (cols x rows) = transpose of src (rows x cols, leading dim lds), optional elementwise product with src2
+void transpose(Exec& ex, const double* src, int64_t rows, int64_t cols, int64_t lds, double* dst,
+               int64_t ldd);
+template <typename TD>
+void cast_copy(Exec& ex, const double* src, TD* dst, int64_t n);
+// strided 2D cast: dst[r*ldd + c] = (TD) src[r*lds + c]
+template <typename TD>
+void cast_2d(Exec& ex, const double* src, int64_t rows, int64_t cols, int64_t lds, TD* dst, int64_t ldd);
+// Curvature-factor helpers on the [T_a][T_m][N] layout (n fastest)
+// F[i2][i][n] = W[i2*ldw + i] * D1T[i][n]
+void factor_first(Exec& ex, const double* W, int64_t T2, int64_t Tm, const double* D1T, int64_t N,
+                  double* F);
+// K[k][i][n] = D1T[k][n] * F[k][i][n]
+void factor_rowscale(Exec& ex, const double* F, int64_t Tk, int64_t Tm, const double* D1T, int64_t N,
+                     double* K);
+// G[k][i][n] = p[k][n] * (F[k][i][n] - sum_k' p[k'][n] F[k'][i][n]); F == nullptr means identity
+void factor_softmax(Exec& ex, const double* F, int64_t TL, int64_t Tm, const double* PT, int64_t N,
+                    double* G);
+// G[k][i][n] = D1T[k][n] * G[k][i][n] + CT[k][n] * (F ? F[k][i][n] : (k == i))
+void factor_combine(Exec& ex, double* G, int64_t Tk, int64_t Tm, const double* D1T,
+                    const double* CT, const double* F, int64_t N);
+
+}  // namespace hs
+
+struct hess_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  int check_inputs = 1;
+  int64_t hbm_budget = 0;
+  int64_t fault_after = -1;
+  int64_t launches = 0;
+  bool fault_hit = false;
+};

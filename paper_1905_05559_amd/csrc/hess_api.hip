@@ -1,0 +1,649 @@
+// C-ABI layer: argument validation, workspace planning and the orchestration of
+// the per-example passes (forward, backprop, curvature factors) and the P x P
+// contractions.  Every array the kernels touch is either a caller buffer or a
+// slice of the caller's workspace.
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "api_internal.h"
+
+namespace hs {
+
+bool launch_ok(Exec& ex) {
+  hess_ctx* c = ex.ctx;
+  c->launches++;
+  if (c->fault_after >= 0 && c->launches > c->fault_after) {
+    c->fault_hit = true;
+    return false;
+  }
+  return true;
+}
+
+int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+hess_status fail(hess_ctx* ctx, hess_status s, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return s;
+}
+
+hess_status validate_mlp(hess_ctx* ctx, const hess_mlp* m, Model& out, bool need_ptrs) {
+  if (!m) return fail(ctx, HESS_E_ARG, "model is NULL");
+  if (m->L < 2) return fail(ctx, HESS_E_SHAPE, "L must be >= 2");
+  if (m->L > 64) return fail(ctx, HESS_E_SHAPE, "L must be <= 64");
+  if (!m->T) return fail(ctx, HESS_E_ARG, "T is NULL");
+  if (m->L > 2 && !m->act) return fail(ctx, HESS_E_ARG, "act is NULL");
+  if (m->dtype != HESS_F64 && m->dtype != HESS_F32) return fail(ctx, HESS_E_ARG, "bad model dtype");
+  out.L = m->L;
+  out.dtype = m->dtype;
+  out.T.assign(m->T, m->T + m->L);
+  out.act.clear();
+  for (int k = 0; k < m->L - 2; ++k) {
+    if (m->act[k] < HESS_TANH || m->act[k] > HESS_RELU) return fail(ctx, HESS_E_ARG, "bad activation");
+    out.act.push_back(m->act[k]);
+  }
+  for (int k = 0; k < m->L; ++k)
+    if (out.T[k] < 1 || out.T[k] > (int64_t)1 << 24) return fail(ctx, HESS_E_SHAPE, "width out of range");
+  out.offW.assign(m->L - 1, 0);
+  out.offb.assign(m->L - 1, 0);
+  long double P = 0;
+  int64_t o = 0;
+  for (int k = 0; k < m->L - 1; ++k) {
+    out.offW[k] = o;
+    out.offb[k] = o + out.T[k + 1] * out.T[k];
+    o += out.T[k + 1] * out.T[k] + out.T[k + 1];
+    P += (long double)out.T[k + 1] * out.T[k] + out.T[k + 1];
+  }
+  if (P > (long double)((int64_t)1 << 31)) return fail(ctx, HESS_E_SHAPE, "P overflows");
+  out.P = o;
+  out.W.clear();
+  out.b.clear();
+  if (need_ptrs) {
+    if (!m->W || !m->b) return fail(ctx, HESS_E_ARG, "W or b array is NULL");
+    for (int k = 0; k < m->L - 1; ++k) {
+      if (!m->W[k] || !m->b[k]) return fail(ctx, HESS_E_ARG, "a W or b pointer is NULL");
+      out.W.push_back(m->W[k]);
+      out.b.push_back(m->b[k]);
+    }
+  }
+  return HESS_OK;
+}
+
+hess_status validate_data(hess_ctx* ctx, const hess_data* d, bool need_ptrs) {
+  if (!d) return fail(ctx, HESS_E_ARG, "data is NULL");
+  if (d->N < 1 || d->N > ((int64_t)1 << 31)) return fail(ctx, HESS_E_SHAPE, "N out of range");
+  if (d->dtype != HESS_F64 && d->dtype != HESS_F32) return fail(ctx, HESS_E_ARG, "bad data dtype");
+  if (need_ptrs && (!d->X || !d->Y)) return fail(ctx, HESS_E_ARG, "X or Y is NULL");
+  return HESS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Per-example passes in FP64 (forward, backprop) and their transposed copies.
+// ---------------------------------------------------------------------------
+void plan_prep(Arena& ar, const Model& m, int64_t N, Prep& p, bool want_transposes) {
+  const int L = m.L;
+  p.N = N;
+  p.Abar.assign(L + 1, nullptr);
+  p.lda.assign(L + 1, 0);
+  p.D1.assign(L + 1, nullptr);
+  p.D2.assign(L + 1, nullptr);
+  p.E.assign(L + 1, nullptr);
+  p.delta.assign(L + 1, nullptr);
+  p.D1T.assign(L + 1, nullptr);
+  p.CT.assign(L + 1, nullptr);
+  p.W64.assign(L - 1, nullptr);
+  p.Wbar.assign(L - 1, nullptr);
+  int64_t tmax = 0;
+  for (int l = 1; l <= L; ++l) tmax = std::max(tmax, m.T[l - 1]);
+  for (int l = 1; l <= L - 1; ++l) {
+    p.lda[l] = rup(m.T[l - 1] + 1, 4);
+    p.Abar[l] = ar.take<double>(N * p.lda[l]);
+  }
+  for (int l = 2; l <= L - 1; ++l) {
+    p.D1[l] = ar.take<double>(N * m.T[l - 1]);
+    p.D2[l] = ar.take<double>(N * m.T[l - 1]);
+    p.E[l] = ar.take<double>(N * m.T[l - 1]);
+  }
+  for (int l = 2; l <= L; ++l) p.delta[l] = ar.take<double>(N * m.T[l - 1]);
+  p.Yhat = ar.take<double>(N * m.T[L - 1]);
+  p.Z = ar.take<double>(N * tmax);
+  for (int k = 0; k < L - 1; ++k) {
+    p.W64[k] = ar.take<double>(m.T[k + 1] * m.T[k]);
+    p.Wbar[k] = ar.take<double>(m.T[k + 1] * (m.T[k] + 1));
+  }
+  p.flags = ar.take<int>(8);
+  if (want_transposes) {
+    for (int l = 2; l <= L - 1; ++l) {
+      p.D1T[l] = ar.take<double>(N * m.T[l - 1]);
+      p.CT[l] = ar.take<double>(N * m.T[l - 1]);
+    }
+    p.PT = ar.take<double>(N * m.T[L - 1]);
+  }
+}
+
+// Device-side input checks; reads back one flag word.  Returns HESS_OK or an error.
+hess_status check_inputs(Exec& ex, const Model& m, const hess_data* d, Prep& p) {
+  hess_ctx* ctx = ex.ctx;
+  if (!ctx->check_inputs) return HESS_OK;
+  hipMemsetAsync(p.flags, 0, 8 * sizeof(int), ex.stream);
+  for (int k = 0; k < m.L - 1; ++k) {
+    check_finite(ex, m.W[k], m.dtype, m.T[k + 1] * m.T[k], p.flags + 0);
+    check_finite(ex, m.b[k], m.dtype, m.T[k + 1], p.flags + 0);
+  }
+  if (d) {
+    check_finite(ex, d->X, d->dtype, d->N * m.T[0], p.flags + 0);
+    check_onehot(ex, d->Y, d->dtype, d->N, m.T[m.L - 1], p.flags + 1);
+  }
+  int h[8] = {0};
+  hipMemcpyAsync(h, p.flags, 8 * sizeof(int), hipMemcpyDeviceToHost, ex.stream);
+  if (hipStreamSynchronize(ex.stream) != hipSuccess)
+    return fail(ctx, HESS_E_DEVICE, std::string("input check: ") + hipGetErrorString(hipGetLastError()));
+  if (ctx->fault_hit) return fail(ctx, HESS_E_DEVICE, "injected device fault");
+  if (h[0]) return fail(ctx, HESS_E_NONFINITE, "non-finite value in W, b or X");
+  if (h[1]) return fail(ctx, HESS_E_LABEL, "a row of Y is not exactly one-hot");
+  return HESS_OK;
+}
+
+// Forward pass (Sec. 2 model function) and per-example backprop.
+void run_prep(Exec& ex, const Model& m, const hess_data* d, Prep& p, bool want_transposes) {
+  const int L = m.L;
+  const int64_t N = p.N;
+  const int64_t T1 = m.T[0];
+  to_f64_rows(ex, d->X, d->dtype, N, T1, T1, p.Abar[1], p.lda[1], 1);
+  for (int k = 0; k < L - 1; ++k) {
+    to_f64_rows(ex, m.W[k], m.dtype, m.T[k + 1], m.T[k], m.T[k], p.W64[k], m.T[k], 0);
+    make_wbar(ex, m.W[k], m.b[k], m.dtype, m.T[k + 1], m.T[k], p.Wbar[k]);
+  }
+  for (int l = 2; l <= L; ++l) {
+    const int64_t Tin = m.T[l - 2], Tl = m.T[l - 1];
+    // Z^(l) = Abar^(l-1) Wbar^(l-1)^T  (bias folded in through the ones column)
+    gemm_rm<double>(ex, false, true, N, Tl, Tin + 1, 1.0, p.Abar[l - 1], p.lda[l - 1], p.Wbar[l - 2],
+                    Tin + 1, 0.0, p.Z, Tl);
+    if (l < L)
+      activate(ex, m.act[l - 2], p.Z, N, Tl, p.Abar[l], p.lda[l], p.D1[l], p.D2[l]);
+    else
+      softmax_rows(ex, p.Z, N, Tl, p.Yhat);
+  }
+  output_delta(ex, p.Yhat, d->Y, d->dtype, N, m.T[L - 1], p.delta[L]);
+  for (int l = L - 1; l >= 2; --l) {
+    // E^(l) = delta^(l+1) W^(l);  delta^(l) = sigma'(Z^(l)) * E^(l)
+    gemm_rm<double>(ex, false, false, N, m.T[l - 1], m.T[l], 1.0, p.delta[l + 1], m.T[l], p.W64[l - 1],
+                    m.T[l - 1], 0.0, p.E[l], m.T[l - 1]);
+    mul(ex, p.D1[l], p.E[l], p.delta[l], N * m.T[l - 1]);
+  }
+  if (want_transposes) {
+    for (int l = 2; l <= L - 1; ++l) {
+      const int64_t Tl = m.T[l - 1];
+      transpose(ex, p.D1[l], N, Tl, Tl, p.D1T[l], N);
+      // C^(l) = sigma''(Z^(l)) * E^(l), stored transposed
+      mul(ex, p.D2[l], p.E[l], p.Z, N * Tl);
+      transpose(ex, p.Z, N, Tl, Tl, p.CT[l], N);
+    }
+    transpose(ex, p.Yhat, N, m.T[L - 1], m.T[L - 1], p.PT, N);
+  }
+}
+
+hess_status finish(Exec& ex, const char* what) {
+  hess_ctx* ctx = ex.ctx;
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(ex.stream);
+  if (ctx->fault_hit) return fail(ctx, HESS_E_DEVICE, std::string(what) + ": injected device fault");
+  if (e1 != hipSuccess || e2 != hipSuccess)
+    return fail(ctx, HESS_E_DEVICE, std::string(what) + ": " +
+                                        hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  ctx->last_error.clear();
+  return HESS_OK;
+}
+
+hess_status begin(hess_ctx* ctx, Exec& ex) {
+  if (!ctx) return HESS_E_ARG;
+  ex.ctx = ctx;
+  ex.stream = ctx->stream;
+  ctx->fault_hit = false;
+  ctx->last_error.clear();
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, HESS_E_DEVICE, "hipSetDevice failed");
+  (void)hipGetLastError();
+  return HESS_OK;
+}
+
+hess_status check_ws(hess_ctx* ctx, size_t need, void* ws, size_t ws_bytes, size_t out_bytes) {
+  if (ctx->hbm_budget > 0 && (int64_t)(need + out_bytes) > ctx->hbm_budget)
+    return fail(ctx, HESS_E_BUDGET, "footprint " + std::to_string(need + out_bytes) +
+                                        " B exceeds the HBM budget " + std::to_string(ctx->hbm_budget) + " B");
+  if (need > 0 && (!ws || ws_bytes < need))
+    return fail(ctx, HESS_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " B");
+  return HESS_OK;
+}
+
+// Row/column side of the Khatri-Rao contraction for one layer l (params W^(l-1), b^(l)).
+template <typename T>
+KrgSide<T> side_layer(const Model& m, int l, const T* abar, int64_t lda, const T* scale, int64_t ld_scale) {
+  KrgSide<T> s;
+  s.src = abar;
+  s.ld = lda;
+  s.n_units = (int32_t)m.T[l - 1];
+  s.len = (int32_t)(m.T[l - 2] + 1);
+  s.pad = (int32_t)rup(s.len, 16);
+  s.scale = scale;
+  s.ld_scale = ld_scale;
+  s.perm = 0;
+  s.off = m.offW[l - 2];
+  s.Tin = (int32_t)m.T[l - 2];
+  s.Tout = (int32_t)m.T[l - 1];
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// OPG.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct OpgBufs {
+  std::vector<T*> abar, delta;
+};
+
+template <typename T>
+void plan_opg_ops(Arena& ar, const Model& m, int64_t N, const Prep& p, OpgBufs<T>& b) {
+  const int L = m.L;
+  b.abar.assign(L + 1, nullptr);
+  b.delta.assign(L + 1, nullptr);
+  for (int l = 1; l <= L - 1; ++l) b.abar[l] = ar.take<T>(N * p.lda[l]);
+  for (int l = 2; l <= L; ++l) b.delta[l] = ar.take<T>(N * m.T[l - 1]);
+}
+
+template <typename T>
+void cast_ops(Exec& ex, const Model& m, const Prep& p, OpgBufs<T>& b) {
+  for (int l = 1; l <= m.L - 1; ++l) cast_copy<T>(ex, p.Abar[l], b.abar[l], p.N * p.lda[l]);
+  for (int l = 2; l <= m.L; ++l) cast_copy<T>(ex, p.delta[l], b.delta[l], p.N * m.T[l - 1]);
+}
+
+template <typename T, typename TOut>
+void run_opg(Exec& ex, const Model& m, int64_t N, const Prep& p, const OpgBufs<T>& b, TOut* G, bool bf16) {
+  const int L = m.L;
+  for (int l = 2; l <= L; ++l)
+    for (int mm = 2; mm <= l; ++mm) {
+      KrgArgs<T, TOut> a;
+      a.r = side_layer<T>(m, l, b.abar[l - 1], p.lda[l - 1], b.delta[l], m.T[l - 1]);
+      a.c = side_layer<T>(m, mm, b.abar[mm - 1], p.lda[mm - 1], b.delta[mm], m.T[mm - 1]);
+      a.wmode = KRG_RANK1;
+      a.wts = nullptr;
+      a.ldw = 0;
+      a.out = G;
+      a.ldo = m.P;
+      a.symmetric = (l == mm);
+      a.accumulate = 0;
+      a.mirror = 1;
+      a.scale = 1.0 / (double)N;
+      a.N = N;
+      if constexpr (std::is_same<T, float>::value && std::is_same<TOut, float>::value) {
+        if (bf16) {
+          krg_bf16(ex, a);
+          continue;
+        }
+      }
+      krg<T, TOut>(ex, a);
+    }
+}
+
+size_t plan_opg(const Model& m, int64_t N, int prec, void* ws, Prep& p, void* ops) {
+  Arena ar(ws);
+  plan_prep(ar, m, N, p, false);
+  if (prec == HESS_P_F64) {
+    // the FP64 prep arrays are the operands
+  } else {
+    plan_opg_ops<float>(ar, m, N, p, *static_cast<OpgBufs<float>*>(ops));
+  }
+  return ar.used;
+}
+
+// ---------------------------------------------------------------------------
+// Exact Hessian: per column layer m, propagate the R-operator of the unit
+// directions e_i of Z^(m) (forward factors F, K; backward factors G) and
+// contract.  For a basis direction in W^(m-1)[i, j] (or b^(m)[i], j = bias) the
+// R-quantities of example n are abar^(m-1)_{n,j} times column i of these factors:
+//   F^(m,m) = I,  F^(l,m) = W^(l-1) D^(l-1) F^(l-1,m)          (R{Z^(l)})
+//   K^(l,m) = D^(l) F^(l,m)                                    (R{A^(l)})
+//   G^(L,m) = S_n F^(L,m),  S_n = diag(p_n) - p_n p_n^T         (R{delta^(L)})
+//   G^(l,m) = diag(sigma''^(l) E^(l)) F^(l,m) + D^(l) W^(l)^T G^(l+1,m)   (R{delta^(l)})
+// so that the Hessian-vector accumulation (Appendix A.1) gives, for l >= m,
+//   H[(l,i',j'),(m,i,j)] = (1/N) sum_n abar^(m-1)_{nj} [ G^(l,m)_n[i',i] abar^(l-1)_{nj'}
+//                                                      + [l > m] delta^(l)_{ni'} K^(l-1,m)_n[j',i] ]
+// (the K term has no bias row).  Blocks with l < m follow by symmetry.
+// ---------------------------------------------------------------------------
+struct HFactors {
+  std::vector<double*> F, K, G;   // indexed by layer, layout [T_a][T_m][N]
+};
+template <typename T>
+struct HOps {
+  OpgBufs<T> base;                // abar and delta in operand precision
+  std::vector<T*> G, K;           // weights in operand precision
+  T* D1T = nullptr;               // sigma'^(m) transposed, operand precision
+};
+
+template <typename T>
+size_t plan_exact(const Model& m, int64_t N, void* ws, Prep& p, HOps<T>& ops, std::vector<HFactors>& fac,
+                  bool same_type) {
+  Arena ar(ws);
+  const int L = m.L;
+  plan_prep(ar, m, N, p, true);
+  if (!same_type) plan_opg_ops<T>(ar, m, N, p, ops.base);
+  // factors are planned per column layer in one reusable region (max over m)
+  const size_t base_used = ar.used;
+  size_t peak = base_used;
+  fac.assign(L + 1, HFactors());
+  std::vector<T*> Gop_dummy;
+  for (int mm = 2; mm <= L; ++mm) {
+    Arena a2(ws);
+    a2.used = base_used;
+    HFactors& f = fac[mm];
+    f.F.assign(L + 1, nullptr);
+    f.K.assign(L + 1, nullptr);
+    f.G.assign(L + 1, nullptr);
+    const int64_t Tm = m.T[mm - 1];
+    for (int l = mm + 1; l <= L; ++l) f.F[l] = a2.take<double>(m.T[l - 1] * Tm * N);
+    for (int l = mm + 1; l <= L - 1; ++l) f.K[l] = a2.take<double>(m.T[l - 1] * Tm * N);
+    for (int l = mm; l <= L; ++l) f.G[l] = a2.take<double>(m.T[l - 1] * Tm * N);
+    if (!same_type) {
+      // operand-precision copies live after the FP64 factors of the same m
+      for (int l = mm; l <= L; ++l) a2.take<T>(m.T[l - 1] * Tm * N);
+      for (int l = mm + 1; l <= L - 1; ++l) a2.take<T>(m.T[l - 1] * Tm * N);
+      a2.take<T>(Tm * N);
+    }
+    peak = std::max(peak, a2.used);
+  }
+  ar.used = peak;
+  return ar.used;
+}
+
+template <typename T, typename TOut>
+void run_exact(Exec& ex, const Model& m, int64_t N, Prep& p, HOps<T>& ops, std::vector<HFactors>& fac,
+               void* ws, size_t base_used_hint, TOut* H, bool same_type) {
+  const int L = m.L;
+  if (!same_type) cast_ops<T>(ex, m, p, ops.base);
+  std::vector<T*> abar(L + 1), delta(L + 1);
+  for (int l = 1; l <= L; ++l) {
+    if (same_type) {
+      abar[l] = (l <= L - 1) ? reinterpret_cast<T*>(p.Abar[l]) : nullptr;
+      delta[l] = (l >= 2) ? reinterpret_cast<T*>(p.delta[l]) : nullptr;
+    } else {
+      abar[l] = (l <= L - 1) ? ops.base.abar[l] : nullptr;
+      delta[l] = (l >= 2) ? ops.base.delta[l] : nullptr;
+    }
+  }
+  for (int mm = 2; mm <= L; ++mm) {
+    HFactors& f = fac[mm];
+    const int64_t Tm = m.T[mm - 1];
+    // forward factors
+    if (mm < L) factor_first(ex, p.W64[mm - 1], m.T[mm], Tm, p.D1T[mm], N, f.F[mm + 1]);
+    for (int l = mm + 2; l <= L; ++l) {
+      factor_rowscale(ex, f.F[l - 1], m.T[l - 2], Tm, p.D1T[l - 1], N, f.K[l - 1]);
+      gemm_rm<double>(ex, false, false, m.T[l - 1], Tm * N, m.T[l - 2], 1.0, p.W64[l - 2], m.T[l - 2],
+                      f.K[l - 1], Tm * N, 0.0, f.F[l], Tm * N);
+    }
+    // backward factors
+    factor_softmax(ex, mm < L ? f.F[L] : nullptr, m.T[L - 1], Tm, p.PT, N, f.G[L]);
+    for (int l = L - 1; l >= mm; --l) {
+      gemm_rm<double>(ex, true, false, m.T[l - 1], Tm * N, m.T[l], 1.0, p.W64[l - 1], m.T[l - 1], f.G[l + 1],
+                      Tm * N, 0.0, f.G[l], Tm * N);
+      factor_combine(ex, f.G[l], m.T[l - 1], Tm, p.D1T[l], p.CT[l], l == mm ? nullptr : f.F[l], N);
+    }
+    // operand-precision weights
+    std::vector<const T*> Gw(L + 1, nullptr), Kw(L + 1, nullptr);
+    const T* D1w = nullptr;
+    if (same_type) {
+      for (int l = mm; l <= L; ++l) Gw[l] = reinterpret_cast<const T*>(f.G[l]);
+      for (int l = mm + 1; l <= L - 1; ++l) Kw[l] = reinterpret_cast<const T*>(f.K[l]);
+      if (mm < L) D1w = reinterpret_cast<const T*>(p.D1T[mm]);
+    } else {
+      // carve the copies right after this m's FP64 factors (mirrors plan_exact)
+      Arena a2(ws);
+      a2.used = base_used_hint;
+      for (int l = mm + 1; l <= L; ++l) a2.take<double>(m.T[l - 1] * Tm * N);
+      for (int l = mm + 1; l <= L - 1; ++l) a2.take<double>(m.T[l - 1] * Tm * N);
+      for (int l = mm; l <= L; ++l) a2.take<double>(m.T[l - 1] * Tm * N);
+      for (int l = mm; l <= L; ++l) {
+        T* g = a2.take<T>(m.T[l - 1] * Tm * N);
+        cast_copy<T>(ex, f.G[l], g, m.T[l - 1] * Tm * N);
+        Gw[l] = g;
+      }
+      for (int l = mm + 1; l <= L - 1; ++l) {
+        T* k = a2.take<T>(m.T[l - 1] * Tm * N);
+        cast_copy<T>(ex, f.K[l], k, m.T[l - 1] * Tm * N);
+        Kw[l] = k;
+      }
+      T* d1 = a2.take<T>(Tm * N);
+      if (mm < L) {
+        cast_copy<T>(ex, p.D1T[mm], d1, Tm * N);
+        D1w = d1;
+      }
+    }
+    // term 1: weighted Gram of abar^(l-1) and abar^(m-1)
+    for (int l = mm; l <= L; ++l) {
+      KrgArgs<T, TOut> a;
+      a.r = side_layer<T>(m, l, abar[l - 1], p.lda[l - 1], nullptr, 0);
+      a.c = side_layer<T>(m, mm, abar[mm - 1], p.lda[mm - 1], nullptr, 0);
+      a.wmode = KRG_PAIR_FULL;
+      a.wts = Gw[l];
+      a.ldw = N;
+      a.out = H;
+      a.ldo = m.P;
+      a.symmetric = (l == mm);
+      a.accumulate = 0;
+      a.mirror = 1;
+      a.scale = 1.0 / (double)N;
+      a.N = N;
+      krg<T, TOut>(ex, a);
+    }
+    // term 2 (l > m): delta^(l)_{i'} abar^(m-1)_j weighted by K^(l-1,m)[j', i]
+    for (int l = mm + 1; l <= L; ++l) {
+      KrgArgs<T, TOut> a;
+      KrgSide<T> r;
+      r.src = delta[l];
+      r.ld = m.T[l - 1];
+      r.n_units = (int32_t)m.T[l - 2];   // units j' (inputs of layer l, no bias)
+      r.len = (int32_t)m.T[l - 1];       // slots i'
+      r.pad = (int32_t)rup(r.len, 16);
+      r.scale = nullptr;
+      r.ld_scale = 0;
+      r.perm = 1;
+      r.off = m.offW[l - 2];
+      r.Tin = (int32_t)m.T[l - 2];
+      r.Tout = (int32_t)m.T[l - 1];
+      a.r = r;
+      a.c = side_layer<T>(m, mm, abar[mm - 1], p.lda[mm - 1], nullptr, 0);
+      if (l - 1 == mm) {
+        a.wmode = KRG_PAIR_DIAG;
+        a.wts = D1w;
+      } else {
+        a.wmode = KRG_PAIR_FULL;
+        a.wts = Kw[l - 1];
+      }
+      a.ldw = N;
+      a.out = H;
+      a.ldo = m.P;
+      a.symmetric = 0;
+      a.accumulate = 1;
+      a.mirror = 1;
+      a.scale = 1.0 / (double)N;
+      a.N = N;
+      krg<T, TOut>(ex, a);
+    }
+  }
+}
+
+}  // namespace hs
+
+using namespace hs;
+
+extern "C" {
+
+hess_status hess_create(hess_ctx** ctx, int device, void* stream) {
+  if (!ctx) return HESS_E_ARG;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return HESS_E_DEVICE;
+  }
+  hess_ctx* c = new hess_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  *ctx = c;
+  return HESS_OK;
+}
+
+hess_status hess_destroy(hess_ctx* ctx) {
+  delete ctx;
+  return HESS_OK;
+}
+
+const char* hess_status_str(hess_status s) {
+  switch (s) {
+    case HESS_OK: return "ok";
+    case HESS_E_ARG: return "invalid argument";
+    case HESS_E_SHAPE: return "invalid shape";
+    case HESS_E_LABEL: return "labels are not one-hot";
+    case HESS_E_NONFINITE: return "non-finite input";
+    case HESS_E_WORKSPACE: return "workspace too small";
+    case HESS_E_BUDGET: return "HBM budget exceeded";
+    case HESS_E_DEVICE: return "device error";
+    case HESS_E_NOCONV: return "eigensolver did not converge";
+    case HESS_E_NOTPD: return "damped matrix is not positive definite";
+    case HESS_E_UNSUPPORTED: return "unsupported precision for this operation";
+  }
+  return "unknown status";
+}
+
+const char* hess_last_error(const hess_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+hess_status hess_set_option(hess_ctx* ctx, int opt, int64_t value) {
+  if (!ctx) return HESS_E_ARG;
+  switch (opt) {
+    case HESS_OPT_CHECK_INPUTS: ctx->check_inputs = value != 0; return HESS_OK;
+    case HESS_OPT_HBM_BUDGET: ctx->hbm_budget = value; return HESS_OK;
+    case HESS_OPT_FAULT_AFTER: ctx->fault_after = value; ctx->launches = 0; return HESS_OK;
+  }
+  return fail(ctx, HESS_E_ARG, "unknown option");
+}
+
+hess_status hess_num_params(const hess_mlp* m, int64_t* P) {
+  if (!P) return HESS_E_ARG;
+  Model mm;
+  hess_status s = validate_mlp(nullptr, m, mm, false);
+  if (s != HESS_OK) return s;
+  *P = mm.P;
+  return HESS_OK;
+}
+
+static size_t ws_opg(const Model& m, int64_t N, int prec) {
+  Prep p;
+  OpgBufs<float> b;
+  return plan_opg(m, N, prec, nullptr, p, &b);
+}
+static size_t ws_exact(const Model& m, int64_t N, int prec) {
+  Prep p;
+  std::vector<HFactors> fac;
+  if (prec == HESS_P_F64) {
+    HOps<double> o;
+    return plan_exact<double>(m, N, nullptr, p, o, fac, true);
+  }
+  HOps<float> o;
+  return plan_exact<float>(m, N, nullptr, p, o, fac, false);
+}
+
+hess_status hess_workspace_size(hess_ctx* ctx, int op, const hess_mlp* mlp, const hess_data* d, int prec,
+                                int64_t arg, const void* opts, size_t* bytes) {
+  if (!bytes) return fail(ctx, HESS_E_ARG, "bytes is NULL");
+  Model m;
+  hess_status s;
+  switch (op) {
+    case HESS_OP_EXACT:
+    case HESS_OP_OPG:
+      if ((s = validate_mlp(ctx, mlp, m, false)) != HESS_OK) return s;
+      if ((s = validate_data(ctx, d, false)) != HESS_OK) return s;
+      *bytes = op == HESS_OP_EXACT ? ws_exact(m, d->N, prec) : ws_opg(m, d->N, prec);
+      return HESS_OK;
+    case HESS_OP_HVP:
+      if ((s = validate_mlp(ctx, mlp, m, false)) != HESS_OK) return s;
+      if ((s = validate_data(ctx, d, false)) != HESS_OK) return s;
+      return hvp_workspace(ctx, m, d->N, prec, arg, bytes);
+    case HESS_OP_TOPK:
+      return topk_workspace(ctx, mlp, d, arg, static_cast<const hess_eig_opts*>(opts), bytes);
+    case HESS_OP_PREDVAR:
+      if ((s = validate_mlp(ctx, mlp, m, false)) != HESS_OK) return s;
+      return predvar_workspace(ctx, m, prec, arg, bytes);
+  }
+  return fail(ctx, HESS_E_ARG, "unknown op");
+}
+
+hess_status hess_opg(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int prec, void* G, void* ws,
+                     size_t ws_bytes) {
+  Exec ex;
+  hess_status s = begin(ctx, ex);
+  if (s != HESS_OK) return s;
+  Model m;
+  if ((s = validate_mlp(ctx, mlp, m, true)) != HESS_OK) return s;
+  if ((s = validate_data(ctx, d, true)) != HESS_OK) return s;
+  if (prec != HESS_P_F64 && prec != HESS_P_F32 && prec != HESS_P_BF16)
+    return fail(ctx, HESS_E_ARG, "bad precision");
+  if (!G) return fail(ctx, HESS_E_ARG, "output is NULL");
+  const size_t need = ws_opg(m, d->N, prec);
+  const size_t out_bytes = (size_t)m.P * m.P * (prec == HESS_P_F64 ? 8 : 4);
+  if ((s = check_ws(ctx, need, ws, ws_bytes, out_bytes)) != HESS_OK) return s;
+  Prep p;
+  OpgBufs<float> b;
+  plan_opg(m, d->N, prec, ws, p, &b);
+  if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
+  run_prep(ex, m, d, p, false);
+  if (prec == HESS_P_F64) {
+    OpgBufs<double> bd;
+    bd.abar = p.Abar;
+    bd.delta = p.delta;
+    run_opg<double, double>(ex, m, d->N, p, bd, static_cast<double*>(G), false);
+  } else {
+    cast_ops<float>(ex, m, p, b);
+    run_opg<float, float>(ex, m, d->N, p, b, static_cast<float*>(G), prec == HESS_P_BF16);
+  }
+  return finish(ex, "hess_opg");
+}
+
+hess_status hess_exact(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int prec, void* H, void* ws,
+                       size_t ws_bytes) {
+  Exec ex;
+  hess_status s = begin(ctx, ex);
+  if (s != HESS_OK) return s;
+  Model m;
+  if ((s = validate_mlp(ctx, mlp, m, true)) != HESS_OK) return s;
+  if ((s = validate_data(ctx, d, true)) != HESS_OK) return s;
+  if (prec == HESS_P_BF16) return fail(ctx, HESS_E_UNSUPPORTED, "BF16 is offered for the OPG only");
+  if (prec != HESS_P_F64 && prec != HESS_P_F32) return fail(ctx, HESS_E_ARG, "bad precision");
+  if (!H) return fail(ctx, HESS_E_ARG, "output is NULL");
+  const size_t need = ws_exact(m, d->N, prec);
+  const size_t out_bytes = (size_t)m.P * m.P * (prec == HESS_P_F64 ? 8 : 4);
+  if ((s = check_ws(ctx, need, ws, ws_bytes, out_bytes)) != HESS_OK) return s;
+  Prep p;
+  std::vector<HFactors> fac;
+  if (prec == HESS_P_F64) {
+    HOps<double> o;
+    plan_exact<double>(m, d->N, ws, p, o, fac, true);
+    if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
+    run_prep(ex, m, d, p, true);
+    run_exact<double, double>(ex, m, d->N, p, o, fac, ws, 0, static_cast<double*>(H), true);
+  } else {
+    HOps<float> o;
+    // base offset of the per-m factor region = arena usage after prep + operand copies
+    Arena ar(ws);
+    Prep p0;
+    plan_prep(ar, m, d->N, p0, true);
+    plan_opg_ops<float>(ar, m, d->N, p0, o.base);
+    const size_t base_used = ar.used;
+    plan_exact<float>(m, d->N, ws, p, o, fac, false);
+    if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
+    run_prep(ex, m, d, p, true);
+    run_exact<float, float>(ex, m, d->N, p, o, fac, ws, base_used, static_cast<float*>(H), false);
+  }
+  return finish(ex, "hess_exact");
+}
+
+}  // extern "C"

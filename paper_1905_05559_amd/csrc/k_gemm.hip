@@ -1,0 +1,171 @@
+// Generic strided GEMM on MFMA (FP64 and FP32), used for the forward and backward
+// passes, the curvature-factor propagation, the R-operator passes of dense
+// Hessian-vector products and the subspace-iteration products.
+//
+// Tiling: 256 threads = 4 wavefronts in a 2 x 2 grid; each wavefront owns a
+// (BM/2) x (BN/2) sub-tile made of 16 x 16 MFMA blocks.  The K dimension is staged
+// through LDS in chunks of 16, stored k-contiguous per row so that each lane picks
+// up its four k values of a chunk with one vector read; the sum over k inside a
+// chunk is permuted (lane group q takes k = 4q..4q+3 over the four MFMA steps),
+// which is legal because A and B use the same permutation.
+#include "mfma.h"
+
+namespace hs {
+
+namespace {
+
+constexpr int KC = 16;
+constexpr int KP = KC + 4;  // padded row length in LDS (bank spread)
+
+template <typename T, int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g, int64_t tiles_n, int64_t ntiles) {
+  using Op = MfmaOp<T>;
+  using acc_t = typename Op::acc_t;
+  __shared__ __attribute__((aligned(16))) T As[BM * KP];
+  __shared__ __attribute__((aligned(16))) T Bs[BN * KP];
+
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x, ntiles);
+  if (tile < 0) return;
+  const int64_t bz = blockIdx.y;
+  const T* A = g.A + bz * g.sab;
+  const T* B = g.B + bz * g.sbb;
+  T* C = g.C + bz * g.scb;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  constexpr int WM = BM / 2, WN = BN / 2, RB = WM / 16, CB = WN / 16;
+  const int64_t m0 = (tile / tiles_n) * BM, n0 = (tile % tiles_n) * BN;
+
+  constexpr int AE = BM * KC / 256, BE = BN * KC / 256;
+  const bool a_kfast = (g.sak == 1);
+  const bool b_kfast = (g.sbk == 1);
+  T ra[AE], rb[BE];
+
+  auto idx_a = [&](int e, int& m, int& k) {
+    if (a_kfast) { m = e / KC; k = e % KC; } else { k = e / BM; m = e % BM; }
+  };
+  auto idx_b = [&](int e, int& n, int& k) {
+    if (b_kfast) { n = e / KC; k = e % KC; } else { k = e / BN; n = e % BN; }
+  };
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < AE; ++i) {
+      int m, k;
+      idx_a(tid + i * 256, m, k);
+      const int64_t gm = m0 + m, gk = k0 + k;
+      ra[i] = (gm < g.M && gk < g.K) ? A[gm * g.sam + gk * g.sak] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < BE; ++i) {
+      int n, k;
+      idx_b(tid + i * 256, n, k);
+      const int64_t gn = n0 + n, gk = k0 + k;
+      rb[i] = (gn < g.N && gk < g.K) ? B[gk * g.sbk + gn * g.sbn] : T(0);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < AE; ++i) {
+      int m, k;
+      idx_a(tid + i * 256, m, k);
+      As[m * KP + k] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < BE; ++i) {
+      int n, k;
+      idx_b(tid + i * 256, n, k);
+      Bs[n * KP + k] = rb[i];
+    }
+  };
+
+  acc_t acc[RB][CB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) acc[i][j] = Op::zero();
+
+  const int row = lane & 15, q = lane >> 4;
+  const int64_t nk = (g.K + KC - 1) / KC;
+  load(0);
+  store();
+  __syncthreads();
+  for (int64_t kc = 0; kc < nk; ++kc) {
+    if (kc + 1 < nk) load((kc + 1) * KC);
+    T a[RB][4], b[CB][4];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[i][s] = As[(wr * WM + i * 16 + row) * KP + 4 * q + s];
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) b[j][s] = Bs[(wc * WN + j * 16 + row) * KP + 4 * q + s];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) acc[i][j] = Op::mma(a[i][s], b[j][s], acc[i][j]);
+    __syncthreads();
+    if (kc + 1 < nk) {
+      store();
+      __syncthreads();
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = m0 + wr * WM + i * 16 + Op::row_of(q, v);
+        const int64_t n = n0 + wc * WN + j * 16 + row;
+        if (m < g.M && n < g.N) {
+          T* c = C + m * g.scm + n * g.scn;
+          const T val = g.alpha * acc[i][j][v];
+          *c = (g.beta != T(0)) ? val + g.beta * (*c) : val;
+        }
+      }
+}
+
+template <typename T, int BM, int BN>
+void launch(Exec& ex, const GemmArgs<T>& g) {
+  const int64_t tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  const int64_t nt = tm * tn;
+  dim3 grid((unsigned)xcd_grid(nt), (unsigned)g.batch);
+  if (!launch_ok(ex)) return;
+  hipLaunchKernelGGL((gemm_kernel<T, BM, BN>), grid, dim3(256), 0, ex.stream, g, tn, nt);
+}
+
+}  // namespace
+
+template <typename T>
+void gemm(Exec& ex, const GemmArgs<T>& g) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+  if (g.M >= 128 && g.N >= 128)
+    launch<T, 128, 128>(ex, g);
+  else
+    launch<T, 64, 64>(ex, g);
+}
+
+template <typename T>
+void gemm_rm(Exec& ex, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, const T* A,
+             int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc) {
+  GemmArgs<T> g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.sam = ta ? 1 : lda; g.sak = ta ? lda : 1; g.sab = 0;
+  g.B = B; g.sbk = tb ? 1 : ldb; g.sbn = tb ? ldb : 1; g.sbb = 0;
+  g.C = C; g.scm = ldc; g.scn = 1; g.scb = 0;
+  g.alpha = alpha; g.beta = beta; g.batch = 1;
+  gemm<T>(ex, g);
+}
+
+template void gemm<float>(Exec&, const GemmArgs<float>&);
+template void gemm<double>(Exec&, const GemmArgs<double>&);
+template void gemm_rm<float>(Exec&, bool, bool, int64_t, int64_t, int64_t, float, const float*,
+                             int64_t, const float*, int64_t, float, float*, int64_t);
+template void gemm_rm<double>(Exec&, bool, bool, int64_t, int64_t, int64_t, double, const double*,
+                              int64_t, const double*, int64_t, double, double*, int64_t);
+
+}  // namespace hs

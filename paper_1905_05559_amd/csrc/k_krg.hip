@@ -1,0 +1,254 @@
+// Khatri-Rao Gram contraction: the P x P tiles of the OPG and of the exact Hessian.
+//
+// Both matrices are sums over the N examples of products of per-example factors
+// that are indexed by (unit, input) pairs of two layers.  For a row parameter
+// (layer l, unit i', input j') and a column parameter (layer m, unit i, input j):
+//
+//   OPG:  (1/N) sum_n  delta^(l)_{n,i'} abar^(l-1)_{n,j'}  delta^(m)_{n,i} abar^(m-1)_{n,j}
+//   H:    (1/N) sum_n  G^(l,m)_n[i',i] abar^(l-1)_{n,j'} abar^(m-1)_{n,j}  (+ cross-layer term)
+//
+// (abar = activations with a trailing 1 for the bias.)  The per-example gradient
+// matrix J of the OPG definition is never stored: its tiles are formed in LDS
+// from delta and abar (RANK1 mode).  For H the per-example unit-pair weights
+// G_n[i',i] come from the R-operator propagation of unit directions and are
+// applied to the B fragments in registers (PAIR modes).
+//
+// Tile: 128 x 128 outputs per workgroup of 4 wavefronts (2 x 2), each wavefront
+// 64 x 64 = 4 x 4 MFMA blocks of 16 x 16.  Units are padded to a multiple of 16
+// slots in compute space so every MFMA block lies inside one (row unit, column
+// unit) pair.  K (the example index) is staged in chunks of 16 through LDS with
+// the same k-permutation as the generic GEMM.  Symmetric blocks enumerate only the
+// lower triangle of tiles and mirror every stored entry, so the result is exactly
+// symmetric.
+#include "mfma.h"
+
+namespace hs {
+
+namespace {
+
+constexpr int BM = 128, BN = 128, KC = 16, KP = KC + 4;
+constexpr int MAXU = BM / 16 + 1;  // units a tile can touch (pad >= 16)
+
+__device__ __forceinline__ int64_t flat_index(int32_t perm, int64_t off, int32_t Tin, int32_t Tout,
+                                              int64_t u, int64_t s) {
+  const int64_t i = perm ? s : u, j = perm ? u : s;
+  return j < Tin ? off + i * Tin + j : off + (int64_t)Tout * Tin + i;
+}
+
+__device__ __forceinline__ void tile_of(int64_t t, int32_t symmetric, int64_t tiles_c, int64_t& tr,
+                                        int64_t& tc) {
+  if (symmetric) {
+    int64_t r = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (r * (r + 1) / 2 > t) --r;
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    tr = r;
+    tc = t - r * (r + 1) / 2;
+  } else {
+    tr = t / tiles_c;
+    tc = t % tiles_c;
+  }
+}
+
+template <typename T, typename TOut>
+__device__ __forceinline__ void store_out(TOut* out, int64_t idx, double v, int32_t accumulate) {
+  if (accumulate)
+    out[idx] = (TOut)((double)out[idx] + v);
+  else
+    out[idx] = (TOut)v;
+}
+
+template <typename T, typename TOut, int WMODE>
+__global__ __launch_bounds__(256) void krg_kernel(KrgArgs<T, TOut> a, int64_t tiles_c, int64_t ntiles) {
+  using Op = MfmaOp<T>;
+  using acc_t = typename Op::acc_t;
+  __shared__ __attribute__((aligned(16))) T As[BM * KP];
+  __shared__ __attribute__((aligned(16))) T Bs[BN * KP];
+  __shared__ __attribute__((aligned(16))) T Ws[(WMODE == KRG_RANK1) ? 4 : MAXU * MAXU * KC];
+
+  const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
+  if (t < 0) return;
+  int64_t tr, tc;
+  tile_of(t, a.symmetric, tiles_c, tr, tc);
+  const int64_t r0 = tr * BM, c0 = tc * BN;
+  const int64_t ur_lo = r0 / a.r.pad, uc_lo = c0 / a.c.pad;
+  const int64_t ur_hi = min((int64_t)a.r.n_units - 1, (r0 + BM - 1) / a.r.pad);
+  const int64_t uc_hi = min((int64_t)a.c.n_units - 1, (c0 + BN - 1) / a.c.pad);
+  if (WMODE == KRG_PAIR_DIAG && (ur_hi < uc_lo || uc_hi < ur_lo)) return;
+  const int nur = (int)(ur_hi - ur_lo + 1), nuc = (int)(uc_hi - uc_lo + 1);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+
+  // Staging assignment: thread -> one row (column) of the tile and 8 consecutive k.
+  const int srow = tid & 127, sk0 = (tid >> 7) * 8;
+  const int64_t gr = r0 + srow, gc = c0 + srow;
+  const int64_t sur = gr / a.r.pad, ssr = gr % a.r.pad;
+  const int64_t suc = gc / a.c.pad, ssc = gc % a.c.pad;
+  const bool rvalid = sur < a.r.n_units && ssr < a.r.len;
+  const bool cvalid = suc < a.c.n_units && ssc < a.c.len;
+  T ra[8], rbv[8];
+  constexpr int WE = (WMODE == KRG_RANK1) ? 1 : (MAXU * MAXU * KC + 255) / 256;
+  T rw[WE];
+  const int nw = nur * nuc * KC;
+
+  auto load = [&](int64_t n0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t n = n0 + sk0 + i;
+      T va = T(0), vb = T(0);
+      if (n < a.N) {
+        if (rvalid) {
+          va = a.r.src[n * a.r.ld + ssr];
+          if (WMODE == KRG_RANK1 && a.r.scale) va *= a.r.scale[n * a.r.ld_scale + sur];
+        }
+        if (cvalid) {
+          vb = a.c.src[n * a.c.ld + ssc];
+          if (WMODE == KRG_RANK1 && a.c.scale) vb *= a.c.scale[n * a.c.ld_scale + suc];
+        }
+      }
+      ra[i] = va;
+      rbv[i] = vb;
+    }
+    if (WMODE != KRG_RANK1) {
+#pragma unroll
+      for (int i = 0; i < WE; ++i) {
+        const int e = tid + i * 256;
+        T w = T(0);
+        if (e < nw) {
+          const int kk = e % KC, p = e / KC;
+          const int64_t ur = ur_lo + p / nuc, uc = uc_lo + p % nuc;
+          const int64_t n = n0 + kk;
+          if (n < a.N) {
+            if (WMODE == KRG_PAIR_FULL)
+              w = a.wts[(ur * a.c.n_units + uc) * a.ldw + n];
+            else if (ur == uc)
+              w = a.wts[ur * a.ldw + n];
+          }
+        }
+        rw[i] = w;
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      As[srow * KP + sk0 + i] = ra[i];
+      Bs[srow * KP + sk0 + i] = rbv[i];
+    }
+    if (WMODE != KRG_RANK1) {
+#pragma unroll
+      for (int i = 0; i < WE; ++i) {
+        const int e = tid + i * 256;
+        if (e < nw) {
+          const int kk = e % KC, p = e / KC;
+          Ws[((p / nuc) * MAXU + (p % nuc)) * KC + kk] = rw[i];
+        }
+      }
+    }
+  };
+
+  // Unit pair of every MFMA block of this wavefront (wave-uniform).
+  int pu[4], pc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    pu[i] = (int)((r0 + wr * 64 + i * 16) / a.r.pad - ur_lo);
+    pc[i] = (int)((c0 + wc * 64 + i * 16) / a.c.pad - uc_lo);
+  }
+
+  acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = Op::zero();
+
+  const int row = lane & 15, q = lane >> 4;
+  const int64_t nk = (a.N + KC - 1) / KC;
+  load(0);
+  store();
+  __syncthreads();
+  for (int64_t kc = 0; kc < nk; ++kc) {
+    if (kc + 1 < nk) load((kc + 1) * KC);
+    T av[4][4], bv[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) av[i][s] = As[(wr * 64 + i * 16 + row) * KP + 4 * q + s];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) bv[j][s] = Bs[(wc * 64 + j * 16 + row) * KP + 4 * q + s];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (WMODE == KRG_RANK1) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) acc[i][j] = Op::mma(av[i][s], bv[j][s], acc[i][j]);
+        } else {
+          if (WMODE == KRG_PAIR_DIAG && (pu[i] + ur_lo) != (pc[j] + uc_lo)) continue;
+          const T* wp = &Ws[(pu[i] * MAXU + pc[j]) * KC + 4 * q];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) acc[i][j] = Op::mma(av[i][s], bv[j][s] * wp[s], acc[i][j]);
+        }
+      }
+    __syncthreads();
+    if (kc + 1 < nk) {
+      store();
+      __syncthreads();
+    }
+  }
+
+  // Epilogue: scale by 1/N, map compute indices to flat parameter indices.
+  int64_t fcol[4];
+  bool cok[4];
+  int64_t ccomp[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t c = c0 + wc * 64 + j * 16 + row;
+    const int64_t uc = c / a.c.pad, sc = c % a.c.pad;
+    ccomp[j] = c;
+    cok[j] = uc < a.c.n_units && sc < a.c.len;
+    fcol[j] = cok[j] ? flat_index(a.c.perm, a.c.off, a.c.Tin, a.c.Tout, uc, sc) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = r0 + wr * 64 + i * 16 + Op::row_of(q, v);
+      const int64_t ur = r / a.r.pad, sr = r % a.r.pad;
+      if (!(ur < a.r.n_units && sr < a.r.len)) continue;
+      const int64_t fr = flat_index(a.r.perm, a.r.off, a.r.Tin, a.r.Tout, ur, sr);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!cok[j]) continue;
+        if (a.symmetric && r < ccomp[j]) continue;
+        const double val = a.scale * (double)acc[i][j][v];
+        store_out<T, TOut>(a.out, fr * a.ldo + fcol[j], val, a.accumulate);
+        if (a.mirror && !(a.symmetric && r == ccomp[j]))
+          store_out<T, TOut>(a.out, fcol[j] * a.ldo + fr, val, a.accumulate);
+      }
+    }
+}
+
+}  // namespace
+
+template <typename T, typename TOut>
+void krg(Exec& ex, const KrgArgs<T, TOut>& a) {
+  const int64_t rows = (int64_t)a.r.n_units * a.r.pad, cols = (int64_t)a.c.n_units * a.c.pad;
+  const int64_t tr = (rows + BM - 1) / BM, tc = (cols + BN - 1) / BN;
+  const int64_t nt = a.symmetric ? tr * (tr + 1) / 2 : tr * tc;
+  if (nt <= 0) return;
+  if (!launch_ok(ex)) return;
+  dim3 grid((unsigned)xcd_grid(nt));
+  if (a.wmode == KRG_RANK1)
+    hipLaunchKernelGGL((krg_kernel<T, TOut, KRG_RANK1>), grid, dim3(256), 0, ex.stream, a, tc, nt);
+  else if (a.wmode == KRG_PAIR_FULL)
+    hipLaunchKernelGGL((krg_kernel<T, TOut, KRG_PAIR_FULL>), grid, dim3(256), 0, ex.stream, a, tc, nt);
+  else
+    hipLaunchKernelGGL((krg_kernel<T, TOut, KRG_PAIR_DIAG>), grid, dim3(256), 0, ex.stream, a, tc, nt);
+}
+
+template void krg<double, double>(Exec&, const KrgArgs<double, double>&);
+template void krg<float, float>(Exec&, const KrgArgs<float, float>&);
+
+}  // namespace hs

@@ -1,0 +1,150 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (relative Frobenius error over the compared entries): FP64 paths
+1e-10, FP32 paths 1e-5, BF16 OPG 2e-2.  Every result is also reported with its
+max-abs error.  Outputs must be exactly symmetric.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp
+from paper_1905_05559_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 2e-2}
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_05559_amd import api as A
+    return A
+
+
+def relf(A, R):
+    return float(np.linalg.norm(A - R) / np.linalg.norm(R))
+
+
+def report(tag, A, R):
+    e = relf(A, R)
+    print("%-48s relF %.3e  maxabs %.3e" % (tag, e, float(np.abs(A - R).max())), flush=True)
+    sys.stdout.flush()
+    return e
+
+
+def to_dev(api, w, dtype):
+    td = {"float64": torch.float64, "float32": torch.float32}[dtype]
+    model = api.MLP.from_workload(w, dtype=td)
+    X = torch.from_numpy(w.X).to("cuda", td)
+    Y = torch.from_numpy(w.Y).to("cuda", td)
+    return model, X, Y
+
+
+def oracle_of(w):
+    return mlp.model_from(w.T, w.acts, w.W, w.b), w.X.astype(np.float64), w.Y.astype(np.float64)
+
+
+SMALL = [
+    ([4, 8, 3], ["tanh"], 64, 1),
+    ([5, 3], [], 37, 2),
+    ([7, 20, 13, 5], ["sigmoid", "relu"], 100, 3),
+    ([3, 17, 2], ["relu"], 1, 4),
+    ([33, 40, 10], ["tanh"], 129, 5),
+    ([150, 30, 4], ["sigmoid"], 50, 6),
+    ([6, 9, 7, 8, 4], ["tanh", "sigmoid", "tanh"], 70, 7),
+]
+
+
+@pytest.mark.parametrize("T,acts,N,seed", SMALL)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_small_exact_and_opg(api, T, acts, N, seed, prec):
+    print("case T=%s acts=%s N=%d seed=%d prec=%s" % (T, acts, N, seed, prec), flush=True)
+    w = workloads.mlp_gaussian(T, acts, N, seed, dtype="float64" if prec == "f64" else "float32")
+    model, X, Y = to_dev(api, w, w.dtype)
+    om, Xo, Yo = oracle_of(w)
+    Href = mlp.hessian(om, Xo, Yo)
+    Gref = mlp.opg(om, Xo, Yo)
+    H = api.hess_exact(model, X, Y, prec).double().cpu().numpy()
+    G = api.hess_opg(model, X, Y, prec).double().cpu().numpy()
+    assert np.array_equal(H, H.T) and np.array_equal(G, G.T)
+    assert report("H   %s %s" % (T, prec), H, Href) <= TOL[prec]
+    assert report("OPG %s %s" % (T, prec), G, Gref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("T,acts,N,seed", SMALL[:5])
+def test_small_opg_bf16(api, T, acts, N, seed):
+    w = workloads.mlp_gaussian(T, acts, N, seed, dtype="float32")
+    model, X, Y = to_dev(api, w, "float32")
+    om, Xo, Yo = oracle_of(w)
+    G = api.hess_opg(model, X, Y, "bf16").double().cpu().numpy()
+    assert np.array_equal(G, G.T)
+    assert report("OPG %s bf16" % T, G, mlp.opg(om, Xo, Yo)) <= TOL["bf16"]
+
+
+@pytest.fixture(scope="module")
+def sig64():
+    w = workloads.sigmoid_64()
+    om, Xo, Yo = oracle_of(w)
+    return w, om, Xo, Yo, mlp.opg(om, Xo, Yo)
+
+
+SIG64_BLOCKS = [(0, 64), (4032, 4096), (4096, 4170), (4746, 4810)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_sigmoid64_opg_full(api, sig64, prec):
+    w, om, Xo, Yo, Gref = sig64
+    model, X, Y = to_dev(api, w, "float64" if prec == "f64" else "float32")
+    if prec == "f64":
+        model = api.MLP.from_workload(w, dtype=torch.float64)
+        X, Y = X.double(), Y.double()
+    G = api.hess_opg(model, X, Y, prec).double().cpu().numpy()
+    assert np.array_equal(G, G.T)
+    assert report("sigmoid64 OPG %s" % prec, G, Gref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_sigmoid64_exact_sampled_blocks(api, sig64, prec):
+    w, om, Xo, Yo, _ = sig64
+    td = torch.float64 if prec == "f64" else torch.float32
+    model = api.MLP.from_workload(w, dtype=td)
+    X = torch.from_numpy(w.X).to("cuda", td)
+    Y = torch.from_numpy(w.Y).to("cuda", td)
+    H = api.hess_exact(model, X, Y, prec)
+    Hn = H.double().cpu().numpy()
+    del H
+    assert np.array_equal(Hn, Hn.T)
+    for c0, c1 in SIG64_BLOCKS:
+        ref = mlp.hessian_cols(om, Xo, Yo, c0, c1)
+        assert report("sigmoid64 H[:, %d:%d] %s" % (c0, c1, prec), Hn[:, c0:c1], ref) <= TOL[prec]
+
+
+def test_sigmoid64_reduced_n_exact_full(api):
+    w = workloads.sigmoid_64(N=600)
+    om, Xo, Yo = oracle_of(w)
+    Href = mlp.hessian(om, Xo, Yo, block=256)
+    for prec in ("f64", "f32"):
+        td = torch.float64 if prec == "f64" else torch.float32
+        model = api.MLP.from_workload(w, dtype=td)
+        X = torch.from_numpy(w.X).to("cuda", td)
+        Y = torch.from_numpy(w.Y).to("cuda", td)
+        H = api.hess_exact(model, X, Y, prec).double().cpu().numpy()
+        assert report("sigmoid64 N=600 H %s" % prec, H, Href) <= TOL[prec]
+
+
+def test_run_twice_bitwise(api):
+    """No atomics in any reduction: two runs give bitwise-identical results."""
+    w = workloads.mlp_gaussian([33, 40, 10], ["tanh"], 300, 9, dtype="float32")
+    model, X, Y = to_dev(api, w, "float32")
+    for prec in ("f32", "bf16"):
+        a = api.hess_opg(model, X, Y, prec).cpu()
+        b = api.hess_opg(model, X, Y, prec).cpu()
+        assert torch.equal(a, b)
+    a = api.hess_exact(model, X, Y, "f32").cpu()
+    b = api.hess_exact(model, X, Y, "f32").cpu()
+    assert torch.equal(a, b)
