@@ -1,0 +1,211 @@
+#!/usr/bin/env python
+"""Benchmark of the Hessian / OPG hot path on one MI355X.
+
+Workload (default): the MNIST-shaped synthetic MLP [784, 100, 10], ReLU hidden
+layer, N = 60000 examples, x_{n,j} = 0 with probability 0.8 else U[0,1), labels
+uniform over 10 classes, Glorot-uniform weights, zero biases (P = 79510).  One
+step computes, with inputs already resident in HBM:
+  * the OPG  J^T J / N  (BF16 operands, FP32 accumulation), P x P FP32
+  * the exact Hessian H (FP32 MFMA), P x P FP32
+value = 2 P^2 / step time  ("exact-H+OPG P^2-entries/s": P^2 entries of each matrix).
+
+The JSON line also carries the roofline of the dominant kernel (algorithmic flops
+per launch / average launch time from HIP events on the library's stream) and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}   # MI355X dense MFMA peaks
+HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_dtype(name: str) -> str:
+    for k in ("bf16", "f64", "f32"):
+        if "_" + k in name:
+            return k
+    return "f32"
+
+
+def source_hash() -> str:
+    """Hash of the contraction kernel sources (traffic counters are valid only for this hash)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1905_05559_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.startswith("k_krg") or f == "mfma.h":
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """Measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled) for `kernel`, if the
+    counters were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(w, seconds_hint: float):
+    """The FP64 oracle on a bounded sample of the same workload.
+
+    Sample: H columns [0, bh) (basis Hessian-vector products over all N examples) and
+    the OPG tile rows [0, bg) x columns [0, cg) (from those columns of J).  Rate in
+    P^2-entries/s for one H entry plus one OPG entry: 2 / (t_H/entry + t_OPG/entry)."""
+    from oracle import mlp
+
+    om = mlp.model_from(w.T, w.acts, w.W, w.b)
+    X = w.X.astype(np.float64)
+    Y = w.Y.astype(np.float64)
+    P = mlp.num_params(w.T)
+    bh = 16
+    t0 = time.perf_counter()
+    mlp.hessian_cols(om, X, Y, 0, bh, block=bh)
+    th = time.perf_counter() - t0
+    bg, cg = 256, 2048
+    t0 = time.perf_counter()
+    mlp.opg_tile(om, X, Y, list(range(bg)), list(range(cg)))
+    tg = time.perf_counter() - t0
+    per_h = th / (bh * P)
+    per_g = tg / (bg * cg)
+    threads = os.environ.get("OMP_NUM_THREADS") or str(len(os.sched_getaffinity(0)))
+    return {
+        "value": 2.0 / (per_h + per_g),
+        "unit": "P^2-entries/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": "FP64 NumPy oracle, same workload: H columns 0..%d (basis HVPs over all N=%d examples, "
+                  "%.1f s) and OPG tile %dx%d from J columns (%.1f s); rate = 2/(s per H entry + s per OPG "
+                  "entry)" % (bh, X.shape[0], th, bg, cg, tg),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mnist", choices=["mnist", "sigmoid64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1905_05559_amd import api, workloads
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    t0 = time.perf_counter()
+    w = workloads.mnist_relu() if args.workload == "mnist" else workloads.sigmoid_64()
+    log("workload %s T=%s N=%d P=%d (generated in %.1f s)" % (w.name, w.T, w.N, w.P, time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    model = api.MLP.from_workload(w, dtype=torch.float32)
+    X = torch.from_numpy(w.X).to(dev, torch.float32)
+    Y = torch.from_numpy(w.Y).to(dev, torch.float32)
+    P = w.P
+
+    ctx = api.Context(0)
+    ctx.set_option("profile", 1)
+    H = torch.empty((P, P), dtype=torch.float32, device=dev)
+    G = torch.empty((P, P), dtype=torch.float32, device=dev)
+    ws_bytes = max(api.workspace_size("exact", model, X, Y, "f32", ctx=ctx),
+                   api.workspace_size("opg", model, X, Y, "bf16", ctx=ctx))
+    ctx.workspace(ws_bytes)
+    log("outputs 2 x %.1f GB, workspace %.2f GB" % (P * P * 4 / 1e9, ws_bytes / 1e9))
+
+    def step():
+        api.hess_opg(model, X, Y, "bf16", out=G, ctx=ctx)
+        api.hess_exact(model, X, Y, "f32", out=H, ctx=ctx)
+
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        step()
+        log("warmup step %d: %.3f s" % (i, time.perf_counter() - t))
+    torch.cuda.synchronize()
+    ctx.profile_reset()
+    s = ctx.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for i in range(args.steps):
+        step()
+        log("step %d done" % i)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    prof = ctx.profile()
+    for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]):
+        log("  %-24s launches %5d  total %9.2f ms  %8.2f TFLOP/s  %8.1f GB/s" % (
+            k, v["launches"], v["ms"], v["flops"] / v["ms"] / 1e9 if v["ms"] else 0,
+            v["bytes"] / v["ms"] / 1e6 if v["ms"] else 0))
+    dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    dname, d = dom
+    dt = kernel_dtype(dname)
+    achieved = d["flops"] / d["ms"] / 1e9  # TFLOP/s
+    traffic = load_traffic(dname)
+    roofline = {
+        "bound": "mfma", "kernel": dname, "dtype": dt,
+        "achieved": round(achieved, 3), "peak": PEAKS_TFLOPS[dt], "unit": "TFLOP/s",
+        "frac": round(achieved / PEAKS_TFLOPS[dt], 4),
+        "avg_launch_ms": round(d["ms"] / d["launches"], 4),
+        "flops_per_launch": d["flops"] / d["launches"],
+        "traffic": traffic,
+        "share_of_step": round(d["ms"] / args.steps / ms, 4),
+    }
+    value = 2.0 * P * P / (ms / 1e3)
+    out = {
+        "metric": "exact-H+OPG P^2-entries/s",
+        "value": value,
+        "unit": "P^2-entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (H) + bf16->f32 (OPG)",
+        "data": "synthetic",
+        "config": {"workload": w.name, "T": w.T, "N": w.N, "P": P,
+                   "step": "OPG (BF16 MFMA, FP32 acc) + exact H (FP32 MFMA), P x P each, inputs resident in HBM"},
+        "roofline": roofline,
+        "kernels": {k: {"launches": v["launches"], "ms_per_step": v["ms"] / args.steps,
+                        "tflops": v["flops"] / v["ms"] / 1e9 if v["ms"] else 0.0} for k, v in prof.items()},
+    }
+    del H, G
+    ctx.release_workspace()
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(w, 20.0)
+        log("cpu baseline took %.1f s" % (time.perf_counter() - t))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -98,8 +98,27 @@ const char* hess_last_error(const hess_ctx* ctx);
  * HESS_E_BUDGET before launching anything.  HESS_OPT_FAULT_AFTER: test hook; when
  * >= 0, the call during which that many kernel launches have been issued on this
  * context reports HESS_E_DEVICE (no kernel faults; the launch is skipped). */
-typedef enum { HESS_OPT_CHECK_INPUTS = 0, HESS_OPT_HBM_BUDGET = 1, HESS_OPT_FAULT_AFTER = 2 } hess_opt;
+typedef enum {
+  HESS_OPT_CHECK_INPUTS = 0, HESS_OPT_HBM_BUDGET = 1, HESS_OPT_FAULT_AFTER = 2, HESS_OPT_PROFILE = 3
+} hess_opt;
 hess_status hess_set_option(hess_ctx* ctx, int opt, int64_t value);
+
+/* Per-kernel timing.  With HESS_OPT_PROFILE = 1 every P x P contraction and every
+ * GEMM launch is bracketed by HIP events on the context stream; the elapsed times
+ * are collected when the call synchronises.  hess_profile_read copies up to
+ * max_entries aggregates (one per kernel class, since the last reset) to `out`
+ * and returns the number of classes; flops and bytes are the algorithmic counts
+ * of the launches (2 flops per multiply-add; bytes = operands read once plus
+ * outputs written). */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double ms;
+  double flops;
+  double bytes;
+} hess_prof_entry;
+int hess_profile_read(hess_ctx* ctx, hess_prof_entry* out, int max_entries);
+hess_status hess_profile_reset(hess_ctx* ctx);
 
 /* P of the model (Sec. 2).  Host-only; validates the widths. */
 hess_status hess_num_params(const hess_mlp* m, int64_t* P);
@@ -121,7 +140,10 @@ hess_status hess_exact(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int
                        void* H, void* ws, size_t ws_bytes);
 
 /* OPG = (1/N) sum_n grad C_n grad C_n^T = J^T J / N with J[n,:] = grad C_n
- * (paper, Sec. 3, the OPG definition and its Jacobian form; J is never stored).
+ * (paper, Sec. 3, the OPG definition and its Jacobian form).  For HESS_P_F64 and
+ * HESS_P_F32 the tiles of J are formed in LDS from the per-example factors and J
+ * is never stored; for HESS_P_BF16 J^T is formed once in BF16 in the workspace
+ * (P x N x 2 bytes) and contracted as one symmetric Gram product.
  * G: device, P x P row-major, FP64 for HESS_P_F64 else FP32, exactly symmetric. */
 hess_status hess_opg(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int prec,
                      void* G, void* ws, size_t ws_bytes);

@@ -17,13 +17,13 @@ ACT = {"tanh": 0, "sigmoid": 1, "relu": 2}
 DTYPE = {"float64": 0, "float32": 1}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 OP = {"exact": 0, "opg": 1, "hvp": 2, "topk": 3, "predvar": 4}
-OPT = {"check_inputs": 0, "hbm_budget": 1, "fault_after": 2}
+OPT = {"check_inputs": 0, "hbm_budget": 1, "fault_after": 2, "profile": 3}
 
 # Every symbol include/hess.h declares.
 EXPORTS = (
     "hess_create", "hess_destroy", "hess_status_str", "hess_last_error", "hess_set_option",
     "hess_num_params", "hess_workspace_size", "hess_exact", "hess_opg", "hess_hvp",
-    "hess_topk_eig", "hess_predvar",
+    "hess_topk_eig", "hess_predvar", "hess_profile_read", "hess_profile_reset",
 )
 
 
@@ -45,6 +45,11 @@ class HessEigOpts(C.Structure):
 class HessEigInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("applies", C.c_int32), ("max_rel_residual", C.c_double),
                 ("shift_used", C.c_double)]
+
+
+class HessProfEntry(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("ms", C.c_double), ("flops", C.c_double),
+                ("bytes", C.c_double)]
 
 
 _lib = None
@@ -75,6 +80,8 @@ def load(path: str = LIB_PATH):
         "hess_topk_eig": (st, [vp, pm, pd, i64, C.POINTER(HessEigOpts), vp, vp,
                                C.POINTER(HessEigInfo), vp, C.c_size_t]),
         "hess_predvar": (st, [vp, pm, i64, vp, vp, C.c_double, i64, vp, vp, vp, vp, C.c_size_t]),
+        "hess_profile_read": (C.c_int, [vp, C.POINTER(HessProfEntry), C.c_int]),
+        "hess_profile_reset": (st, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -56,6 +56,16 @@ class Context:
     def set_option(self, name: str, value: int):
         self._check(self.lib.hess_set_option(self.h, L.OPT[name], int(value)))
 
+    def profile(self) -> dict:
+        """Per-kernel-class aggregates {name: {launches, ms, flops, bytes}} since the last reset."""
+        buf = (L.HessProfEntry * 64)()
+        n = self.lib.hess_profile_read(self.h, buf, 64)
+        return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms, "flops": buf[i].flops,
+                                       "bytes": buf[i].bytes} for i in range(min(n, 64))}
+
+    def profile_reset(self):
+        self._check(self.lib.hess_profile_reset(self.h))
+
     def last_error(self) -> str:
         return self.lib.hess_last_error(self.h).decode()
 

@@ -6,6 +6,7 @@
 #include <stddef.h>
 
 #include <string>
+#include <vector>
 
 #include "hess.h"
 
@@ -40,6 +41,10 @@ struct Exec {
 };
 
 bool launch_ok(Exec& ex);   // fault-injection hook + hipGetLastError check
+
+// Profiling brackets around one launch (no-ops unless HESS_OPT_PROFILE is set).
+int prof_begin(Exec& ex, const char* name, double flops, double bytes);
+void prof_end(Exec& ex, int token);
 
 // ---------------------------------------------------------------------------
 // Generic strided GEMM on MFMA:  C(m,n) = alpha * sum_k A(m,k) B(k,n) + beta * C(m,n)
@@ -100,8 +105,17 @@ struct KrgArgs {
 };
 template <typename T, typename TOut>
 void krg(Exec& ex, const KrgArgs<T, TOut>& a);
-// BF16 variant (RANK1 only): operands rounded to bf16 after scaling, fp32 accumulate.
-void krg_bf16(Exec& ex, const KrgArgs<float, float>& a);
+// BF16 OPG: materialise Jt (P x ldk, BF16, p-major) then one symmetric Gram product.
+constexpr int JT_MAXL = 16;
+struct JtArgs {
+  __bf16* Jt; int64_t ldk; int64_t P; int64_t N; int nlayers;
+  const float* delta[JT_MAXL]; int64_t ld_delta[JT_MAXL];   // per weight layer k: delta^(k+2) (N x T)
+  const float* abar[JT_MAXL]; int64_t ld_abar[JT_MAXL];     // abar^(k+1) (N x lda, bias column = 1)
+  int64_t offW[JT_MAXL]; int32_t Tin[JT_MAXL], Tout[JT_MAXL];
+};
+void jt_bf16(Exec& ex, const JtArgs& a);
+int64_t jt_ld(int64_t N);
+void gram_bf16(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64_t N, float scale, float* C, int64_t ldc);
 
 // ---------------------------------------------------------------------------
 // Element-wise and small kernels (k_elem.hip).
@@ -149,7 +163,22 @@ void factor_combine(Exec& ex, double* G, int64_t Tk, int64_t Tm, const double* D
 
 }  // namespace hs
 
+struct hess_prof_rec {
+  int agg;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+struct hess_prof_agg {
+  std::string name;
+  int64_t launches = 0;
+  double ms = 0, flops = 0, bytes = 0;
+};
+
 struct hess_ctx {
+  int profile = 0;
+  std::vector<hess_prof_rec> pending;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<hess_prof_agg> aggs;
   int device = 0;
   hipStream_t stream = nullptr;
   std::string last_error;

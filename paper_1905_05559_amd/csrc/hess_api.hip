@@ -23,6 +23,57 @@ bool launch_ok(Exec& ex) {
   return true;
 }
 
+int prof_begin(Exec& ex, const char* name, double flops, double bytes) {
+  hess_ctx* c = ex.ctx;
+  if (!c->profile) return -1;
+  int agg = -1;
+  for (size_t i = 0; i < c->aggs.size(); ++i)
+    if (c->aggs[i].name == name) agg = (int)i;
+  if (agg < 0) {
+    c->aggs.push_back(hess_prof_agg());
+    c->aggs.back().name = name;
+    agg = (int)c->aggs.size() - 1;
+  }
+  hess_prof_rec r;
+  r.agg = agg;
+  r.flops = flops;
+  r.bytes = bytes;
+  for (hipEvent_t* e : {&r.a, &r.b}) {
+    if (!c->event_pool.empty()) {
+      *e = c->event_pool.back();
+      c->event_pool.pop_back();
+    } else if (hipEventCreate(e) != hipSuccess) {
+      return -1;
+    }
+  }
+  hipEventRecord(r.a, ex.stream);
+  c->pending.push_back(r);
+  return (int)c->pending.size() - 1;
+}
+
+void prof_end(Exec& ex, int token) {
+  if (token < 0) return;
+  hipEventRecord(ex.ctx->pending[token].b, ex.stream);
+}
+
+// After the stream has been synchronised: fold the pending event pairs into the aggregates.
+static void prof_collect(hess_ctx* c) {
+  for (auto& r : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      hess_prof_agg& g = c->aggs[r.agg];
+      g.launches += 1;
+      g.ms += ms;
+      g.flops += r.flops;
+      g.bytes += r.bytes;
+    }
+    c->event_pool.push_back(r.a);
+    c->event_pool.push_back(r.b);
+  }
+  c->pending.clear();
+  (void)hipGetLastError();
+}
+
 int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 hess_status fail(hess_ctx* ctx, hess_status s, const std::string& msg) {
@@ -190,6 +241,7 @@ hess_status finish(Exec& ex, const char* what) {
   hess_ctx* ctx = ex.ctx;
   hipError_t e1 = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(ex.stream);
+  prof_collect(ctx);
   if (ctx->fault_hit) return fail(ctx, HESS_E_DEVICE, std::string(what) + ": injected device fault");
   if (e1 != hipSuccess || e2 != hipSuccess)
     return fail(ctx, HESS_E_DEVICE, std::string(what) + ": " +
@@ -242,6 +294,8 @@ KrgSide<T> side_layer(const Model& m, int l, const T* abar, int64_t lda, const T
 template <typename T>
 struct OpgBufs {
   std::vector<T*> abar, delta;
+  __bf16* Jt = nullptr;
+  int64_t ldk = 0;
 };
 
 template <typename T>
@@ -259,8 +313,30 @@ void cast_ops(Exec& ex, const Model& m, const Prep& p, OpgBufs<T>& b) {
   for (int l = 2; l <= m.L; ++l) cast_copy<T>(ex, p.delta[l], b.delta[l], p.N * m.T[l - 1]);
 }
 
+// BF16: J^T formed once (rounded to BF16), then one symmetric Gram product over all P.
+void run_opg_bf16(Exec& ex, const Model& m, int64_t N, const Prep& p, const OpgBufs<float>& b, float* G) {
+  JtArgs a;
+  a.Jt = b.Jt;
+  a.ldk = b.ldk;
+  a.P = m.P;
+  a.N = N;
+  a.nlayers = m.L - 1;
+  for (int k = 0; k < m.L - 1; ++k) {
+    const int l = k + 2;
+    a.delta[k] = b.delta[l];
+    a.ld_delta[k] = m.T[l - 1];
+    a.abar[k] = b.abar[l - 1];
+    a.ld_abar[k] = p.lda[l - 1];
+    a.offW[k] = m.offW[k];
+    a.Tin[k] = (int32_t)m.T[k];
+    a.Tout[k] = (int32_t)m.T[k + 1];
+  }
+  jt_bf16(ex, a);
+  gram_bf16(ex, b.Jt, m.P, b.ldk, N, (float)(1.0 / (double)N), G, m.P);
+}
+
 template <typename T, typename TOut>
-void run_opg(Exec& ex, const Model& m, int64_t N, const Prep& p, const OpgBufs<T>& b, TOut* G, bool bf16) {
+void run_opg(Exec& ex, const Model& m, int64_t N, const Prep& p, const OpgBufs<T>& b, TOut* G) {
   const int L = m.L;
   for (int l = 2; l <= L; ++l)
     for (int mm = 2; mm <= l; ++mm) {
@@ -277,12 +353,6 @@ void run_opg(Exec& ex, const Model& m, int64_t N, const Prep& p, const OpgBufs<T
       a.mirror = 1;
       a.scale = 1.0 / (double)N;
       a.N = N;
-      if constexpr (std::is_same<T, float>::value && std::is_same<TOut, float>::value) {
-        if (bf16) {
-          krg_bf16(ex, a);
-          continue;
-        }
-      }
       krg<T, TOut>(ex, a);
     }
 }
@@ -293,7 +363,12 @@ size_t plan_opg(const Model& m, int64_t N, int prec, void* ws, Prep& p, void* op
   if (prec == HESS_P_F64) {
     // the FP64 prep arrays are the operands
   } else {
-    plan_opg_ops<float>(ar, m, N, p, *static_cast<OpgBufs<float>*>(ops));
+    OpgBufs<float>& b = *static_cast<OpgBufs<float>*>(ops);
+    plan_opg_ops<float>(ar, m, N, p, b);
+    if (prec == HESS_P_BF16) {
+      b.ldk = jt_ld(N);
+      b.Jt = ar.take<__bf16>((size_t)m.P * b.ldk);
+    }
   }
   return ar.used;
 }
@@ -333,7 +408,6 @@ size_t plan_exact(const Model& m, int64_t N, void* ws, Prep& p, HOps<T>& ops, st
   const size_t base_used = ar.used;
   size_t peak = base_used;
   fac.assign(L + 1, HFactors());
-  std::vector<T*> Gop_dummy;
   for (int mm = 2; mm <= L; ++mm) {
     Arena a2(ws);
     a2.used = base_used;
@@ -494,7 +568,34 @@ hess_status hess_create(hess_ctx** ctx, int device, void* stream) {
 }
 
 hess_status hess_destroy(hess_ctx* ctx) {
+  if (ctx) {
+    if (!ctx->pending.empty()) {
+      (void)hipStreamSynchronize(ctx->stream);
+      prof_collect(ctx);
+    }
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  }
   delete ctx;
+  return HESS_OK;
+}
+
+int hess_profile_read(hess_ctx* ctx, hess_prof_entry* out, int max_entries) {
+  if (!ctx) return 0;
+  const int n = (int)ctx->aggs.size();
+  for (int i = 0; i < n && i < max_entries && out; ++i) {
+    std::memset(&out[i], 0, sizeof(hess_prof_entry));
+    std::strncpy(out[i].name, ctx->aggs[i].name.c_str(), sizeof(out[i].name) - 1);
+    out[i].launches = ctx->aggs[i].launches;
+    out[i].ms = ctx->aggs[i].ms;
+    out[i].flops = ctx->aggs[i].flops;
+    out[i].bytes = ctx->aggs[i].bytes;
+  }
+  return n;
+}
+
+hess_status hess_profile_reset(hess_ctx* ctx) {
+  if (!ctx) return HESS_E_ARG;
+  ctx->aggs.clear();
   return HESS_OK;
 }
 
@@ -523,6 +624,7 @@ hess_status hess_set_option(hess_ctx* ctx, int opt, int64_t value) {
     case HESS_OPT_CHECK_INPUTS: ctx->check_inputs = value != 0; return HESS_OK;
     case HESS_OPT_HBM_BUDGET: ctx->hbm_budget = value; return HESS_OK;
     case HESS_OPT_FAULT_AFTER: ctx->fault_after = value; ctx->launches = 0; return HESS_OK;
+    case HESS_OPT_PROFILE: ctx->profile = value != 0; return HESS_OK;
   }
   return fail(ctx, HESS_E_ARG, "unknown option");
 }
@@ -587,6 +689,8 @@ hess_status hess_opg(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int
   if ((s = validate_data(ctx, d, true)) != HESS_OK) return s;
   if (prec != HESS_P_F64 && prec != HESS_P_F32 && prec != HESS_P_BF16)
     return fail(ctx, HESS_E_ARG, "bad precision");
+  if (prec == HESS_P_BF16 && m.L - 1 > JT_MAXL)
+    return fail(ctx, HESS_E_UNSUPPORTED, "BF16 OPG supports at most 16 weight layers");
   if (!G) return fail(ctx, HESS_E_ARG, "output is NULL");
   const size_t need = ws_opg(m, d->N, prec);
   const size_t out_bytes = (size_t)m.P * m.P * (prec == HESS_P_F64 ? 8 : 4);
@@ -600,10 +704,13 @@ hess_status hess_opg(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int
     OpgBufs<double> bd;
     bd.abar = p.Abar;
     bd.delta = p.delta;
-    run_opg<double, double>(ex, m, d->N, p, bd, static_cast<double*>(G), false);
+    run_opg<double, double>(ex, m, d->N, p, bd, static_cast<double*>(G));
   } else {
     cast_ops<float>(ex, m, p, b);
-    run_opg<float, float>(ex, m, d->N, p, b, static_cast<float*>(G), prec == HESS_P_BF16);
+    if (prec == HESS_P_BF16)
+      run_opg_bf16(ex, m, d->N, p, b, static_cast<float*>(G));
+    else
+      run_opg<float, float>(ex, m, d->N, p, b, static_cast<float*>(G));
   }
   return finish(ex, "hess_opg");
 }

@@ -135,7 +135,11 @@ void launch(Exec& ex, const GemmArgs<T>& g) {
   const int64_t nt = tm * tn;
   dim3 grid((unsigned)xcd_grid(nt), (unsigned)g.batch);
   if (!launch_ok(ex)) return;
+  const double b = (double)g.batch;
+  const int tok = prof_begin(ex, sizeof(T) == 8 ? "gemm_f64" : "gemm_f32", 2.0 * g.M * g.N * g.K * b,
+                             (double)(g.M * g.K + g.K * g.N + g.M * g.N) * sizeof(T) * b);
   hipLaunchKernelGGL((gemm_kernel<T, BM, BN>), grid, dim3(256), 0, ex.stream, g, tn, nt);
+  prof_end(ex, tok);
 }
 
 }  // namespace

@@ -57,7 +57,7 @@ __device__ __forceinline__ void store_out(TOut* out, int64_t idx, double v, int3
     out[idx] = (TOut)v;
 }
 
-template <typename T, typename TOut, int WMODE>
+template <typename T, typename TOut, int WMODE, bool SYM>
 __global__ __launch_bounds__(256) void krg_kernel(KrgArgs<T, TOut> a, int64_t tiles_c, int64_t ntiles) {
   using Op = MfmaOp<T>;
   using acc_t = typename Op::acc_t;
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void krg_kernel(KrgArgs<T, TOut> a, int64_t ti
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
   if (t < 0) return;
   int64_t tr, tc;
-  tile_of(t, a.symmetric, tiles_c, tr, tc);
+  tile_of(t, SYM, tiles_c, tr, tc);
   const int64_t r0 = tr * BM, c0 = tc * BN;
   const int64_t ur_lo = r0 / a.r.pad, uc_lo = c0 / a.c.pad;
   const int64_t ur_hi = min((int64_t)a.r.n_units - 1, (r0 + BM - 1) / a.r.pad);
@@ -221,10 +221,10 @@ __global__ __launch_bounds__(256) void krg_kernel(KrgArgs<T, TOut> a, int64_t ti
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (!cok[j]) continue;
-        if (a.symmetric && r < ccomp[j]) continue;
+        if (SYM && r < ccomp[j]) continue;
         const double val = a.scale * (double)acc[i][j][v];
         store_out<T, TOut>(a.out, fr * a.ldo + fcol[j], val, a.accumulate);
-        if (a.mirror && !(a.symmetric && r == ccomp[j]))
+        if (a.mirror && !(SYM && r == ccomp[j]))
           store_out<T, TOut>(a.out, fcol[j] * a.ldo + fr, val, a.accumulate);
       }
     }
@@ -239,13 +239,34 @@ void krg(Exec& ex, const KrgArgs<T, TOut>& a) {
   const int64_t nt = a.symmetric ? tr * (tr + 1) / 2 : tr * tc;
   if (nt <= 0) return;
   if (!launch_ok(ex)) return;
+  // algorithmic work of this launch (for the per-kernel profile)
+  const double Pr = (double)a.r.n_units * a.r.len, Pc = (double)a.c.n_units * a.c.len;
+  double entries = a.symmetric ? Pr * (Pr + 1) / 2 : Pr * Pc;
+  if (a.wmode == KRG_PAIR_DIAG) entries = (double)std::min(a.r.n_units, a.c.n_units) * a.r.len * a.c.len;
+  double wbytes = 0;
+  if (a.wmode == KRG_PAIR_FULL) wbytes = (double)a.r.n_units * a.c.n_units * a.N * sizeof(T);
+  if (a.wmode == KRG_PAIR_DIAG) wbytes = (double)a.r.n_units * a.N * sizeof(T);
+  if (a.wmode == KRG_RANK1) wbytes = (double)a.N * (a.r.n_units + a.c.n_units) * sizeof(T);
+  const double src = (double)a.N * (a.r.ld + (a.symmetric ? 0 : a.c.ld)) * sizeof(T);
+  const double obytes = entries * sizeof(TOut) * (a.mirror ? 2 : 1) * (a.accumulate ? 2 : 1);
+  const char* names[2][3][2] = {{{"krg_f32_rank1", "krg_f32_rank1_sym"}, {"krg_f32_pair", "krg_f32_pair_sym"},
+                                 {"krg_f32_pairdiag", "krg_f32_pairdiag_sym"}},
+                                {{"krg_f64_rank1", "krg_f64_rank1_sym"}, {"krg_f64_pair", "krg_f64_pair_sym"},
+                                 {"krg_f64_pairdiag", "krg_f64_pairdiag_sym"}}};
+  const int tok = prof_begin(ex, names[sizeof(T) == 8][a.wmode][a.symmetric ? 1 : 0], 2.0 * a.N * entries,
+                             src + wbytes + obytes);
   dim3 grid((unsigned)xcd_grid(nt));
-  if (a.wmode == KRG_RANK1)
-    hipLaunchKernelGGL((krg_kernel<T, TOut, KRG_RANK1>), grid, dim3(256), 0, ex.stream, a, tc, nt);
-  else if (a.wmode == KRG_PAIR_FULL)
-    hipLaunchKernelGGL((krg_kernel<T, TOut, KRG_PAIR_FULL>), grid, dim3(256), 0, ex.stream, a, tc, nt);
-  else
-    hipLaunchKernelGGL((krg_kernel<T, TOut, KRG_PAIR_DIAG>), grid, dim3(256), 0, ex.stream, a, tc, nt);
+#define KRG_LAUNCH(MODE, SYMV) \
+  hipLaunchKernelGGL((krg_kernel<T, TOut, MODE, SYMV>), grid, dim3(256), 0, ex.stream, a, tc, nt)
+  if (a.wmode == KRG_RANK1) {
+    if (a.symmetric) KRG_LAUNCH(KRG_RANK1, true); else KRG_LAUNCH(KRG_RANK1, false);
+  } else if (a.wmode == KRG_PAIR_FULL) {
+    if (a.symmetric) KRG_LAUNCH(KRG_PAIR_FULL, true); else KRG_LAUNCH(KRG_PAIR_FULL, false);
+  } else {
+    KRG_LAUNCH(KRG_PAIR_DIAG, false);
+  }
+#undef KRG_LAUNCH
+  prof_end(ex, tok);
 }
 
 template void krg<double, double>(Exec&, const KrgArgs<double, double>&);

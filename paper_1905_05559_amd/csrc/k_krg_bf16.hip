@@ -1,110 +1,142 @@
-// BF16 variant of the Khatri-Rao Gram contraction for the OPG (RANK1 mode only):
-// the per-example gradient tiles J[n, p] = delta^(l)_{n,i} abar^(l-1)_{n,j} are formed
-// in FP32 while staging, rounded to BF16 (round to nearest even) into LDS and
-// contracted with v_mfma_f32_16x16x32_bf16 into FP32 accumulators.
+// BF16 OPG: OPG = J^T J / N with the per-example gradient matrix J formed once in
+// BF16 and contracted as one symmetric Gram product on BF16 MFMA.
 //
-// Tile: 128 x 128 per workgroup, 4 wavefronts in 2 x 2, each 64 x 64 = 4 x 4 blocks;
-// K chunk 32 = one MFMA step per block.  LDS rows hold 32 k values (+8 padding).
+// 1) jt_bf16: Jt[p][n] = bf16_rne(delta^(l)_{n,i} * abar^(l-1)_{n,j}) for the flat
+//    parameter p = (layer l, unit i, input j) (j = T_{l-1} is the bias, abar = 1);
+//    columns n >= N are zero.  Jt is p-major so that the contraction index n is
+//    contiguous for the MFMA operands.  (On a 288 GB part the BF16 J of the
+//    MNIST-shaped workload, 9.5 GB, fits comfortably in the workspace.)
+// 2) gram_bf16: C[p][q] = scale * sum_n Jt[p][n] Jt[q][n] for the lower triangle of
+//    256 x 256 tiles, mirrored, FP32 accumulation (v_mfma_f32_16x16x32_bf16).
+//    4 wavefronts (2 x 2), each 128 x 128 = 8 x 8 MFMA blocks; K staged through LDS
+//    in chunks of 64 with 16-byte vector loads prefetched one chunk ahead.
 #include "mfma.h"
 
 namespace hs {
 
 namespace {
 
-constexpr int BM = 128, BN = 128, KC = 32, KP = KC + 8;
+constexpr int JP = 64, JN = 64;   // jt_bf16 tile (params x examples)
 
-__device__ __forceinline__ int64_t flat_index(int32_t perm, int64_t off, int32_t Tin, int32_t Tout,
-                                              int64_t u, int64_t s) {
-  const int64_t i = perm ? s : u, j = perm ? u : s;
-  return j < Tin ? off + i * Tin + j : off + (int64_t)Tout * Tin + i;
+__global__ __launch_bounds__(256) void jt_bf16_kernel(JtArgs a) {
+  __shared__ __bf16 tile[JP][JN + 8];
+  const int64_t tiles_n = a.ldk / JN;
+  const int64_t p0 = (blockIdx.x / tiles_n) * JP, n0 = (blockIdx.x % tiles_n) * JN;
+  const int tid = threadIdx.x;
+  // phase 1: each thread forms 16 entries (one parameter, 16 examples)
+  const int pp = tid & 63, nb = (tid >> 6) * 16;
+  const int64_t p = p0 + pp;
+  int lay = -1;
+  int64_t i = 0, j = 0;
+  if (p < a.P) {
+    for (int k = 0; k < a.nlayers; ++k) {
+      const int64_t ow = a.offW[k], ob = ow + (int64_t)a.Tout[k] * a.Tin[k];
+      if (p >= ow && p < ob + a.Tout[k]) {
+        lay = k;
+        if (p < ob) {
+          i = (p - ow) / a.Tin[k];
+          j = (p - ow) % a.Tin[k];
+        } else {
+          i = p - ob;
+          j = a.Tin[k];
+        }
+        break;
+      }
+    }
+  }
+#pragma unroll 4
+  for (int t = 0; t < 16; ++t) {
+    const int64_t n = n0 + nb + t;
+    float v = 0.f;
+    if (lay >= 0 && n < a.N) {
+      const float d = a.delta[lay][n * a.ld_delta[lay] + i];
+      const float x = a.abar[lay][n * a.ld_abar[lay] + j];
+      v = d * x;
+    }
+    tile[pp][nb + t] = (__bf16)v;
+  }
+  __syncthreads();
+  // phase 2: write 64 rows x 128 bytes, 16 bytes per thread
+  for (int e = tid; e < JP * (JN / 8); e += 256) {
+    const int r = e / (JN / 8), seg = e % (JN / 8);
+    const int64_t pr = p0 + r;
+    if (pr < a.P)
+      *reinterpret_cast<bf8_t*>(&a.Jt[pr * a.ldk + n0 + seg * 8]) =
+          *reinterpret_cast<const bf8_t*>(&tile[r][seg * 8]);
+  }
 }
 
-__global__ __launch_bounds__(256) void krg_bf16_kernel(KrgArgs<float, float> a, int64_t tiles_c,
-                                                       int64_t ntiles) {
-  __shared__ __attribute__((aligned(16))) __bf16 As[BM * KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[BN * KP];
+constexpr int GB = 256, GK = 64, GKP = GK + 8;
+
+__global__ __launch_bounds__(256) void gram_bf16_kernel(const __bf16* __restrict__ Jt, int64_t P, int64_t ldk,
+                                                        int64_t nk, float scale, float* __restrict__ C,
+                                                        int64_t ldc, int64_t ntiles) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __bf16* As = reinterpret_cast<__bf16*>(smem);
+  __bf16* Bs = As + GB * GKP;
 
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
   if (t < 0) return;
-  int64_t tr, tc;
-  if (a.symmetric) {
-    int64_t r = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while (r * (r + 1) / 2 > t) --r;
-    while ((r + 1) * (r + 2) / 2 <= t) ++r;
-    tr = r;
-    tc = t - r * (r + 1) / 2;
-  } else {
-    tr = t / tiles_c;
-    tc = t % tiles_c;
-  }
-  const int64_t r0 = tr * BM, c0 = tc * BN;
+  int64_t tr = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (tr * (tr + 1) / 2 > t) --tr;
+  while ((tr + 1) * (tr + 2) / 2 <= t) ++tr;
+  const int64_t tc = t - tr * (tr + 1) / 2;
+  const int64_t r0 = tr * GB, c0 = tc * GB;
+  const bool diag = (tr == tc);
+
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
 
-  const int srow = tid & 127, sk0 = (tid >> 7) * 16;
-  const int64_t gr = r0 + srow, gc = c0 + srow;
-  const int64_t sur = gr / a.r.pad, ssr = gr % a.r.pad;
-  const int64_t suc = gc / a.c.pad, ssc = gc % a.c.pad;
-  const bool rvalid = sur < a.r.n_units && ssr < a.r.len;
-  const bool cvalid = suc < a.c.n_units && ssc < a.c.len;
-  float ra[16], rbv[16];
-
-  auto load = [&](int64_t n0) {
+  // staging: 256 rows x 8 segments of 8 bf16 per side; thread -> 8 segments per side
+  bf8_t ra[8], rb[8];
+  auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int64_t n = n0 + sk0 + i;
-      float va = 0.f, vb = 0.f;
-      if (n < a.N) {
-        if (rvalid) {
-          va = a.r.src[n * a.r.ld + ssr];
-          if (a.r.scale) va *= a.r.scale[n * a.r.ld_scale + sur];
-        }
-        if (cvalid) {
-          vb = a.c.src[n * a.c.ld + ssc];
-          if (a.c.scale) vb *= a.c.scale[n * a.c.ld_scale + suc];
-        }
-      }
-      ra[i] = va;
-      rbv[i] = vb;
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + i * 256;
+      const int row = e >> 3, seg = e & 7;
+      const int64_t gr = r0 + row, gc = c0 + row;
+      bf8_t z = {};
+      ra[i] = gr < P ? *reinterpret_cast<const bf8_t*>(&Jt[gr * ldk + k0 + seg * 8]) : z;
+      if (!diag) rb[i] = gc < P ? *reinterpret_cast<const bf8_t*>(&Jt[gc * ldk + k0 + seg * 8]) : z;
     }
   };
   auto store = [&]() {
-    bf8_t x0, x1, y0, y1;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      x0[i] = (__bf16)ra[i];
-      x1[i] = (__bf16)ra[8 + i];
-      y0[i] = (__bf16)rbv[i];
-      y1[i] = (__bf16)rbv[8 + i];
+      const int e = tid + i * 256;
+      const int row = e >> 3, seg = e & 7;
+      *reinterpret_cast<bf8_t*>(&As[row * GKP + seg * 8]) = ra[i];
+      if (!diag) *reinterpret_cast<bf8_t*>(&Bs[row * GKP + seg * 8]) = rb[i];
     }
-    *reinterpret_cast<bf8_t*>(&As[srow * KP + sk0]) = x0;
-    *reinterpret_cast<bf8_t*>(&As[srow * KP + sk0 + 8]) = x1;
-    *reinterpret_cast<bf8_t*>(&Bs[srow * KP + sk0]) = y0;
-    *reinterpret_cast<bf8_t*>(&Bs[srow * KP + sk0 + 8]) = y1;
   };
+  const __bf16* Bsrc = diag ? As : Bs;
 
-  f4_t acc[4][4];
+  f4_t acc[8][8];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 8; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
   const int row = lane & 15, q = lane >> 4;
-  const int64_t nk = (a.N + KC - 1) / KC;
   load(0);
   store();
   __syncthreads();
   for (int64_t kc = 0; kc < nk; ++kc) {
-    if (kc + 1 < nk) load((kc + 1) * KC);
-    bf8_t av[4], bv[4];
+    if (kc + 1 < nk) load((kc + 1) * GK);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) av[i] = *reinterpret_cast<const bf8_t*>(&As[(wr * 64 + i * 16 + row) * KP + 8 * q]);
+    for (int ks = 0; ks < GK / 32; ++ks) {
+      bf8_t av[8], bv[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const bf8_t*>(&Bs[(wc * 64 + j * 16 + row) * KP + 8 * q]);
+      for (int i = 0; i < 8; ++i)
+        av[i] = *reinterpret_cast<const bf8_t*>(&As[(wr * 128 + i * 16 + row) * GKP + ks * 32 + 8 * q]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 8; ++j)
+        bv[j] = *reinterpret_cast<const bf8_t*>(&Bsrc[(wc * 128 + j * 16 + row) * GKP + ks * 32 + 8 * q]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = mma_bf16(av[i], bv[j], acc[i][j]);
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = mma_bf16(av[i], bv[j], acc[i][j]);
+    }
     __syncthreads();
     if (kc + 1 < nk) {
       store();
@@ -112,44 +144,53 @@ __global__ __launch_bounds__(256) void krg_bf16_kernel(KrgArgs<float, float> a, 
     }
   }
 
-  int64_t fcol[4], ccomp[4];
-  bool cok[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t c = c0 + wc * 64 + j * 16 + row;
-    const int64_t uc = c / a.c.pad, sc = c % a.c.pad;
-    ccomp[j] = c;
-    cok[j] = uc < a.c.n_units && sc < a.c.len;
-    fcol[j] = cok[j] ? flat_index(a.c.perm, a.c.off, a.c.Tin, a.c.Tout, uc, sc) : 0;
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 8; ++i)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t r = r0 + wr * 64 + i * 16 + 4 * q + v;
-      const int64_t ur = r / a.r.pad, sr = r % a.r.pad;
-      if (!(ur < a.r.n_units && sr < a.r.len)) continue;
-      const int64_t fr = flat_index(a.r.perm, a.r.off, a.r.Tin, a.r.Tout, ur, sr);
+      const int64_t r = r0 + wr * 128 + i * 16 + 4 * q + v;
+      if (r >= P) continue;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (!cok[j]) continue;
-        if (a.symmetric && r < ccomp[j]) continue;
-        const float val = (float)(a.scale * (double)acc[i][j][v]);
-        a.out[fr * a.ldo + fcol[j]] = val;
-        if (a.mirror && !(a.symmetric && r == ccomp[j])) a.out[fcol[j] * a.ldo + fr] = val;
+      for (int j = 0; j < 8; ++j) {
+        const int64_t c = c0 + wc * 128 + j * 16 + row;
+        if (c >= P || (diag && r < c)) continue;
+        const float val = scale * acc[i][j][v];
+        C[r * ldc + c] = val;
+        if (r != c) C[c * ldc + r] = val;
       }
     }
 }
 
 }  // namespace
 
-void krg_bf16(Exec& ex, const KrgArgs<float, float>& a) {
-  const int64_t rows = (int64_t)a.r.n_units * a.r.pad, cols = (int64_t)a.c.n_units * a.c.pad;
-  const int64_t tr = (rows + BM - 1) / BM, tc = (cols + BN - 1) / BN;
-  const int64_t nt = a.symmetric ? tr * (tr + 1) / 2 : tr * tc;
+void jt_bf16(Exec& ex, const JtArgs& a) {
+  const int64_t tiles = ((a.P + JP - 1) / JP) * (a.ldk / JN);
+  if (tiles <= 0) return;
+  if (!launch_ok(ex)) return;
+  const int tok = prof_begin(ex, "jt_bf16", 2.0 * 0.5 * a.P * a.N, (double)a.P * a.ldk * 2.0);
+  hipLaunchKernelGGL(jt_bf16_kernel, dim3((unsigned)tiles), dim3(256), 0, ex.stream, a);
+  prof_end(ex, tok);
+}
+
+int64_t jt_ld(int64_t N) { return (N + GK - 1) / GK * GK; }
+
+void gram_bf16(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64_t N, float scale, float* C,
+               int64_t ldc) {
+  const int64_t tr = (P + GB - 1) / GB;
+  const int64_t nt = tr * (tr + 1) / 2;
   if (nt <= 0) return;
   if (!launch_ok(ex)) return;
-  hipLaunchKernelGGL(krg_bf16_kernel, dim3((unsigned)xcd_grid(nt)), dim3(256), 0, ex.stream, a, tc, nt);
+  const size_t shm = 2 * GB * GKP * sizeof(__bf16);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)gram_bf16_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    attr = true;
+  }
+  const double entries = (double)P * (P + 1) / 2;
+  const int tok = prof_begin(ex, "gram_bf16_sym", 2.0 * N * entries, (double)P * ldk * 2.0 + (double)P * P * 4.0);
+  hipLaunchKernelGGL(gram_bf16_kernel, dim3((unsigned)xcd_grid(nt)), dim3(256), shm, ex.stream, Jt, P, ldk,
+                     ldk / GK, scale, C, ldc, nt);
+  prof_end(ex, tok);
 }
 
 }  // namespace hs
