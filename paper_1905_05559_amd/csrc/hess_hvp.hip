@@ -1,0 +1,291 @@
+// Hessian-vector products for B dense directions (paper, Sec. 5.1 and Appendix A.1),
+// by forward-over-reverse R-operator propagation through every layer's W, b and sigma:
+//
+//   R{Z^(l)}     = R{A^(l-1)} W^(l-1)^T + Abar^(l-1) Vbar^(l-1)^T          (R{A^(1)} = 0)
+//   R{A^(l)}     = sigma'(Z^(l)) * R{Z^(l)}
+//   R{delta^(L)} = Yhat * (R{Z^(L)} - sum(Yhat * R{Z^(L)}))
+//   R{delta^(l)} = sigma''(Z^(l)) E^(l) * R{Z^(l)}
+//                  + sigma'(Z^(l)) * (R{delta^(l+1)} W^(l) + delta^(l+1) V_W^(l))
+//   (HV)_{Wbar^(l-1)} = (1/N) [ R{delta^(l)}^T Abar^(l-1) + delta^(l)^T R{A^(l-1)} ]
+//
+// (Vbar = [V_W | V_b]; the ones column of Abar turns the weight formula into the bias
+// one.)  R tensors are laid out [n][b][unit] so the W products are plain GEMMs over
+// (n, b) rows and the direction-dependent products are GEMMs batched over b.  The
+// example range is processed in chunks to bound the workspace; the accumulation over
+// chunks is the sum over n of the definition.
+#include <algorithm>
+#include <cmath>
+
+#include "api_internal.h"
+#include "mfma.h"
+
+namespace hs {
+
+namespace {
+
+constexpr int TPB = 256;
+inline unsigned grid_for(int64_t n) {
+  int64_t g = (n + TPB - 1) / TPB;
+  if (g > (1 << 20)) g = 1 << 20;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+// Vbar[(b, i)][j] = V[b][offW + i*Tin + j] (j < Tin), V[b][offb + i] (j == Tin)
+template <typename T>
+__global__ void k_pack_vbar(const T* V, int64_t B, int64_t P, int64_t offW, int64_t offb, int64_t Tout,
+                            int64_t Tin, T* Vbar) {
+  GRID_STRIDE(e, B * Tout * (Tin + 1)) {
+    const int64_t j = e % (Tin + 1), bi = e / (Tin + 1), i = bi % Tout, b = bi / Tout;
+    Vbar[e] = V[b * P + (j < Tin ? offW + i * Tin + j : offb + i)];
+  }
+}
+
+template <typename T>
+__global__ void k_unpack_hv(const T* HVbar, int64_t B, int64_t P, int64_t offW, int64_t offb, int64_t Tout,
+                            int64_t Tin, T* HV) {
+  GRID_STRIDE(e, B * Tout * (Tin + 1)) {
+    const int64_t j = e % (Tin + 1), bi = e / (Tin + 1), i = bi % Tout, b = bi / Tout;
+    HV[b * P + (j < Tin ? offW + i * Tin + j : offb + i)] = HVbar[e];
+  }
+}
+
+// RA[n][b][t] = D1[n][t] * RZ[n][b][t]
+template <typename T>
+__global__ void k_ra(const T* RZ, const T* D1, int64_t Nc, int64_t B, int64_t Tl, T* RA) {
+  GRID_STRIDE(e, Nc * B * Tl) {
+    const int64_t t = e % Tl, n = e / (B * Tl);
+    RA[e] = D1[n * Tl + t] * RZ[e];
+  }
+}
+
+// RD[n][b][:] = Yhat[n] * (RZ[n][b][:] - sum_t Yhat[n][t] RZ[n][b][t]), one thread per (n, b)
+template <typename T>
+__global__ void k_ryhat(const T* RZ, const T* Yh, int64_t Nc, int64_t B, int64_t TL, T* RD) {
+  GRID_STRIDE(e, Nc * B) {
+    const int64_t n = e / B;
+    const T* z = RZ + e * TL;
+    const T* p = Yh + n * TL;
+    T s = 0;
+    for (int64_t t = 0; t < TL; ++t) s += p[t] * z[t];
+    for (int64_t t = 0; t < TL; ++t) RD[e * TL + t] = p[t] * (z[t] - s);
+  }
+}
+
+// RD[n][b][t] = D1[n][t] * RD[n][b][t] + CE[n][t] * RZ[n][b][t]
+template <typename T>
+__global__ void k_rdelta(T* RD, const T* RZ, const T* D1, const T* CE, int64_t Nc, int64_t B, int64_t Tl) {
+  GRID_STRIDE(e, Nc * B * Tl) {
+    const int64_t t = e % Tl, n = e / (B * Tl);
+    RD[e] = D1[n * Tl + t] * RD[e] + CE[n * Tl + t] * RZ[e];
+  }
+}
+
+#define LAUNCH(kernel, n, ...)                                                                 \
+  do {                                                                                         \
+    if (!launch_ok(ex)) return;                                                                \
+    hipLaunchKernelGGL(kernel, dim3(grid_for(n)), dim3(TPB), 0, ex.stream, __VA_ARGS__);       \
+  } while (0)
+
+template <typename T>
+struct HvpBufs {
+  std::vector<T*> abar, delta, D1, CE, W, Vbar, HVbar, RZ, RA, RD;
+  T* Yhat = nullptr;
+  int64_t Nc = 0;
+};
+
+int64_t hvp_chunk(const Model& m, int64_t N, int64_t B, size_t esz) {
+  int64_t sumT = 0;
+  for (int l = 2; l <= m.L; ++l) sumT += m.T[l - 1];
+  const double budget = 6.0e9;  // bytes of R tensors per chunk
+  int64_t nc = (int64_t)(budget / ((double)B * sumT * 3.0 * esz));
+  nc = std::max<int64_t>(64, nc / 64 * 64);
+  return std::min(N, nc);
+}
+
+template <typename T>
+size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h) {
+  const int L = m.L;
+  plan_prep(ar, m, N, p, false);
+  h.abar.assign(L + 1, nullptr);
+  h.delta.assign(L + 1, nullptr);
+  h.D1.assign(L + 1, nullptr);
+  h.CE.assign(L + 1, nullptr);
+  h.W.assign(L + 1, nullptr);
+  h.Vbar.assign(L + 1, nullptr);
+  h.HVbar.assign(L + 1, nullptr);
+  h.RZ.assign(L + 1, nullptr);
+  h.RA.assign(L + 1, nullptr);
+  h.RD.assign(L + 1, nullptr);
+  const bool same = sizeof(T) == 8;
+  for (int l = 1; l <= L - 1; ++l) h.abar[l] = same ? nullptr : ar.take<T>(N * p.lda[l]);
+  for (int l = 2; l <= L; ++l) h.delta[l] = same ? nullptr : ar.take<T>(N * m.T[l - 1]);
+  for (int l = 2; l <= L - 1; ++l) {
+    h.D1[l] = same ? nullptr : ar.take<T>(N * m.T[l - 1]);
+    h.CE[l] = ar.take<T>(N * m.T[l - 1]);
+  }
+  h.Yhat = same ? nullptr : ar.take<T>(N * m.T[L - 1]);
+  for (int l = 2; l <= L; ++l) {
+    h.W[l] = same ? nullptr : ar.take<T>(m.T[l - 1] * m.T[l - 2]);
+    h.Vbar[l] = ar.take<T>(B * m.T[l - 1] * (m.T[l - 2] + 1));
+    h.HVbar[l] = ar.take<T>(B * m.T[l - 1] * (m.T[l - 2] + 1));
+  }
+  h.Nc = hvp_chunk(m, N, B, sizeof(T));
+  for (int l = 2; l <= L; ++l) {
+    h.RZ[l] = ar.take<T>(h.Nc * B * m.T[l - 1]);
+    h.RD[l] = ar.take<T>(h.Nc * B * m.T[l - 1]);
+    if (l < L) h.RA[l] = ar.take<T>(h.Nc * B * m.T[l - 1]);
+  }
+  return ar.used;
+}
+
+template <typename T>
+void run_hvp(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, const T* V, T* HV) {
+  const int L = m.L;
+  const bool same = sizeof(T) == 8;
+  // operands in the arithmetic precision
+  for (int l = 1; l <= L - 1; ++l) {
+    if (same)
+      h.abar[l] = reinterpret_cast<T*>(p.Abar[l]);
+    else
+      cast_copy<T>(ex, p.Abar[l], h.abar[l], N * p.lda[l]);
+  }
+  for (int l = 2; l <= L; ++l) {
+    if (same)
+      h.delta[l] = reinterpret_cast<T*>(p.delta[l]);
+    else
+      cast_copy<T>(ex, p.delta[l], h.delta[l], N * m.T[l - 1]);
+  }
+  for (int l = 2; l <= L - 1; ++l) {
+    const int64_t n = N * m.T[l - 1];
+    mul(ex, p.D2[l], p.E[l], p.Z, n);  // sigma'' E in FP64, then cast
+    cast_copy<T>(ex, p.Z, h.CE[l], n);
+    if (same)
+      h.D1[l] = reinterpret_cast<T*>(p.D1[l]);
+    else
+      cast_copy<T>(ex, p.D1[l], h.D1[l], n);
+  }
+  if (same)
+    h.Yhat = reinterpret_cast<T*>(p.Yhat);
+  else
+    cast_copy<T>(ex, p.Yhat, h.Yhat, N * m.T[L - 1]);
+  for (int l = 2; l <= L; ++l) {
+    const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
+    if (same)
+      h.W[l] = reinterpret_cast<T*>(p.W64[l - 2]);
+    else
+      cast_copy<T>(ex, p.W64[l - 2], h.W[l], Tl * Tin);
+    LAUNCH(k_pack_vbar<T>, B * Tl * (Tin + 1), V, B, m.P, m.offW[l - 2], m.offb[l - 2], Tl, Tin, h.Vbar[l]);
+  }
+
+  const T invN = (T)(1.0 / (double)N);
+  for (int64_t n0 = 0; n0 < N; n0 += h.Nc) {
+    const int64_t Nc = std::min(h.Nc, N - n0);
+    const T beta_acc = n0 == 0 ? T(0) : T(1);
+    // ---- R-forward
+    for (int l = 2; l <= L; ++l) {
+      const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
+      // R{Z^(l)} = Abar^(l-1) Vbar^T  (N_c x (B T_l)) ...
+      gemm_rm<T>(ex, false, true, Nc, B * Tl, Tin + 1, T(1), h.abar[l - 1] + n0 * p.lda[l - 1], p.lda[l - 1],
+                 h.Vbar[l], Tin + 1, T(0), h.RZ[l], B * Tl);
+      // ... + R{A^(l-1)} W^(l-1)^T  ((N_c B) x T_l)
+      if (l >= 3)
+        gemm_rm<T>(ex, false, true, Nc * B, Tl, Tin, T(1), h.RA[l - 1], Tin, h.W[l], Tin, T(1), h.RZ[l], Tl);
+      if (l < L) LAUNCH(k_ra<T>, Nc * B * Tl, h.RZ[l], h.D1[l] + n0 * Tl, Nc, B, Tl, h.RA[l]);
+    }
+    // ---- R-backward
+    LAUNCH(k_ryhat<T>, Nc * B, h.RZ[L], h.Yhat + n0 * m.T[L - 1], Nc, B, m.T[L - 1], h.RD[L]);
+    for (int l = L - 1; l >= 2; --l) {
+      const int64_t Tl = m.T[l - 1], Tn = m.T[l];
+      // R{delta^(l+1)} W^(l)   ((N_c B) x T_l)
+      gemm_rm<T>(ex, false, false, Nc * B, Tl, Tn, T(1), h.RD[l + 1], Tn, h.W[l + 1], Tl, T(0), h.RD[l], Tl);
+      // + delta^(l+1) V_W^(l)_b, batched over directions b
+      GemmArgs<T> g;
+      g.M = Nc; g.N = Tl; g.K = Tn;
+      g.A = h.delta[l + 1] + n0 * Tn; g.sam = Tn; g.sak = 1; g.sab = 0;
+      g.B = h.Vbar[l + 1]; g.sbk = Tl + 1; g.sbn = 1; g.sbb = Tn * (Tl + 1);
+      g.C = h.RD[l]; g.scm = B * Tl; g.scn = 1; g.scb = Tl;
+      g.alpha = T(1); g.beta = T(1); g.batch = B;
+      gemm<T>(ex, g);
+      LAUNCH(k_rdelta<T>, Nc * B * Tl, h.RD[l], h.RZ[l], h.D1[l] + n0 * Tl, h.CE[l] + n0 * Tl, Nc, B, Tl);
+    }
+    // ---- accumulation over the examples of this chunk
+    for (int l = 2; l <= L; ++l) {
+      const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
+      // R{delta^(l)}^T Abar^(l-1): ((B T_l) x (T_in + 1)), contraction over n
+      gemm_rm<T>(ex, true, false, B * Tl, Tin + 1, Nc, invN, h.RD[l], B * Tl, h.abar[l - 1] + n0 * p.lda[l - 1],
+                 p.lda[l - 1], beta_acc, h.HVbar[l], Tin + 1);
+      if (l >= 3) {
+        // + delta^(l)^T R{A^(l-1)}_b, batched over b, into the weight columns
+        GemmArgs<T> g;
+        g.M = Tl; g.N = Tin; g.K = Nc;
+        g.A = h.delta[l] + n0 * Tl; g.sam = 1; g.sak = Tl; g.sab = 0;
+        g.B = h.RA[l - 1]; g.sbk = B * Tin; g.sbn = 1; g.sbb = Tin;
+        g.C = h.HVbar[l]; g.scm = Tin + 1; g.scn = 1; g.scb = Tl * (Tin + 1);
+        g.alpha = invN; g.beta = T(1); g.batch = B;
+        gemm<T>(ex, g);
+      }
+    }
+  }
+  for (int l = 2; l <= L; ++l) {
+    const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
+    LAUNCH(k_unpack_hv<T>, B * Tl * (Tin + 1), h.HVbar[l], B, m.P, m.offW[l - 2], m.offb[l - 2], Tl, Tin, HV);
+  }
+}
+
+size_t ws_hvp(const Model& m, int64_t N, int prec, int64_t B) {
+  Arena ar(nullptr);
+  Prep p;
+  if (prec == HESS_P_F64) {
+    HvpBufs<double> h;
+    return plan_hvp<double>(ar, m, N, B, p, h);
+  }
+  HvpBufs<float> h;
+  return plan_hvp<float>(ar, m, N, B, p, h);
+}
+
+}  // namespace
+
+hess_status hvp_workspace(hess_ctx* ctx, const Model& m, int64_t N, int prec, int64_t B, size_t* bytes) {
+  if (prec != HESS_P_F64 && prec != HESS_P_F32) return fail(ctx, HESS_E_UNSUPPORTED, "HVP: F64 or F32 only");
+  if (B < 1 || B > 65535) return fail(ctx, HESS_E_SHAPE, "B out of range (1..65535)");
+  *bytes = ws_hvp(m, N, prec, B);
+  return HESS_OK;
+}
+
+}  // namespace hs
+
+using namespace hs;
+
+extern "C" hess_status hess_hvp(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int prec, int64_t B,
+                                const void* V, void* HV, void* ws, size_t ws_bytes) {
+  Exec ex;
+  hess_status s = begin(ctx, ex);
+  if (s != HESS_OK) return s;
+  Model m;
+  if ((s = validate_mlp(ctx, mlp, m, true)) != HESS_OK) return s;
+  if ((s = validate_data(ctx, d, true)) != HESS_OK) return s;
+  if (prec != HESS_P_F64 && prec != HESS_P_F32) return fail(ctx, HESS_E_UNSUPPORTED, "HVP: F64 or F32 only");
+  if (B < 1 || B > 65535) return fail(ctx, HESS_E_SHAPE, "B out of range (1..65535)");
+  if (!V || !HV) return fail(ctx, HESS_E_ARG, "V or HV is NULL");
+  const size_t need = ws_hvp(m, d->N, prec, B);
+  if ((s = check_ws(ctx, need, ws, ws_bytes, (size_t)B * m.P * (prec == HESS_P_F64 ? 16 : 8))) != HESS_OK)
+    return s;
+  Arena ar(ws);
+  Prep p;
+  if (prec == HESS_P_F64) {
+    HvpBufs<double> h;
+    plan_hvp<double>(ar, m, d->N, B, p, h);
+    if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
+    run_prep(ex, m, d, p, false);
+    run_hvp<double>(ex, m, d->N, B, p, h, static_cast<const double*>(V), static_cast<double*>(HV));
+  } else {
+    HvpBufs<float> h;
+    plan_hvp<float>(ar, m, d->N, B, p, h);
+    if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
+    run_prep(ex, m, d, p, false);
+    run_hvp<float>(ex, m, d->N, B, p, h, static_cast<const float*>(V), static_cast<float*>(HV));
+  }
+  return finish(ex, "hess_hvp");
+}

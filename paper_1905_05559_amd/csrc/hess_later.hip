@@ -2,9 +2,6 @@
 #include "api_internal.h"
 
 namespace hs {
-hess_status hvp_workspace(hess_ctx* ctx, const Model&, int64_t, int, int64_t, size_t*) {
-  return fail(ctx, HESS_E_UNSUPPORTED, "hess_hvp not built yet");
-}
 hess_status topk_workspace(hess_ctx* ctx, const hess_mlp*, const hess_data*, int64_t, const hess_eig_opts*,
                            size_t*) {
   return fail(ctx, HESS_E_UNSUPPORTED, "hess_topk_eig not built yet");
@@ -15,10 +12,6 @@ hess_status predvar_workspace(hess_ctx* ctx, const Model&, int, int64_t, size_t*
 }  // namespace hs
 
 extern "C" {
-hess_status hess_hvp(hess_ctx* ctx, const hess_mlp*, const hess_data*, int, int64_t, const void*, void*, void*,
-                     size_t) {
-  return hs::fail(ctx, HESS_E_UNSUPPORTED, "hess_hvp not built yet");
-}
 hess_status hess_topk_eig(hess_ctx* ctx, const hess_mlp*, const hess_data*, int64_t, const hess_eig_opts*,
                           double*, double*, hess_eig_info*, void*, size_t) {
   return hs::fail(ctx, HESS_E_UNSUPPORTED, "hess_topk_eig not built yet");

@@ -148,3 +148,51 @@ def test_run_twice_bitwise(api):
     a = api.hess_exact(model, X, Y, "f32").cpu()
     b = api.hess_exact(model, X, Y, "f32").cpu()
     assert torch.equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# Dense Hessian-vector products (R-operator, Appendix A.1).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("T,acts,N,seed", SMALL)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_small_hvp(api, T, acts, N, seed, prec):
+    print("hvp case T=%s N=%d prec=%s" % (T, N, prec), flush=True)
+    w = workloads.mlp_gaussian(T, acts, N, seed, dtype="float64" if prec == "f64" else "float32")
+    model, X, Y = to_dev(api, w, w.dtype)
+    om, Xo, Yo = oracle_of(w)
+    P = mlp.num_params(T)
+    for B in (1, 5):
+        V = workloads.gaussian_directions(B, P, seed + B, dtype=w.dtype)
+        ref = mlp.hvp(om, Xo, Yo, V.astype(np.float64))
+        HV = api.hess_hvp(model, X, Y, torch.from_numpy(V).cuda(), prec).double().cpu().numpy()
+        assert report("HV %s B=%d %s" % (T, B, prec), HV, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_sigmoid64_hvp(api, sig64, prec):
+    w, om, Xo, Yo, _ = sig64
+    td = torch.float64 if prec == "f64" else torch.float32
+    model = api.MLP.from_workload(w, dtype=td)
+    X = torch.from_numpy(w.X).to("cuda", td)
+    Y = torch.from_numpy(w.Y).to("cuda", td)
+    V = workloads.gaussian_directions(8, w.P, 77, dtype="float64")
+    ref = mlp.hvp(om, Xo, Yo, V)
+    HV = api.hess_hvp(model, X, Y, torch.from_numpy(V).to("cuda", td), prec).double().cpu().numpy()
+    assert report("sigmoid64 HV B=8 %s" % prec, HV, ref) <= TOL[prec]
+
+
+def test_hvp_basis_equals_exact_columns(api):
+    """H e_j from the dense R-operator path equals column j of the assembled H."""
+    w = workloads.mlp_gaussian([6, 9, 7, 8, 4], ["tanh", "sigmoid", "tanh"], 70, 7, dtype="float64")
+    model, X, Y = to_dev(api, w, "float64")
+    P = w.P
+    H = api.hess_exact(model, X, Y, "f64")
+    cols = [0, 5, 53, 54, 60, P - 1]
+    V = torch.zeros((len(cols), P), dtype=torch.float64, device="cuda")
+    for k, c in enumerate(cols):
+        V[k, c] = 1.0
+    HV = api.hess_hvp(model, X, Y, V, "f64")
+    err = (HV - H[:, cols].T).abs().max().item() / H.abs().max().item()
+    print("basis HVP vs exact columns: rel max err %.3e" % err, flush=True)
+    assert err < 1e-12
