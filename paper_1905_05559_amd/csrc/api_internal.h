@@ -41,9 +41,34 @@ hess_status validate_data(hess_ctx* ctx, const hess_data* d, bool need_ptrs);
 void plan_prep(Arena& ar, const Model& m, int64_t N, Prep& p, bool want_transposes);
 hess_status check_inputs(Exec& ex, const Model& m, const hess_data* d, Prep& p);
 void run_prep(Exec& ex, const Model& m, const hess_data* d, Prep& p, bool want_transposes);
+void run_forward(Exec& ex, const Model& m, const void* X, int xdtype, Prep& p);
+void run_backward(Exec& ex, const Model& m, Prep& p);
 hess_status finish(Exec& ex, const char* what);
 hess_status begin(hess_ctx* ctx, Exec& ex);
 hess_status check_ws(hess_ctx* ctx, size_t need, void* ws, size_t ws_bytes, size_t out_bytes);
+
+// Buffers of the R-operator (dense-direction) passes; see hess_hvp.hip.
+template <typename T>
+struct HvpBufs {
+  std::vector<T*> abar, delta, D1, CE, W, Vbar, HVbar, RZ, RA, RD;
+  T* Yhat = nullptr;
+  T* S = nullptr;
+  int64_t Nc = 0, Bmax = 0;
+};
+template <typename T>
+size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h);
+template <typename T>
+void hvp_setup(Exec& ex, const Model& m, int64_t N, Prep& p, HvpBufs<T>& h);
+template <typename T>
+void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, const T* V, int64_t ldv,
+               T* HV);
+template <typename T>
+void opg_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, const T* V, int64_t ldv,
+               T* GV);
+// JV[n][b] = (J v_b)_n = grad C_n . v_b for the per-example gradients held in the buffers.
+template <typename T>
+void jv_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, const T* V, int64_t ldv,
+              T* JV);
 
 // Workspace queries of the other translation units.
 hess_status hvp_workspace(hess_ctx* ctx, const Model& m, int64_t N, int prec, int64_t B, size_t* bytes);

@@ -198,7 +198,39 @@ hess_status check_inputs(Exec& ex, const Model& m, const hess_data* d, Prep& p) 
   return HESS_OK;
 }
 
-// Forward pass (Sec. 2 model function) and per-example backprop.
+// Forward pass (Sec. 2 model function): Abar, sigma', sigma'' per hidden layer and the
+// softmax output Yhat; the output pre-activations Z^(L) are left in p.Z.
+void run_forward(Exec& ex, const Model& m, const void* X, int xdtype, Prep& p) {
+  const int L = m.L;
+  const int64_t N = p.N;
+  const int64_t T1 = m.T[0];
+  to_f64_rows(ex, X, xdtype, N, T1, T1, p.Abar[1], p.lda[1], 1);
+  for (int k = 0; k < L - 1; ++k) {
+    to_f64_rows(ex, m.W[k], m.dtype, m.T[k + 1], m.T[k], m.T[k], p.W64[k], m.T[k], 0);
+    make_wbar(ex, m.W[k], m.b[k], m.dtype, m.T[k + 1], m.T[k], p.Wbar[k]);
+  }
+  for (int l = 2; l <= L; ++l) {
+    const int64_t Tin = m.T[l - 2], Tl = m.T[l - 1];
+    gemm_rm<double>(ex, false, true, N, Tl, Tin + 1, 1.0, p.Abar[l - 1], p.lda[l - 1], p.Wbar[l - 2],
+                    Tin + 1, 0.0, p.Z, Tl);
+    if (l < L)
+      activate(ex, m.act[l - 2], p.Z, N, Tl, p.Abar[l], p.lda[l], p.D1[l], p.D2[l]);
+    else
+      softmax_rows(ex, p.Z, N, Tl, p.Yhat);
+  }
+}
+
+// Per-example backprop from a given delta^(L): E^(l) = delta^(l+1) W^(l), delta^(l) = sigma' E^(l).
+void run_backward(Exec& ex, const Model& m, Prep& p) {
+  const int64_t N = p.N;
+  for (int l = m.L - 1; l >= 2; --l) {
+    gemm_rm<double>(ex, false, false, N, m.T[l - 1], m.T[l], 1.0, p.delta[l + 1], m.T[l], p.W64[l - 1],
+                    m.T[l - 1], 0.0, p.E[l], m.T[l - 1]);
+    mul(ex, p.D1[l], p.E[l], p.delta[l], N * m.T[l - 1]);
+  }
+}
+
+// Forward pass and per-example backprop of the cost (delta^(L) = Yhat - Y).
 void run_prep(Exec& ex, const Model& m, const hess_data* d, Prep& p, bool want_transposes) {
   const int L = m.L;
   const int64_t N = p.N;

@@ -1,0 +1,646 @@
+// Leading (algebraically largest) eigenpairs of H or of the OPG (paper, Sec. 4.1,
+// 5.3, 5.4): randomized block subspace iteration accelerated by a Chebyshev
+// polynomial filter, with FP64 re-orthogonalisation (shifted Cholesky-QR, three
+// passes) and FP64 Rayleigh-Ritz (cyclic Jacobi on the b x b projected matrix).
+//
+// The paper asks the Lanczos solver for which='LA' and sorts the pairs in
+// descending order; H is indefinite away from a minimum, so plain power-type
+// subspace iteration (which converges to the largest |lambda|) would answer a
+// different question.  The filter T_d((x - c) / e) with c, e mapping
+// [lambda_lb, a] onto [-1, 1] is bounded by 1 on that interval and grows quickly
+// above the cut a (the smallest Ritz value of the block), so the block converges
+// to the algebraically largest eigenvalues.  lambda_lb is a lower bound of the
+// spectrum from the spectral radius estimated by a few unfiltered block steps.
+//
+// Block vectors are stored b x Ppad (row k = vector k, zero-padded columns) in FP64.
+// The operator is applied in its own precision: a dense M (FP64 or FP32) through the
+// MFMA GEMM, or the matrix-free H (R-operator) or OPG (J^T J v / N) products.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "api_internal.h"
+#include "mfma.h"
+
+namespace hs {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int BMAX = 128;     // largest block size (Jacobi and Cholesky run in LDS)
+constexpr int64_t KSPLIT = 4096;  // columns per split of the b x b Gram products
+
+inline unsigned grid_for(int64_t n) {
+  int64_t g = (n + TPB - 1) / TPB;
+  if (g > (1 << 20)) g = 1 << 20;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+#define LAUNCH(kernel, n, ...)                                                                 \
+  do {                                                                                         \
+    if (!launch_ok(ex)) return;                                                                \
+    hipLaunchKernelGGL(kernel, dim3(grid_for(n)), dim3(TPB), 0, ex.stream, __VA_ARGS__);       \
+  } while (0)
+
+// SplitMix64 finaliser (Steele, Lea & Flood, 2014) used as a counter-based generator.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// Q[k][p] ~ N(0, 1) by Box-Muller on two counter-derived uniforms; zero in the padding.
+__global__ void k_randn(uint64_t seed, int64_t b, int64_t P, int64_t ldp, double* Q) {
+  GRID_STRIDE(e, b * ldp) {
+    const int64_t k = e / ldp, p = e % ldp;
+    if (p >= P) {
+      Q[e] = 0.0;
+      continue;
+    }
+    const uint64_t c = (uint64_t)(k * P + p);
+    const uint64_t h1 = splitmix64(seed ^ splitmix64(2 * c));
+    const uint64_t h2 = splitmix64(seed ^ splitmix64(2 * c + 1));
+    const double u1 = ((double)(h1 >> 11) + 1.0) * 0x1.0p-53;
+    const double u2 = (double)(h2 >> 11) * 0x1.0p-53;
+    Q[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  }
+}
+
+__global__ void k_fill(double* x, int64_t n, double v) {
+  GRID_STRIDE(i, n) { x[i] = v; }
+}
+
+__global__ void k_f32_to_f64_2d(const float* src, int64_t rows, int64_t cols, int64_t lds, double* dst,
+                                int64_t ldd) {
+  GRID_STRIDE(i, rows * cols) {
+    const int64_t r = i / cols, c = i % cols;
+    dst[r * ldd + c] = (double)src[r * lds + c];
+  }
+}
+
+// out[i] = sum_s part[s * n + i], summed in split order (deterministic)
+__global__ void k_sum_splits(const double* part, int64_t S, int64_t n, double* out) {
+  GRID_STRIDE(i, n) {
+    double s = 0.0;
+    for (int64_t k = 0; k < S; ++k) s += part[k * n + i];
+    out[i] = s;
+  }
+}
+
+// out = alpha * A + beta * B + gamma * C  (elementwise)
+__global__ void k_axpbypcz(double alpha, const double* A, double beta, const double* B, double gamma,
+                           const double* C, int64_t n, double* out) {
+  GRID_STRIDE(i, n) {
+    double v = alpha * A[i] + beta * B[i];
+    if (C) v += gamma * C[i];
+    out[i] = v;
+  }
+}
+
+// W = L L^T (b x b, b <= BMAX) with an optional diagonal shift; writes L^{-1} (lower).
+// shift_mode 1 adds 11 (P b + b (b + 1)) u trace(W) to the diagonal (shifted
+// Cholesky-QR, Fukaya et al. 2020).  info[0] = 1 on a non-positive pivot.
+__global__ __launch_bounds__(256) void k_chol_inv(const double* W, int b, int64_t P, int shift_mode,
+                                                  double* Linv, int* info) {
+  extern __shared__ double As[];  // b x (b + 1)
+  const int ld = b + 1, tid = threadIdx.x;
+  __shared__ double trace;
+  __shared__ int bad;
+  for (int e = tid; e < b * b; e += blockDim.x) As[(e / b) * ld + e % b] = W[e];
+  if (tid == 0) {
+    double t = 0.0;
+    for (int i = 0; i < b; ++i) t += W[i * b + i];
+    trace = t;
+    bad = 0;
+  }
+  __syncthreads();
+  if (shift_mode) {
+    const double s = 11.0 * ((double)P * b + (double)b * (b + 1)) * 1.1102230246251565e-16 * trace;
+    for (int i = tid; i < b; i += blockDim.x) As[i * ld + i] += s;
+  }
+  __syncthreads();
+  for (int j = 0; j < b; ++j) {
+    if (tid == 0) {
+      const double d = As[j * ld + j];
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = 1;
+        As[j * ld + j] = 1.0;
+      } else {
+        As[j * ld + j] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double piv = As[j * ld + j];
+    for (int i = j + 1 + tid; i < b; i += blockDim.x) As[i * ld + j] /= piv;
+    __syncthreads();
+    const int n = b - j - 1;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+      const int i = j + 1 + e / n, k = j + 1 + e % n;
+      if (k <= i) As[i * ld + k] -= As[i * ld + j] * As[k * ld + j];
+    }
+    __syncthreads();
+  }
+  // column c of L^{-1} by forward substitution (one thread per column)
+  for (int c = tid; c < b; c += blockDim.x) {
+    for (int i = 0; i < c; ++i) Linv[i * b + c] = 0.0;
+    for (int i = c; i < b; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= As[i * ld + k] * Linv[k * b + c];
+      Linv[i * b + c] = s / As[i * ld + i];
+    }
+  }
+  if (tid == 0 && bad) info[0] = 1;
+}
+
+// Cyclic Jacobi for the symmetric b x b matrix (T + T^T) / 2 with round-robin parallel
+// ordering; eigenvalues sorted descending in ev, eigenvectors in the columns of U.
+__global__ __launch_bounds__(256) void k_jacobi(const double* Tm, int b, int max_sweeps, double* ev, double* U,
+                                                int* sweeps_out) {
+  extern __shared__ double A[];  // n x (n + 1), n = b rounded up to even
+  __shared__ double red[256];
+  __shared__ double cs[BMAX / 2][2];
+  __shared__ int pr[BMAX / 2][2];
+  __shared__ int perm[BMAX];
+  const int n = (b + 1) & ~1, ld = n + 1, tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    double v = 0.0;
+    if (i < b && j < b) v = 0.5 * (Tm[i * b + j] + Tm[j * b + i]);
+    A[i * ld + j] = v;
+  }
+  for (int e = tid; e < b * b; e += blockDim.x) U[e] = (e / b == e % b) ? 1.0 : 0.0;
+  __syncthreads();
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < b * b; e += blockDim.x) {
+      const int i = e / b, j = e % b;
+      const double v = A[i * ld + j] * A[i * ld + j];
+      tot += v;
+      if (i != j) off += v;
+    }
+    red[tid] = off;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    const double offs = red[0];
+    __syncthreads();
+    red[tid] = tot;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    const double tots = red[0];
+    __syncthreads();
+    if (offs <= 1e-30 * tots || tots == 0.0) break;
+    for (int r = 0; r < n - 1; ++r) {
+      const int np = n / 2;
+      if (tid < np) {
+        int p, q;
+        if (tid == 0) {
+          p = r;
+          q = n - 1;
+        } else {
+          p = (r + tid) % (n - 1);
+          q = (r - tid + n - 1) % (n - 1);
+        }
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double c = 1.0, s = 0.0;
+        if (q < b) {
+          const double apq = A[p * ld + q];
+          if (apq != 0.0) {
+            const double tau = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
+            const double t = tau >= 0.0 ? 1.0 / (tau + sqrt(1.0 + tau * tau)) : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        pr[tid][0] = p;
+        pr[tid][1] = q;
+        cs[tid][0] = c;
+        cs[tid][1] = s;
+      }
+      __syncthreads();
+      // rows p, q  <-  J^T A
+      for (int e = tid; e < np * n; e += blockDim.x) {
+        const int k = e / n, j = e % n;
+        const int p = pr[k][0], q = pr[k][1];
+        const double c = cs[k][0], s = cs[k][1];
+        const double apj = A[p * ld + j], aqj = A[q * ld + j];
+        A[p * ld + j] = c * apj - s * aqj;
+        A[q * ld + j] = s * apj + c * aqj;
+      }
+      __syncthreads();
+      // columns p, q  <-  A J ; U <- U J
+      for (int e = tid; e < np * n; e += blockDim.x) {
+        const int k = e / n, i = e % n;
+        const int p = pr[k][0], q = pr[k][1];
+        const double c = cs[k][0], s = cs[k][1];
+        const double aip = A[i * ld + p], aiq = A[i * ld + q];
+        A[i * ld + p] = c * aip - s * aiq;
+        A[i * ld + q] = s * aip + c * aiq;
+        if (i < b && q < b) {
+          const double uip = U[i * b + p], uiq = U[i * b + q];
+          U[i * b + p] = c * uip - s * uiq;
+          U[i * b + q] = s * uip + c * uiq;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // sort descending (stable: lower index first on ties)
+  if (tid == 0) {
+    for (int i = 0; i < b; ++i) perm[i] = i;
+    for (int i = 0; i < b; ++i) {
+      int best = i;
+      for (int j = i + 1; j < b; ++j)
+        if (A[perm[j] * ld + perm[j]] > A[perm[best] * ld + perm[best]]) best = j;
+      const int t = perm[i];
+      perm[i] = perm[best];
+      perm[best] = t;
+    }
+    *sweeps_out = sweep;
+  }
+  __syncthreads();
+  for (int i = tid; i < b; i += blockDim.x) ev[i] = A[perm[i] * ld + perm[i]];
+  // permute columns of U through the LDS matrix (A no longer needed)
+  __syncthreads();
+  for (int e = tid; e < b * b; e += blockDim.x) A[(e / b) * ld + e % b] = U[e];
+  __syncthreads();
+  for (int e = tid; e < b * b; e += blockDim.x) {
+    const int i = e / b, j = e % b;
+    U[e] = A[i * ld + perm[j]];
+  }
+}
+
+// res[k] = || MX[k] - theta[k] X[k] ||_2, one workgroup per row
+__global__ __launch_bounds__(256) void k_resid(const double* MX, const double* X, const double* theta, int64_t P,
+                                               int64_t ldp, double* res) {
+  __shared__ double red[256];
+  const int64_t k = blockIdx.x;
+  const double th = theta[k];
+  double s = 0.0;
+  for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
+    const double r = MX[k * ldp + p] - th * X[k * ldp + p];
+    s += r * r;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) res[k] = sqrt(red[0]);
+}
+
+// Flip row k so that its largest-|.| entry (lowest index on ties) is positive; copy to out.
+__global__ __launch_bounds__(256) void k_sign_copy(const double* X, int64_t P, int64_t ldp, double* out) {
+  __shared__ double vmax[256];
+  __shared__ int64_t imax[256];
+  const int64_t k = blockIdx.x;
+  double best = -1.0;
+  int64_t bi = P;
+  for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
+    const double a = fabs(X[k * ldp + p]);
+    if (a > best) {
+      best = a;
+      bi = p;
+    }
+  }
+  vmax[threadIdx.x] = best;
+  imax[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double o = vmax[threadIdx.x + w];
+      const int64_t oi = imax[threadIdx.x + w];
+      if (o > vmax[threadIdx.x] || (o == vmax[threadIdx.x] && oi < imax[threadIdx.x])) {
+        vmax[threadIdx.x] = o;
+        imax[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const double sg = (imax[0] < P && X[k * ldp + imax[0]] < 0.0) ? -1.0 : 1.0;
+  for (int64_t p = threadIdx.x; p < P; p += blockDim.x) out[k * P + p] = sg * X[k * ldp + p];
+}
+
+struct EigBufs {
+  int64_t b = 0, P = 0, ldp = 0, S = 0;
+  double *Q, *Y, *Yp, *Z, *MQ, *X, *MX;
+  float *Qf, *Yf;
+  double *part, *W, *Linv, *T, *U, *theta, *res;
+  int* info;
+  Prep p;
+  HvpBufs<double> hd;
+  HvpBufs<float> hf;
+};
+
+}  // namespace
+
+static size_t plan_eig(Arena& ar, const Model* m, int64_t N, int64_t P, int64_t b, int source, int prec,
+                       EigBufs& e) {
+  e.b = b;
+  e.P = P;
+  e.ldp = rup(P, KSPLIT);
+  e.S = e.ldp / KSPLIT;
+  const int64_t nb = b * e.ldp;
+  for (double** x : {&e.Q, &e.Y, &e.Yp, &e.Z, &e.MQ, &e.X, &e.MX}) *x = ar.take<double>(nb);
+  e.Qf = ar.take<float>(b * P);
+  e.Yf = ar.take<float>(b * P);
+  e.part = ar.take<double>(e.S * b * b);
+  for (double** x : {&e.W, &e.Linv, &e.T, &e.U}) *x = ar.take<double>(b * b);
+  e.theta = ar.take<double>(b);
+  e.res = ar.take<double>(b);
+  e.info = ar.take<int>(16);
+  if (source == 0) {
+    if (prec == HESS_P_F64)
+      plan_hvp<double>(ar, *m, N, b, e.p, e.hd);
+    else
+      plan_hvp<float>(ar, *m, N, b, e.p, e.hf);
+  }
+  return ar.used;
+}
+
+namespace {
+
+// The Cholesky and Jacobi kernels keep a b x (b + 1) FP64 matrix in LDS (up to 132 KB).
+void set_lds_limits() {
+  static bool done = false;
+  if (done) return;
+  const int lim = 150 * 1024;
+  (void)hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  done = true;
+}
+
+struct EigRun {
+  Exec* ex;
+  EigBufs* e;
+  const Model* m;
+  int64_t N;
+  int source, which, prec, Mdtype;
+  const void* M;
+};
+
+// Y = Op Q (rows), both b x ldp FP64
+void op_apply(EigRun& r, const double* Q, double* Y) {
+  Exec& ex = *r.ex;
+  EigBufs& e = *r.e;
+  const int64_t b = e.b, P = e.P, ldp = e.ldp;
+  if (r.source == 1) {
+    if (r.Mdtype == HESS_F64) {
+      gemm_rm<double>(ex, false, false, b, P, P, 1.0, Q, ldp, static_cast<const double*>(r.M), P, 0.0, Y, ldp);
+    } else {
+      cast_2d<float>(ex, Q, b, P, ldp, e.Qf, P);
+      gemm_rm<float>(ex, false, false, b, P, P, 1.0f, e.Qf, P, static_cast<const float*>(r.M), P, 0.0f, e.Yf, P);
+      LAUNCH(k_f32_to_f64_2d, b * P, e.Yf, b, P, P, Y, ldp);
+    }
+    return;
+  }
+  if (r.prec == HESS_P_F64) {
+    if (r.which == 0)
+      hvp_apply<double>(ex, *r.m, r.N, b, e.p, e.hd, Q, ldp, Y);
+    else
+      opg_apply<double>(ex, *r.m, r.N, b, e.p, e.hd, Q, ldp, Y);
+  } else {
+    cast_2d<float>(ex, Q, b, P, ldp, e.Qf, P);
+    if (r.which == 0)
+      hvp_apply<float>(ex, *r.m, r.N, b, e.p, e.hf, e.Qf, P, e.Yf);
+    else
+      opg_apply<float>(ex, *r.m, r.N, b, e.p, e.hf, e.Qf, P, e.Yf);
+    LAUNCH(k_f32_to_f64_2d, b * P, e.Yf, b, P, P, Y, ldp);
+  }
+}
+
+// C (b x b) = A B^T over ldp columns, split over KSPLIT columns and summed in order
+void gram(EigRun& r, const double* A, const double* B, double* C) {
+  Exec& ex = *r.ex;
+  EigBufs& e = *r.e;
+  GemmArgs<double> g;
+  g.M = e.b; g.N = e.b; g.K = KSPLIT;
+  g.A = A; g.sam = e.ldp; g.sak = 1; g.sab = KSPLIT;
+  g.B = B; g.sbk = 1; g.sbn = e.ldp; g.sbb = KSPLIT;
+  g.C = e.part; g.scm = e.b; g.scn = 1; g.scb = e.b * e.b;
+  g.alpha = 1.0; g.beta = 0.0; g.batch = e.S;
+  gemm<double>(ex, g);
+  LAUNCH(k_sum_splits, e.b * e.b, e.part, e.S, e.b * e.b, C);
+}
+
+// Q = orthonormal rows spanning Y: shifted Cholesky-QR, then two plain passes.  Y is overwritten.
+void orth(EigRun& r, double* Y, double* Q) {
+  Exec& ex = *r.ex;
+  EigBufs& e = *r.e;
+  const int b = (int)e.b;
+  const size_t shm = (size_t)b * (b + 1) * sizeof(double);
+  for (int pass = 0; pass < 3; ++pass) {
+    double* src = pass == 1 ? Q : Y;
+    double* dst = pass == 1 ? Y : Q;
+    gram(r, src, src, e.W);
+    if (!launch_ok(ex)) return;
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), shm, ex.stream, e.W, b, e.P, pass == 0 ? 1 : 0, e.Linv,
+                       e.info);
+    gemm_rm<double>(ex, false, false, b, e.ldp, b, 1.0, e.Linv, b, src, e.ldp, 0.0, dst, e.ldp);
+  }
+}
+
+// Rayleigh-Ritz on the orthonormal block Q: X, MX, theta (descending), res.
+void rayleigh_ritz(EigRun& r, int* sweeps) {
+  Exec& ex = *r.ex;
+  EigBufs& e = *r.e;
+  const int b = (int)e.b;
+  op_apply(r, e.Q, e.MQ);
+  gram(r, e.Q, e.MQ, e.T);
+  const int n = (b + 1) & ~1;
+  const size_t shm = (size_t)n * (n + 1) * sizeof(double);
+  if (!launch_ok(ex)) return;
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), shm, ex.stream, e.T, b, 60, e.theta, e.U, e.info + 4);
+  gemm_rm<double>(ex, true, false, b, e.ldp, b, 1.0, e.U, b, e.Q, e.ldp, 0.0, e.X, e.ldp);
+  gemm_rm<double>(ex, true, false, b, e.ldp, b, 1.0, e.U, b, e.MQ, e.ldp, 0.0, e.MX, e.ldp);
+  if (!launch_ok(ex)) return;
+  hipLaunchKernelGGL(k_resid, dim3(b), dim3(256), 0, ex.stream, e.MX, e.X, e.theta, e.P, e.ldp, e.res);
+  (void)sweeps;
+}
+
+bool read_back(Exec& ex, EigBufs& e, std::vector<double>& theta, std::vector<double>& res, int* info) {
+  theta.assign(e.b, 0.0);
+  res.assign(e.b, 0.0);
+  hipMemcpyAsync(theta.data(), e.theta, e.b * sizeof(double), hipMemcpyDeviceToHost, ex.stream);
+  hipMemcpyAsync(res.data(), e.res, e.b * sizeof(double), hipMemcpyDeviceToHost, ex.stream);
+  hipMemcpyAsync(info, e.info, 16 * sizeof(int), hipMemcpyDeviceToHost, ex.stream);
+  return hipStreamSynchronize(ex.stream) == hipSuccess && !ex.ctx->fault_hit;
+}
+
+}  // namespace
+
+struct TopkPlan {
+  Model m;
+  bool has_model = false;
+  int64_t N = 0, P = 0, b = 0;
+  int source = 0, which = 0, prec = 1, Mdtype = 0, max_iter = 200;
+  double tol = 1e-5;
+  int64_t oversample = 10;
+};
+
+static hess_status topk_validate(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int64_t K,
+                                 const hess_eig_opts* o, TopkPlan& t, bool need_ptrs) {
+  if (!o) return fail(ctx, HESS_E_ARG, "opts is NULL");
+  t.source = o->source;
+  t.which = o->which;
+  if (t.source != 0 && t.source != 1) return fail(ctx, HESS_E_ARG, "opts.source must be 0 or 1");
+  if (t.which != 0 && t.which != 1) return fail(ctx, HESS_E_ARG, "opts.which must be 0 or 1");
+  hess_status s;
+  if (t.source == 1) {
+    if (need_ptrs && !o->M) return fail(ctx, HESS_E_ARG, "opts.M is NULL");
+    if (o->M_dtype != HESS_F64 && o->M_dtype != HESS_F32) return fail(ctx, HESS_E_ARG, "bad opts.M_dtype");
+    if (o->P < 1 || o->P > ((int64_t)1 << 31)) return fail(ctx, HESS_E_SHAPE, "opts.P out of range");
+    t.P = o->P;
+    t.Mdtype = o->M_dtype;
+  } else {
+    if ((s = validate_mlp(ctx, mlp, t.m, need_ptrs)) != HESS_OK) return s;
+    if ((s = validate_data(ctx, d, need_ptrs)) != HESS_OK) return s;
+    if (o->prec != HESS_P_F64 && o->prec != HESS_P_F32)
+      return fail(ctx, HESS_E_UNSUPPORTED, "matrix-free operator: F64 or F32");
+    t.has_model = true;
+    t.N = d->N;
+    t.P = t.m.P;
+    t.prec = o->prec;
+  }
+  t.oversample = o->oversample < 0 ? 10 : o->oversample;
+  t.max_iter = o->max_iter <= 0 ? 200 : o->max_iter;
+  t.tol = o->tol > 0 ? o->tol : 1e-5;
+  if (K < 1 || K > t.P) return fail(ctx, HESS_E_SHAPE, "K out of range");
+  t.b = std::min<int64_t>(rup(K + t.oversample, 16), t.P);
+  if (t.b > BMAX) return fail(ctx, HESS_E_SHAPE, "K + oversample must not exceed 128");
+  return HESS_OK;
+}
+
+hess_status topk_workspace(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int64_t K,
+                           const hess_eig_opts* o, size_t* bytes) {
+  TopkPlan t;
+  hess_status s = topk_validate(ctx, mlp, d, K, o, t, false);
+  if (s != HESS_OK) return s;
+  Arena ar(nullptr);
+  EigBufs e;
+  *bytes = plan_eig(ar, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, e);
+  return HESS_OK;
+}
+
+}  // namespace hs
+
+using namespace hs;
+
+extern "C" hess_status hess_topk_eig(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int64_t K,
+                                     const hess_eig_opts* opts, double* lambda, double* Qout,
+                                     hess_eig_info* info, void* ws, size_t ws_bytes) {
+  Exec ex;
+  hess_status s = begin(ctx, ex);
+  if (s != HESS_OK) return s;
+  TopkPlan t;
+  if ((s = topk_validate(ctx, mlp, d, K, opts, t, true)) != HESS_OK) return s;
+  if (!lambda || !Qout) return fail(ctx, HESS_E_ARG, "lambda or Q is NULL");
+  Arena probe(nullptr);
+  EigBufs e0;
+  const size_t need = plan_eig(probe, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, e0);
+  if ((s = check_ws(ctx, need, ws, ws_bytes, (size_t)K * (t.P + 1) * 8)) != HESS_OK) return s;
+  Arena ar(ws);
+  EigBufs e;
+  plan_eig(ar, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, e);
+  if (t.source == 0) {
+    if ((s = check_inputs(ex, t.m, d, e.p)) != HESS_OK) return s;
+    run_prep(ex, t.m, d, e.p, false);
+    if (t.prec == HESS_P_F64)
+      hvp_setup<double>(ex, t.m, t.N, e.p, e.hd);
+    else
+      hvp_setup<float>(ex, t.m, t.N, e.p, e.hf);
+  }
+  set_lds_limits();
+  EigRun r{&ex, &e, t.has_model ? &t.m : nullptr, t.N, t.source, t.which, t.prec, t.Mdtype,
+           t.source == 1 ? opts->M : nullptr};
+  const int64_t nb = e.b * e.ldp;
+  if (launch_ok(ex))
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(16)), dim3(TPB), 0, ex.stream, reinterpret_cast<double*>(e.info),
+                       (int64_t)8, 0.0);
+  for (double* x : {e.Y, e.Yp, e.Z, e.MQ, e.X, e.MX})
+    if (launch_ok(ex)) hipLaunchKernelGGL(k_fill, dim3(grid_for(nb)), dim3(TPB), 0, ex.stream, x, nb, 0.0);
+  if (launch_ok(ex))
+    hipLaunchKernelGGL(k_randn, dim3(grid_for(nb)), dim3(TPB), 0, ex.stream, (uint64_t)opts->seed, e.b, e.P,
+                       e.ldp, e.Y);
+  orth(r, e.Y, e.Q);
+  int applies = 0;
+  // a few unfiltered block steps: estimate of the spectral radius
+  for (int it = 0; it < 3; ++it) {
+    op_apply(r, e.Q, e.Y);
+    ++applies;
+    orth(r, e.Y, e.Q);
+  }
+  rayleigh_ritz(r, nullptr);
+  ++applies;
+  std::vector<double> theta, res;
+  int hinfo[16];
+  if (!read_back(ex, e, theta, res, hinfo)) return finish(ex, "hess_topk_eig");
+  double rho = 0.0;
+  for (int64_t k = 0; k < e.b; ++k) rho = std::max(rho, std::fabs(theta[k]) + res[k]);
+  const double lb = t.which == 1 ? -0.01 * rho : -1.5 * rho;  // the OPG is positive semidefinite
+  const int degree = 8;
+  int iters = 0;
+  double maxrel = 0.0;
+  bool converged = false;
+  for (;;) {
+    maxrel = 0.0;
+    const double scale = std::max(std::fabs(theta[0]), 1e-300);
+    for (int64_t k = 0; k < K; ++k) maxrel = std::max(maxrel, res[k] / scale);
+    if (!std::isfinite(maxrel)) break;
+    if (maxrel <= t.tol) {
+      converged = true;
+      break;
+    }
+    if (iters >= t.max_iter) break;
+    ++iters;
+    // Chebyshev filter on [lb, a]: Y_1 = (M X - c X) / e, Y_{j+1} = 2 (M Y_j - c Y_j) / e - Y_{j-1}
+    double a = theta[e.b - 1];
+    if (!(a > lb)) a = lb + 0.1 * (rho - lb);
+    const double c = 0.5 * (a + lb), hw = 0.5 * (a - lb);
+    if (launch_ok(ex))
+      hipLaunchKernelGGL(k_axpbypcz, dim3(grid_for(nb)), dim3(TPB), 0, ex.stream, 1.0 / hw, e.MX, -c / hw, e.X,
+                         0.0, nullptr, nb, e.Y);
+    hipMemcpyAsync(e.Yp, e.X, nb * sizeof(double), hipMemcpyDeviceToDevice, ex.stream);
+    for (int j = 1; j < degree; ++j) {
+      op_apply(r, e.Y, e.Z);
+      ++applies;
+      // Z <- 2 (Z - c Y) / hw - Yp ; then rotate (Yp, Y) <- (Y, Z)
+      if (launch_ok(ex))
+        hipLaunchKernelGGL(k_axpbypcz, dim3(grid_for(nb)), dim3(TPB), 0, ex.stream, 2.0 / hw, e.Z, -2.0 * c / hw,
+                           e.Y, -1.0, e.Yp, nb, e.Z);
+      std::swap(e.Yp, e.Y);
+      std::swap(e.Y, e.Z);
+    }
+    orth(r, e.Y, e.Q);
+    rayleigh_ritz(r, nullptr);
+    ++applies;
+    if (!read_back(ex, e, theta, res, hinfo)) return finish(ex, "hess_topk_eig");
+  }
+  // outputs: lambda (K), Q (K x P) sign-normalised
+  hipMemcpyAsync(lambda, e.theta, K * sizeof(double), hipMemcpyDeviceToDevice, ex.stream);
+  if (launch_ok(ex)) hipLaunchKernelGGL(k_sign_copy, dim3((unsigned)K), dim3(256), 0, ex.stream, e.X, e.P, e.ldp, Qout);
+  if (info) {
+    info->iters = iters;
+    info->applies = applies;
+    info->max_rel_residual = maxrel;
+    info->shift_used = lb;
+  }
+  s = finish(ex, "hess_topk_eig");
+  if (s != HESS_OK) return s;
+  if (!converged)
+    return fail(ctx, HESS_E_NOCONV, "no convergence within max_iter (max rel residual " + std::to_string(maxrel) + ")");
+  return HESS_OK;
+}

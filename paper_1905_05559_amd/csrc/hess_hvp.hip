@@ -82,18 +82,46 @@ __global__ void k_rdelta(T* RD, const T* RZ, const T* D1, const T* CE, int64_t N
   }
 }
 
+// S[n][b] = sum_i delta2[n][i] U2[n][b][i] + (same for layers 3 and 4 when present)
+template <typename T>
+__global__ void k_jv(const T* U2, const T* U3, const T* U4, const T* d2, const T* d3, const T* d4, int64_t T2,
+                     int64_t T3, int64_t T4, int64_t Nc, int64_t B, T* S) {
+  GRID_STRIDE(e, Nc * B) {
+    const int64_t n = e / B;
+    T s = 0;
+    for (int64_t i = 0; i < T2; ++i) s += d2[n * T2 + i] * U2[e * T2 + i];
+    if (d3)
+      for (int64_t i = 0; i < T3; ++i) s += d3[n * T3 + i] * U3[e * T3 + i];
+    if (d4)
+      for (int64_t i = 0; i < T4; ++i) s += d4[n * T4 + i] * U4[e * T4 + i];
+    S[e] = s;
+  }
+}
+
+template <typename T>
+__global__ void k_jv_add(const T* U, const T* d, int64_t Tl, int64_t Nc, int64_t B, T* S) {
+  GRID_STRIDE(e, Nc * B) {
+    const int64_t n = e / B;
+    T s = 0;
+    for (int64_t i = 0; i < Tl; ++i) s += d[n * Tl + i] * U[e * Tl + i];
+    S[e] += s;
+  }
+}
+
+// D[n][b][i] = delta[n][i] * S[n][b]
+template <typename T>
+__global__ void k_dscale(const T* d, const T* S, int64_t Nc, int64_t B, int64_t Tl, T* D) {
+  GRID_STRIDE(e, Nc * B * Tl) {
+    const int64_t i = e % Tl, nb = e / Tl, n = nb / B;
+    D[e] = d[n * Tl + i] * S[nb];
+  }
+}
+
 #define LAUNCH(kernel, n, ...)                                                                 \
   do {                                                                                         \
     if (!launch_ok(ex)) return;                                                                \
     hipLaunchKernelGGL(kernel, dim3(grid_for(n)), dim3(TPB), 0, ex.stream, __VA_ARGS__);       \
   } while (0)
-
-template <typename T>
-struct HvpBufs {
-  std::vector<T*> abar, delta, D1, CE, W, Vbar, HVbar, RZ, RA, RD;
-  T* Yhat = nullptr;
-  int64_t Nc = 0;
-};
 
 int64_t hvp_chunk(const Model& m, int64_t N, int64_t B, size_t esz) {
   int64_t sumT = 0;
@@ -103,6 +131,8 @@ int64_t hvp_chunk(const Model& m, int64_t N, int64_t B, size_t esz) {
   nc = std::max<int64_t>(64, nc / 64 * 64);
   return std::min(N, nc);
 }
+
+}  // namespace
 
 template <typename T>
 size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h) {
@@ -137,11 +167,14 @@ size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBuf
     h.RD[l] = ar.take<T>(h.Nc * B * m.T[l - 1]);
     if (l < L) h.RA[l] = ar.take<T>(h.Nc * B * m.T[l - 1]);
   }
+  h.S = ar.take<T>(h.Nc * B);
+  h.Bmax = B;
   return ar.used;
 }
 
+// Operands of the R-operator passes in the arithmetic precision (once per call).
 template <typename T>
-void run_hvp(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, const T* V, T* HV) {
+void hvp_setup(Exec& ex, const Model& m, int64_t N, Prep& p, HvpBufs<T>& h) {
   const int L = m.L;
   const bool same = sizeof(T) == 8;
   // operands in the arithmetic precision
@@ -176,7 +209,17 @@ void run_hvp(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>
       h.W[l] = reinterpret_cast<T*>(p.W64[l - 2]);
     else
       cast_copy<T>(ex, p.W64[l - 2], h.W[l], Tl * Tin);
-    LAUNCH(k_pack_vbar<T>, B * Tl * (Tin + 1), V, B, m.P, m.offW[l - 2], m.offb[l - 2], Tl, Tin, h.Vbar[l]);
+  }
+}
+
+// HV[b, :] = H V[b, :] for b < B (rows of V and HV have stride ldv).
+template <typename T>
+void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, const T* V, int64_t ldv,
+               T* HV) {
+  const int L = m.L;
+  for (int l = 2; l <= L; ++l) {
+    const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
+    LAUNCH(k_pack_vbar<T>, B * Tl * (Tin + 1), V, B, ldv, m.offW[l - 2], m.offb[l - 2], Tl, Tin, h.Vbar[l]);
   }
 
   const T invN = (T)(1.0 / (double)N);
@@ -230,9 +273,87 @@ void run_hvp(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>
   }
   for (int l = 2; l <= L; ++l) {
     const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
-    LAUNCH(k_unpack_hv<T>, B * Tl * (Tin + 1), h.HVbar[l], B, m.P, m.offW[l - 2], m.offb[l - 2], Tl, Tin, HV);
+    LAUNCH(k_unpack_hv<T>, B * Tl * (Tin + 1), h.HVbar[l], B, ldv, m.offW[l - 2], m.offb[l - 2], Tl, Tin, HV);
   }
 }
+
+// OPG V without forming the OPG: (J^T (J v_b)) / N.  (J v_b)_n = sum_l delta^(l)_n . (Vbar_b^(l) abar^(l-1)_n),
+// then the accumulation GEMM of the R-operator path with R{delta^(l)} replaced by delta^(l)_n (J v_b)_n.
+template <typename T>
+void opg_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, const T* V, int64_t ldv,
+               T* GV) {
+  const int L = m.L;
+  for (int l = 2; l <= L; ++l) {
+    const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
+    LAUNCH(k_pack_vbar<T>, B * Tl * (Tin + 1), V, B, ldv, m.offW[l - 2], m.offb[l - 2], Tl, Tin, h.Vbar[l]);
+  }
+  const T invN = (T)(1.0 / (double)N);
+  for (int64_t n0 = 0; n0 < N; n0 += h.Nc) {
+    const int64_t Nc = std::min(h.Nc, N - n0);
+    const T beta_acc = n0 == 0 ? T(0) : T(1);
+    for (int l = 2; l <= L; ++l) {
+      const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
+      gemm_rm<T>(ex, false, true, Nc, B * Tl, Tin + 1, T(1), h.abar[l - 1] + n0 * p.lda[l - 1], p.lda[l - 1],
+                 h.Vbar[l], Tin + 1, T(0), h.RZ[l], B * Tl);
+    }
+    LAUNCH(k_jv<T>, Nc * B, h.RZ[2], h.RZ[3 <= L ? 3 : 2], h.RZ[4 <= L ? 4 : 2], h.delta[2] + n0 * m.T[1],
+           L >= 3 ? h.delta[3] + n0 * m.T[2] : nullptr, L >= 4 ? h.delta[4] + n0 * m.T[3] : nullptr,
+           m.T[1], L >= 3 ? m.T[2] : 0, L >= 4 ? m.T[3] : 0, Nc, B, h.S);
+    for (int l = 5; l <= L; ++l)
+      LAUNCH(k_jv_add<T>, Nc * B, h.RZ[l], h.delta[l] + n0 * m.T[l - 1], m.T[l - 1], Nc, B, h.S);
+    for (int l = 2; l <= L; ++l) {
+      const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
+      LAUNCH(k_dscale<T>, Nc * B * Tl, h.delta[l] + n0 * Tl, h.S, Nc, B, Tl, h.RD[l]);
+      gemm_rm<T>(ex, true, false, B * Tl, Tin + 1, Nc, invN, h.RD[l], B * Tl, h.abar[l - 1] + n0 * p.lda[l - 1],
+                 p.lda[l - 1], beta_acc, h.HVbar[l], Tin + 1);
+    }
+  }
+  for (int l = 2; l <= L; ++l) {
+    const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
+    LAUNCH(k_unpack_hv<T>, B * Tl * (Tin + 1), h.HVbar[l], B, ldv, m.offW[l - 2], m.offb[l - 2], Tl, Tin, GV);
+  }
+}
+
+template <typename T>
+void jv_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, const T* V, int64_t ldv,
+              T* JV) {
+  const int L = m.L;
+  for (int l = 2; l <= L; ++l) {
+    const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
+    LAUNCH(k_pack_vbar<T>, B * Tl * (Tin + 1), V, B, ldv, m.offW[l - 2], m.offb[l - 2], Tl, Tin, h.Vbar[l]);
+  }
+  for (int64_t n0 = 0; n0 < N; n0 += h.Nc) {
+    const int64_t Nc = std::min(h.Nc, N - n0);
+    for (int l = 2; l <= L; ++l) {
+      const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
+      gemm_rm<T>(ex, false, true, Nc, B * Tl, Tin + 1, T(1), h.abar[l - 1] + n0 * p.lda[l - 1], p.lda[l - 1],
+                 h.Vbar[l], Tin + 1, T(0), h.RZ[l], B * Tl);
+    }
+    T* out = JV + n0 * B;
+    LAUNCH(k_jv<T>, Nc * B, h.RZ[2], h.RZ[3 <= L ? 3 : 2], h.RZ[4 <= L ? 4 : 2], h.delta[2] + n0 * m.T[1],
+           L >= 3 ? h.delta[3] + n0 * m.T[2] : nullptr, L >= 4 ? h.delta[4] + n0 * m.T[3] : nullptr,
+           m.T[1], L >= 3 ? m.T[2] : 0, L >= 4 ? m.T[3] : 0, Nc, B, out);
+    for (int l = 5; l <= L; ++l)
+      LAUNCH(k_jv_add<T>, Nc * B, h.RZ[l], h.delta[l] + n0 * m.T[l - 1], m.T[l - 1], Nc, B, out);
+  }
+}
+
+template void jv_apply<double>(Exec&, const Model&, int64_t, int64_t, Prep&, HvpBufs<double>&, const double*,
+                               int64_t, double*);
+template size_t plan_hvp<float>(Arena&, const Model&, int64_t, int64_t, Prep&, HvpBufs<float>&);
+template size_t plan_hvp<double>(Arena&, const Model&, int64_t, int64_t, Prep&, HvpBufs<double>&);
+template void hvp_setup<float>(Exec&, const Model&, int64_t, Prep&, HvpBufs<float>&);
+template void hvp_setup<double>(Exec&, const Model&, int64_t, Prep&, HvpBufs<double>&);
+template void hvp_apply<float>(Exec&, const Model&, int64_t, int64_t, Prep&, HvpBufs<float>&, const float*,
+                               int64_t, float*);
+template void hvp_apply<double>(Exec&, const Model&, int64_t, int64_t, Prep&, HvpBufs<double>&, const double*,
+                                int64_t, double*);
+template void opg_apply<float>(Exec&, const Model&, int64_t, int64_t, Prep&, HvpBufs<float>&, const float*,
+                               int64_t, float*);
+template void opg_apply<double>(Exec&, const Model&, int64_t, int64_t, Prep&, HvpBufs<double>&, const double*,
+                                int64_t, double*);
+
+namespace {
 
 size_t ws_hvp(const Model& m, int64_t N, int prec, int64_t B) {
   Arena ar(nullptr);
@@ -279,13 +400,15 @@ extern "C" hess_status hess_hvp(hess_ctx* ctx, const hess_mlp* mlp, const hess_d
     plan_hvp<double>(ar, m, d->N, B, p, h);
     if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
     run_prep(ex, m, d, p, false);
-    run_hvp<double>(ex, m, d->N, B, p, h, static_cast<const double*>(V), static_cast<double*>(HV));
+    hvp_setup<double>(ex, m, d->N, p, h);
+    hvp_apply<double>(ex, m, d->N, B, p, h, static_cast<const double*>(V), m.P, static_cast<double*>(HV));
   } else {
     HvpBufs<float> h;
     plan_hvp<float>(ar, m, d->N, B, p, h);
     if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
     run_prep(ex, m, d, p, false);
-    run_hvp<float>(ex, m, d->N, B, p, h, static_cast<const float*>(V), static_cast<float*>(HV));
+    hvp_setup<float>(ex, m, d->N, p, h);
+    hvp_apply<float>(ex, m, d->N, B, p, h, static_cast<const float*>(V), m.P, static_cast<float*>(HV));
   }
   return finish(ex, "hess_hvp");
 }

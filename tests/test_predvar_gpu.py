@@ -1,0 +1,76 @@
+"""GPU parity of hess_predvar against the FP64 oracle (logit gradients, dense solve
+and the projection identity), plus its error paths."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import eig, mlp, predvar
+from paper_1905_05559_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_05559_amd import api as A
+    return A
+
+
+CASES = [([4, 8, 3], ["tanh"], 64, 1, 10), ([33, 40, 10], ["tanh"], 129, 5, 20),
+         ([7, 20, 13, 5], ["sigmoid", "relu"], 100, 3, 12)]
+
+
+@pytest.mark.parametrize("T,acts,N,seed,K", CASES)
+def test_predvar_matches_oracle(api, T, acts, N, seed, K):
+    w = workloads.mlp_gaussian(T, acts, N, seed, dtype="float64")
+    om = mlp.model_from(w.T, w.acts, w.W, w.b)
+    H = mlp.hessian(om, w.X, w.Y)
+    lam, Q = eig.topk_eigh(0.5 * (H + H.T), K)
+    delta = max(1e-3, -float(lam.min()) + 0.05)
+    rng = np.random.default_rng(seed)
+    Xq = np.concatenate([w.X[:9], rng.standard_normal((23, T[0]))])
+    cls_auto = predvar.default_classes(om, Xq)
+    cls_given = rng.integers(0, T[-1], size=Xq.shape[0]).astype(np.int32)
+    model = api.MLP.from_workload(w, dtype=torch.float64)
+    lam_d = torch.from_numpy(lam).cuda()
+    Q_d = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    Xq_d = torch.from_numpy(Xq).cuda()
+    for cls, cls_d in ((cls_auto, None), (cls_given, torch.from_numpy(cls_given).cuda())):
+        G = predvar.logit_grad(om, Xq, cls)
+        ref = predvar.predvar_dense(lam, Q, delta, G)
+        ref2 = predvar.predvar_identity(lam, Q, delta, G)
+        s = api.hess_predvar(model, lam_d, Q_d, delta, Xq_d, cls_d).cpu().numpy()
+        err = np.abs(s - ref).max() / np.abs(ref).max()
+        print("predvar %s K=%d cls=%s: rel max err %.2e (identity vs dense %.1e)" % (
+            T, K, "auto" if cls_d is None else "given", err, np.abs(ref2 - ref).max() / np.abs(ref).max()),
+            flush=True)
+        assert err < 1e-10
+
+
+def test_predvar_f32_model_and_errors(api):
+    w = workloads.mlp_gaussian([33, 40, 10], ["tanh"], 129, 5, dtype="float32")
+    om = mlp.model_from(w.T, w.acts, w.W, w.b)
+    H = mlp.hessian(om, w.X.astype(np.float64), w.Y.astype(np.float64))
+    lam, Q = eig.topk_eigh(0.5 * (H + H.T), 8)
+    model = api.MLP.from_workload(w, dtype=torch.float32)
+    Xq = w.X[:16]
+    delta = max(1e-3, -float(lam.min()) + 0.05)
+    G = predvar.logit_grad(om, Xq.astype(np.float64), predvar.default_classes(om, Xq.astype(np.float64)))
+    ref = predvar.predvar_identity(lam, Q, delta, G)
+    s = api.hess_predvar(model, torch.from_numpy(lam).cuda(), torch.from_numpy(np.ascontiguousarray(Q)).cuda(),
+                         delta, torch.from_numpy(Xq).cuda()).cpu().numpy()
+    assert np.abs(s - ref).max() / np.abs(ref).max() < 1e-10
+    # lambda_k + delta <= 0 -> HESS_E_NOTPD
+    bad = lam.copy()
+    bad[-1] = -10.0
+    with pytest.raises(api.HessError) as e:
+        api.hess_predvar(model, torch.from_numpy(bad).cuda(), torch.from_numpy(np.ascontiguousarray(Q)).cuda(),
+                         1e-3, torch.from_numpy(Xq).cuda())
+    assert e.value.name == "HESS_E_NOTPD"
+    # class index out of range -> HESS_E_ARG
+    with pytest.raises(api.HessError) as e:
+        api.hess_predvar(model, torch.from_numpy(lam).cuda(), torch.from_numpy(np.ascontiguousarray(Q)).cuda(),
+                         delta, torch.from_numpy(Xq).cuda(), torch.full((16,), 99, dtype=torch.int32).cuda())
+    assert e.value.name == "HESS_E_ARG"
