@@ -4,10 +4,15 @@
 Workload (default): the MNIST-shaped synthetic MLP [784, 100, 10], ReLU hidden
 layer, N = 60000 examples, x_{n,j} = 0 with probability 0.8 else U[0,1), labels
 uniform over 10 classes, Glorot-uniform weights, zero biases (P = 79510).  One
-step computes, with inputs already resident in HBM:
+step runs every row of the hot path on that workload, with inputs already
+resident in HBM:
   * the OPG  J^T J / N  (BF16 operands, FP32 accumulation), P x P FP32
   * the exact Hessian H (FP32 MFMA), P x P FP32
-value = 2 P^2 / step time  ("exact-H+OPG P^2-entries/s": P^2 entries of each matrix).
+  * the 100 algebraically largest eigenpairs of H (FP32 operator, FP64 Rayleigh-Ritz, tol 1e-5)
+  * 512 dense Hessian-vector products (matrix-free R-operator, FP32)
+  * the damped curvature query for 1024 inputs against those eigenpairs (FP64)
+value = 2 P^2 / step time  ("exact-H+OPG P^2-entries/s": P^2 entries of each matrix),
+with the per-phase times, HVPs/s and query rates reported beside it.
 
 The JSON line also carries the roofline of the dominant kernel (algorithmic flops
 per launch / average launch time from HIP events on the library's stream) and the
@@ -134,13 +139,39 @@ def main():
     H = torch.empty((P, P), dtype=torch.float32, device=dev)
     G = torch.empty((P, P), dtype=torch.float32, device=dev)
     ws_bytes = max(api.workspace_size("exact", model, X, Y, "f32", ctx=ctx),
-                   api.workspace_size("opg", model, X, Y, "bf16", ctx=ctx))
+                   api.workspace_size("opg", model, X, Y, "bf16", ctx=ctx),
+                   api.workspace_size("hvp", model, X, Y, "f32", arg=512, ctx=ctx))
     ctx.workspace(ws_bytes)
     log("outputs 2 x %.1f GB, workspace %.2f GB" % (P * P * 4 / 1e9, ws_bytes / 1e9))
 
-    def step():
+    K, B, NQ = 100, 512, 1024
+    V = torch.from_numpy(workloads.gaussian_directions(B, P, 7)).to(dev)
+    HV = torch.empty_like(V)
+    Xq = torch.from_numpy(workloads.queries_like_mnist(NQ, 11, T1=w.T[0])).to(dev)
+    eopts = api.eig_opts(which="H", source="dense", M=H, tol=1e-5, seed=1, oversample=12, max_iter=200)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    phase_ms = {"opg": 0.0, "exact_H": 0.0, "topk": 0.0, "hvp": 0.0, "predvar": 0.0}
+    eig_info = {}
+
+    def step(record=False):
+        s = ctx.stream
+        ev[0].record(s)
         api.hess_opg(model, X, Y, "bf16", out=G, ctx=ctx)
+        ev[1].record(s)
         api.hess_exact(model, X, Y, "f32", out=H, ctx=ctx)
+        ev[2].record(s)
+        lam, Q, info, st = api.hess_topk_eig(None, None, None, K, eopts, ctx=ctx)
+        ev[3].record(s)
+        api.hess_hvp(model, X, Y, V, "f32", out=HV, ctx=ctx)
+        ev[4].record(s)
+        delta = max(1e-3, 1e-3 - float(lam.min()))  # keeps lambda_k + delta > 0
+        api.hess_predvar(model, lam, Q, delta, Xq, ctx=ctx)
+        ev[5].record(s)
+        if record:
+            torch.cuda.synchronize()
+            for i, k in enumerate(("opg", "exact_H", "topk", "hvp", "predvar")):
+                phase_ms[k] += ev[i].elapsed_time(ev[i + 1])
+            eig_info.update(info)
 
     for i in range(args.warmup):
         t = time.perf_counter()
@@ -153,7 +184,7 @@ def main():
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for i in range(args.steps):
-        step()
+        step(record=True)
         log("step %d done" % i)
     e1.record(s)
     torch.cuda.synchronize()
@@ -178,6 +209,8 @@ def main():
         "share_of_step": round(d["ms"] / args.steps / ms, 4),
     }
     value = 2.0 * P * P / (ms / 1e3)
+    ph = {k: v / args.steps for k, v in phase_ms.items()}
+    log("phases (ms/step): %s" % json.dumps({k: round(v, 2) for k, v in ph.items()}))
     out = {
         "metric": "exact-H+OPG P^2-entries/s",
         "value": value,
@@ -189,15 +222,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (H) + bf16->f32 (OPG)",
+        "dtype": "f32 (H, HVP) + bf16->f32 (OPG) + f64 (QR, Rayleigh-Ritz, query)",
         "data": "synthetic",
         "config": {"workload": w.name, "T": w.T, "N": w.N, "P": P,
-                   "step": "OPG (BF16 MFMA, FP32 acc) + exact H (FP32 MFMA), P x P each, inputs resident in HBM"},
+                   "step": "OPG (BF16 MFMA, FP32 acc) + exact H (FP32 MFMA), P x P each; top-100 eigenpairs "
+                           "of H (FP32 operator, FP64 RR, tol 1e-5); 512 dense HVPs (FP32); damped query "
+                           "for 1024 inputs (FP64); inputs resident in HBM"},
+        "phases_ms": {k: round(v, 3) for k, v in ph.items()},
+        "hvps_per_s": {"dense_B512": B / (ph["hvp"] / 1e3), "basis_via_exact_H": P / (ph["exact_H"] / 1e3)},
+        "opg_p2_entries_per_s": P * P / (ph["opg"] / 1e3),
+        "exact_h_p2_entries_per_s": P * P / (ph["exact_H"] / 1e3),
+        "topk": {"K": K, "iters": eig_info.get("iters"), "applies": eig_info.get("applies"),
+                 "max_rel_residual": eig_info.get("max_rel_residual")},
+        "predvar_queries_per_s": NQ / (ph["predvar"] / 1e3),
         "roofline": roofline,
         "kernels": {k: {"launches": v["launches"], "ms_per_step": v["ms"] / args.steps,
                         "tflops": v["flops"] / v["ms"] / 1e9 if v["ms"] else 0.0} for k, v in prof.items()},
     }
-    del H, G
+    del H, G, V, HV
     ctx.release_workspace()
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
