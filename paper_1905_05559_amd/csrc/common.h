@@ -105,6 +105,10 @@ struct KrgArgs {
 };
 template <typename T, typename TOut>
 void krg(Exec& ex, const KrgArgs<T, TOut>& a);
+// Tile-configuration variants (tuning and tests): 1..4 = (K chunk, LDS stages) in
+// {(16,1), (16,2), (32,1), (32,2)}; 0 = the default for the precision.
+template <typename T, typename TOut>
+void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant);
 // BF16 OPG: materialise Jt (P x ldk, BF16, p-major) then one symmetric Gram product.
 constexpr int JT_MAXL = 16;
 struct JtArgs {

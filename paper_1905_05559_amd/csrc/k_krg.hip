@@ -16,17 +16,19 @@
 // Tile: 128 x 128 outputs per workgroup of 4 wavefronts (2 x 2), each wavefront
 // 64 x 64 = 4 x 4 MFMA blocks of 16 x 16.  Units are padded to a multiple of 16
 // slots in compute space so every MFMA block lies inside one (row unit, column
-// unit) pair.  K (the example index) is staged in chunks of 16 through LDS with
-// the same k-permutation as the generic GEMM.  Symmetric blocks enumerate only the
-// lower triangle of tiles and mirror every stored entry, so the result is exactly
-// symmetric.
+// unit) pair.  K (the example index) is staged through LDS in chunks of KC with the
+// k-permutation of the generic GEMM (lane group q takes 4 consecutive k per 16),
+// with STAGES LDS buffers: with two, the next chunk is written while the current
+// one is read and one barrier per chunk suffices.  Symmetric blocks enumerate only
+// the lower triangle of tiles and mirror every stored entry, so the result is
+// exactly symmetric.
 #include "mfma.h"
 
 namespace hs {
 
 namespace {
 
-constexpr int BM = 128, BN = 128, KC = 16, KP = KC + 4;
+constexpr int BM = 128, BN = 128;
 constexpr int MAXU = BM / 16 + 1;  // units a tile can touch (pad >= 16)
 
 __device__ __forceinline__ int64_t flat_index(int32_t perm, int64_t off, int32_t Tin, int32_t Tout,
@@ -35,8 +37,7 @@ __device__ __forceinline__ int64_t flat_index(int32_t perm, int64_t off, int32_t
   return j < Tin ? off + i * Tin + j : off + (int64_t)Tout * Tin + i;
 }
 
-__device__ __forceinline__ void tile_of(int64_t t, int32_t symmetric, int64_t tiles_c, int64_t& tr,
-                                        int64_t& tc) {
+__device__ __forceinline__ void tile_of(int64_t t, bool symmetric, int64_t tiles_c, int64_t& tr, int64_t& tc) {
   if (symmetric) {
     int64_t r = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (r * (r + 1) / 2 > t) --r;
@@ -49,7 +50,7 @@ __device__ __forceinline__ void tile_of(int64_t t, int32_t symmetric, int64_t ti
   }
 }
 
-template <typename T, typename TOut>
+template <typename TOut>
 __device__ __forceinline__ void store_out(TOut* out, int64_t idx, double v, int32_t accumulate) {
   if (accumulate)
     out[idx] = (TOut)((double)out[idx] + v);
@@ -57,13 +58,19 @@ __device__ __forceinline__ void store_out(TOut* out, int64_t idx, double v, int3
     out[idx] = (TOut)v;
 }
 
-template <typename T, typename TOut, int WMODE, bool SYM>
-__global__ __launch_bounds__(256) void krg_kernel(KrgArgs<T, TOut> a, int64_t tiles_c, int64_t ntiles) {
+template <typename T, typename TOut, int WMODE, bool SYM, int KC, int STAGES>
+// FP32 with K chunk 16 is held to two wavefronts per SIMD (228 registers, no spills):
+// the kernel is latency-sensitive and the second wavefront hides the staging loads.
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && KC == 16) ? 2 : 1) void krg_kernel(KrgArgs<T, TOut> a,
+                                                                                         int64_t tiles_c,
+                                                                                         int64_t ntiles) {
   using Op = MfmaOp<T>;
   using acc_t = typename Op::acc_t;
-  __shared__ __attribute__((aligned(16))) T As[BM * KP];
-  __shared__ __attribute__((aligned(16))) T Bs[BN * KP];
-  __shared__ __attribute__((aligned(16))) T Ws[(WMODE == KRG_RANK1) ? 4 : MAXU * MAXU * KC];
+  constexpr int KP = KC + 4;
+  constexpr int WSZ = (WMODE == KRG_RANK1) ? 4 : MAXU * MAXU * KC;
+  __shared__ __attribute__((aligned(16))) T As[STAGES][BM * KP];
+  __shared__ __attribute__((aligned(16))) T Bs[STAGES][BN * KP];
+  __shared__ __attribute__((aligned(16))) T Ws[STAGES][WSZ];
 
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
   if (t < 0) return;
@@ -79,30 +86,33 @@ __global__ __launch_bounds__(256) void krg_kernel(KrgArgs<T, TOut> a, int64_t ti
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
 
-  // Staging assignment: thread -> one row (column) of the tile and 8 consecutive k.
-  const int srow = tid & 127, sk0 = (tid >> 7) * 8;
+  // Staging assignment: thread -> one row (column) of the tile and KC/2 consecutive k.
+  constexpr int SK = KC / 2;
+  const int srow = tid & 127, sk0 = (tid >> 7) * SK;
   const int64_t gr = r0 + srow, gc = c0 + srow;
   const int64_t sur = gr / a.r.pad, ssr = gr % a.r.pad;
   const int64_t suc = gc / a.c.pad, ssc = gc % a.c.pad;
   const bool rvalid = sur < a.r.n_units && ssr < a.r.len;
   const bool cvalid = suc < a.c.n_units && ssc < a.c.len;
-  T ra[8], rbv[8];
-  constexpr int WE = (WMODE == KRG_RANK1) ? 1 : (MAXU * MAXU * KC + 255) / 256;
+  const T* rsrc = a.r.src + ssr;
+  const T* csrc = a.c.src + ssc;
+  T ra[SK], rbv[SK];
+  constexpr int WE = (WMODE == KRG_RANK1) ? 1 : (WSZ + 255) / 256;
   T rw[WE];
   const int nw = nur * nuc * KC;
 
   auto load = [&](int64_t n0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < SK; ++i) {
       const int64_t n = n0 + sk0 + i;
       T va = T(0), vb = T(0);
       if (n < a.N) {
         if (rvalid) {
-          va = a.r.src[n * a.r.ld + ssr];
+          va = rsrc[n * a.r.ld];
           if (WMODE == KRG_RANK1 && a.r.scale) va *= a.r.scale[n * a.r.ld_scale + sur];
         }
         if (cvalid) {
-          vb = a.c.src[n * a.c.ld + ssc];
+          vb = csrc[n * a.c.ld];
           if (WMODE == KRG_RANK1 && a.c.scale) vb *= a.c.scale[n * a.c.ld_scale + suc];
         }
       }
@@ -129,11 +139,11 @@ __global__ __launch_bounds__(256) void krg_kernel(KrgArgs<T, TOut> a, int64_t ti
       }
     }
   };
-  auto store = [&]() {
+  auto store = [&](int s) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      As[srow * KP + sk0 + i] = ra[i];
-      Bs[srow * KP + sk0 + i] = rbv[i];
+    for (int i = 0; i < SK; ++i) {
+      As[s][srow * KP + sk0 + i] = ra[i];
+      Bs[s][srow * KP + sk0 + i] = rbv[i];
     }
     if (WMODE != KRG_RANK1) {
 #pragma unroll
@@ -141,7 +151,7 @@ __global__ __launch_bounds__(256) void krg_kernel(KrgArgs<T, TOut> a, int64_t ti
         const int e = tid + i * 256;
         if (e < nw) {
           const int kk = e % KC, p = e / KC;
-          Ws[((p / nuc) * MAXU + (p % nuc)) * KC + kk] = rw[i];
+          Ws[s][((p / nuc) * MAXU + (p % nuc)) * KC + kk] = rw[i];
         }
       }
     }
@@ -162,39 +172,79 @@ __global__ __launch_bounds__(256) void krg_kernel(KrgArgs<T, TOut> a, int64_t ti
     for (int j = 0; j < 4; ++j) acc[i][j] = Op::zero();
 
   const int row = lane & 15, q = lane >> 4;
+  // All four column blocks of this wavefront in one column unit (the common case when
+  // units are wider than 64 slots): the pair weight then depends on the row block only
+  // and is applied once to each A fragment instead of once per MFMA block.
+  const bool one_cunit = pc[0] == pc[3];
+  auto compute = [&](int s) {
+#pragma unroll
+    for (int ks = 0; ks < KC / 16; ++ks) {
+      const int ko = ks * 16 + 4 * q;
+      T av[4][4], bv[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) av[i][u] = As[s][(wr * 64 + i * 16 + row) * KP + ko + u];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) bv[j][u] = Bs[s][(wc * 64 + j * 16 + row) * KP + ko + u];
+      if (WMODE == KRG_RANK1) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = Op::mma(av[i][u], bv[j][u], acc[i][j]);
+      } else if (one_cunit) {
+        T w[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const bool live = WMODE != KRG_PAIR_DIAG || (pu[i] + ur_lo) == (pc[0] + uc_lo);
+          const T* wp = &Ws[s][(pu[i] * MAXU + pc[0]) * KC + ko];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) w[i][u] = live ? wp[u] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const T aw = av[i][u] * w[i][u];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = Op::mma(aw, bv[j][u], acc[i][j]);
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (WMODE == KRG_PAIR_DIAG && (pu[i] + ur_lo) != (pc[j] + uc_lo)) continue;
+            const T* wp = &Ws[s][(pu[i] * MAXU + pc[j]) * KC + ko];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[i][j] = Op::mma(av[i][u], bv[j][u] * wp[u], acc[i][j]);
+          }
+      }
+    }
+  };
+
   const int64_t nk = (a.N + KC - 1) / KC;
   load(0);
-  store();
+  store(0);
   __syncthreads();
   for (int64_t kc = 0; kc < nk; ++kc) {
-    if (kc + 1 < nk) load((kc + 1) * KC);
-    T av[4][4], bv[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) av[i][s] = As[(wr * 64 + i * 16 + row) * KP + 4 * q + s];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) bv[j][s] = Bs[(wc * 64 + j * 16 + row) * KP + 4 * q + s];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (WMODE == KRG_RANK1) {
-#pragma unroll
-          for (int s = 0; s < 4; ++s) acc[i][j] = Op::mma(av[i][s], bv[j][s], acc[i][j]);
-        } else {
-          if (WMODE == KRG_PAIR_DIAG && (pu[i] + ur_lo) != (pc[j] + uc_lo)) continue;
-          const T* wp = &Ws[(pu[i] * MAXU + pc[j]) * KC + 4 * q];
-#pragma unroll
-          for (int s = 0; s < 4; ++s) acc[i][j] = Op::mma(av[i][s], bv[j][s] * wp[s], acc[i][j]);
-        }
-      }
-    __syncthreads();
-    if (kc + 1 < nk) {
-      store();
+    const bool more = kc + 1 < nk;
+    if (more) load((kc + 1) * KC);
+    if (STAGES == 2) {
+      compute((int)(kc & 1));
+      if (more) store((int)((kc + 1) & 1));
       __syncthreads();
+    } else {
+      compute(0);
+      __syncthreads();
+      if (more) {
+        store(0);
+        __syncthreads();
+      }
     }
   }
 
@@ -223,17 +273,31 @@ __global__ __launch_bounds__(256) void krg_kernel(KrgArgs<T, TOut> a, int64_t ti
         if (!cok[j]) continue;
         if (SYM && r < ccomp[j]) continue;
         const double val = a.scale * (double)acc[i][j][v];
-        store_out<T, TOut>(a.out, fr * a.ldo + fcol[j], val, a.accumulate);
-        if (a.mirror && !(SYM && r == ccomp[j]))
-          store_out<T, TOut>(a.out, fcol[j] * a.ldo + fr, val, a.accumulate);
+        store_out<TOut>(a.out, fr * a.ldo + fcol[j], val, a.accumulate);
+        if (a.mirror && !(SYM && r == ccomp[j])) store_out<TOut>(a.out, fcol[j] * a.ldo + fr, val, a.accumulate);
       }
     }
 }
 
+template <typename T, typename TOut, int KC, int STAGES>
+void launch_cfg(Exec& ex, const KrgArgs<T, TOut>& a, dim3 grid, int64_t tc, int64_t nt) {
+#define KRG_LAUNCH(MODE, SYMV) \
+  hipLaunchKernelGGL((krg_kernel<T, TOut, MODE, SYMV, KC, STAGES>), grid, dim3(256), 0, ex.stream, a, tc, nt)
+  if (a.wmode == KRG_RANK1) {
+    if (a.symmetric) KRG_LAUNCH(KRG_RANK1, true); else KRG_LAUNCH(KRG_RANK1, false);
+  } else if (a.wmode == KRG_PAIR_FULL) {
+    if (a.symmetric) KRG_LAUNCH(KRG_PAIR_FULL, true); else KRG_LAUNCH(KRG_PAIR_FULL, false);
+  } else {
+    KRG_LAUNCH(KRG_PAIR_DIAG, false);
+  }
+#undef KRG_LAUNCH
+}
+
 }  // namespace
 
+// variant: 0 = default for the precision; 1 = (KC 16, 1 stage); 2 = (16, 2); 3 = (32, 1); 4 = (32, 2)
 template <typename T, typename TOut>
-void krg(Exec& ex, const KrgArgs<T, TOut>& a) {
+void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
   const int64_t rows = (int64_t)a.r.n_units * a.r.pad, cols = (int64_t)a.c.n_units * a.c.pad;
   const int64_t tr = (rows + BM - 1) / BM, tc = (cols + BN - 1) / BN;
   const int64_t nt = a.symmetric ? tr * (tr + 1) / 2 : tr * tc;
@@ -256,20 +320,30 @@ void krg(Exec& ex, const KrgArgs<T, TOut>& a) {
   const int tok = prof_begin(ex, names[sizeof(T) == 8][a.wmode][a.symmetric ? 1 : 0], 2.0 * a.N * entries,
                              src + wbytes + obytes);
   dim3 grid((unsigned)xcd_grid(nt));
-#define KRG_LAUNCH(MODE, SYMV) \
-  hipLaunchKernelGGL((krg_kernel<T, TOut, MODE, SYMV>), grid, dim3(256), 0, ex.stream, a, tc, nt)
-  if (a.wmode == KRG_RANK1) {
-    if (a.symmetric) KRG_LAUNCH(KRG_RANK1, true); else KRG_LAUNCH(KRG_RANK1, false);
-  } else if (a.wmode == KRG_PAIR_FULL) {
-    if (a.symmetric) KRG_LAUNCH(KRG_PAIR_FULL, true); else KRG_LAUNCH(KRG_PAIR_FULL, false);
+  if (variant == 0) variant = 1;  // measured best on the MNIST-shaped H block (K chunk 16, one stage)
+  if constexpr (sizeof(T) == 8) {  // FP64 tiles need twice the LDS: K chunk 16 only
+    if (variant == 2)
+      launch_cfg<T, TOut, 16, 2>(ex, a, grid, tc, nt);
+    else
+      launch_cfg<T, TOut, 16, 1>(ex, a, grid, tc, nt);
   } else {
-    KRG_LAUNCH(KRG_PAIR_DIAG, false);
+    switch (variant) {
+      case 1: launch_cfg<T, TOut, 16, 1>(ex, a, grid, tc, nt); break;
+      case 2: launch_cfg<T, TOut, 16, 2>(ex, a, grid, tc, nt); break;
+      case 3: launch_cfg<T, TOut, 32, 1>(ex, a, grid, tc, nt); break;
+      default: launch_cfg<T, TOut, 32, 2>(ex, a, grid, tc, nt); break;
+    }
   }
-#undef KRG_LAUNCH
   prof_end(ex, tok);
+}
+
+template <typename T, typename TOut>
+void krg(Exec& ex, const KrgArgs<T, TOut>& a) {
+  krg_variant<T, TOut>(ex, a, 0);
 }
 
 template void krg<double, double>(Exec&, const KrgArgs<double, double>&);
 template void krg<float, float>(Exec&, const KrgArgs<float, float>&);
+template void krg_variant<float, float>(Exec&, const KrgArgs<float, float>&, int);
 
 }  // namespace hs
