@@ -82,7 +82,8 @@ typedef struct {
 
 /* Operation codes for hess_workspace_size. */
 typedef enum {
-  HESS_OP_EXACT = 0, HESS_OP_OPG = 1, HESS_OP_HVP = 2, HESS_OP_TOPK = 3, HESS_OP_PREDVAR = 4
+  HESS_OP_EXACT = 0, HESS_OP_OPG = 1, HESS_OP_HVP = 2, HESS_OP_TOPK = 3, HESS_OP_PREDVAR = 4,
+  HESS_OP_BATCHED = 5
 } hess_op;
 
 /* Create a context on `device`; `stream` is a hipStream_t (NULL = the null stream). */
@@ -124,9 +125,10 @@ hess_status hess_profile_reset(hess_ctx* ctx);
 hess_status hess_num_params(const hess_mlp* m, int64_t* P);
 
 /* Bytes of workspace `op` needs.  `arg` is B for HESS_OP_HVP, K for HESS_OP_TOPK,
- * the number of queries for HESS_OP_PREDVAR, unused otherwise.  For HESS_OP_TOPK
- * `opts` is a const hess_eig_opts*, else NULL.  `data` may be NULL for
- * HESS_OP_PREDVAR and for HESS_OP_TOPK with a dense source. */
+ * the number of queries for HESS_OP_PREDVAR, the number of networks M for
+ * HESS_OP_BATCHED (then `m` and `d` point to arrays of M entries), unused otherwise.
+ * For HESS_OP_TOPK `opts` is a const hess_eig_opts*, else NULL.  `data` may be NULL
+ * for HESS_OP_PREDVAR and for HESS_OP_TOPK with a dense source. */
 hess_status hess_workspace_size(hess_ctx* ctx, int op, const hess_mlp* m, const hess_data* d,
                                 int prec, int64_t arg, const void* opts, size_t* bytes);
 
@@ -195,6 +197,17 @@ hess_status hess_topk_eig(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, 
 hess_status hess_predvar(hess_ctx* ctx, const hess_mlp* m, int64_t K, const double* lambda,
                          const double* Q, double delta, int64_t nq, const void* Xq,
                          const int32_t* cls, double* s, void* ws, size_t ws_bytes);
+
+/* Exact H and/or OPG of M independent networks with their own data sets (widths and
+ * N may differ), FP32 (prec must be HESS_P_F32).  Same definitions as hess_exact and
+ * hess_opg (paper, Sec. 3); the per-example passes of each network run as small
+ * launches and all P x P tiles of all networks go through one persistent launch
+ * (plus one for the cross-layer term of H).  models, datas: host arrays of M entries;
+ * H, G: host arrays of M device pointers (P_i x P_i FP32 row-major); H or G (the array)
+ * may be NULL, and so may single entries, to skip that output.  Results equal those of
+ * the single-network calls bitwise. */
+hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* models, const hess_data* datas, int prec,
+                         void* const* H, void* const* G, void* ws, size_t ws_bytes);
 
 #ifdef __cplusplus
 }

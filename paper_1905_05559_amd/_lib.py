@@ -16,14 +16,14 @@ STATUS_NAMES = {
 ACT = {"tanh": 0, "sigmoid": 1, "relu": 2}
 DTYPE = {"float64": 0, "float32": 1}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
-OP = {"exact": 0, "opg": 1, "hvp": 2, "topk": 3, "predvar": 4}
+OP = {"exact": 0, "opg": 1, "hvp": 2, "topk": 3, "predvar": 4, "batched": 5}
 OPT = {"check_inputs": 0, "hbm_budget": 1, "fault_after": 2, "profile": 3}
 
 # Every symbol include/hess.h declares.
 EXPORTS = (
     "hess_create", "hess_destroy", "hess_status_str", "hess_last_error", "hess_set_option",
     "hess_num_params", "hess_workspace_size", "hess_exact", "hess_opg", "hess_hvp",
-    "hess_topk_eig", "hess_predvar", "hess_profile_read", "hess_profile_reset",
+    "hess_topk_eig", "hess_predvar", "hess_profile_read", "hess_profile_reset", "hess_batched",
 )
 
 
@@ -82,6 +82,7 @@ def load(path: str = LIB_PATH):
         "hess_predvar": (st, [vp, pm, i64, vp, vp, C.c_double, i64, vp, vp, vp, vp, C.c_size_t]),
         "hess_profile_read": (C.c_int, [vp, C.POINTER(HessProfEntry), C.c_int]),
         "hess_profile_reset": (st, [vp]),
+        "hess_batched": (st, [vp, i64, pm, pd, C.c_int, C.POINTER(vp), C.POINTER(vp), vp, C.c_size_t]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -262,3 +262,32 @@ def hess_predvar(model: MLP, lam: torch.Tensor, Q: torch.Tensor, delta: float, X
                                     Xq.data_ptr(), cls.data_ptr() if cls is not None else None,
                                     s.data_ptr(), ws.data_ptr(), ws.numel()))
     return s
+
+
+def hess_batched(models: List[MLP], Xs: List[torch.Tensor], Ys: List[torch.Tensor], with_H: bool = True,
+                 with_G: bool = True, outs_H=None, outs_G=None, ctx: Optional[Context] = None):
+    """Exact H and/or OPG (FP32) of several networks in one call, see hess_batched in include/hess.h.
+
+    Returns (list of H or None, list of G or None)."""
+    ctx = ctx or default_context()
+    M = len(models)
+    ms = (L.HessMlp * M)()
+    ds = (L.HessData * M)()
+    keep = []
+    for i, (m, X, Y) in enumerate(zip(models, Xs, Ys)):
+        s = m.struct()
+        d = _data(X, Y)
+        keep.append((s, d))
+        ms[i] = s
+        ds[i] = d
+    Hs = outs_H if outs_H is not None else ([torch.empty((m.P, m.P), dtype=torch.float32, device=Xs[0].device)
+                                               for m in models] if with_H else None)
+    Gs = outs_G if outs_G is not None else ([torch.empty((m.P, m.P), dtype=torch.float32, device=Xs[0].device)
+                                               for m in models] if with_G else None)
+    hp = (C.c_void_p * M)(*[h.data_ptr() for h in Hs]) if Hs is not None else None
+    gp = (C.c_void_p * M)(*[g.data_ptr() for g in Gs]) if Gs is not None else None
+    nb = C.c_size_t()
+    ctx._check(ctx.lib.hess_workspace_size(ctx.h, L.OP["batched"], ms, ds, L.PREC["f32"], M, None, C.byref(nb)))
+    ws = ctx.workspace(nb.value)
+    ctx._check(ctx.lib.hess_batched(ctx.h, M, ms, ds, L.PREC["f32"], hp, gp, ws.data_ptr(), ws.numel()))
+    return Hs, Gs

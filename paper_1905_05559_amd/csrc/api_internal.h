@@ -47,6 +47,27 @@ hess_status finish(Exec& ex, const char* what);
 hess_status begin(hess_ctx* ctx, Exec& ex);
 hess_status check_ws(hess_ctx* ctx, size_t need, void* ws, size_t ws_bytes, size_t out_bytes);
 
+// Operands of the P x P contractions in the arithmetic precision.
+template <typename T>
+struct OpgBufs {
+  std::vector<T*> abar, delta;
+  __bf16* Jt = nullptr;
+  int64_t ldk = 0;
+};
+template <typename T>
+void plan_opg_ops(Arena& ar, const Model& m, int64_t N, const Prep& p, OpgBufs<T>& b);
+template <typename T>
+void cast_ops(Exec& ex, const Model& m, const Prep& p, OpgBufs<T>& b);
+// Row/column side of the contraction for layer l (params W^(l-1), b^(l)).
+template <typename T>
+KrgSide<T> side_layer(const Model& m, int l, const T* abar, int64_t lda, const T* scale, int64_t ld_scale);
+
+// Unit-direction R-operator factors of one column layer; see hess_api.hip.
+struct HFactors {
+  std::vector<double*> F, K, G;   // indexed by layer, layout [T_a][T_m][N]
+};
+void compute_factors(Exec& ex, const Model& m, int64_t N, Prep& p, HFactors& f, int mm);
+
 // Buffers of the R-operator (dense-direction) passes; see hess_hvp.hip.
 template <typename T>
 struct HvpBufs {
@@ -75,5 +96,7 @@ hess_status hvp_workspace(hess_ctx* ctx, const Model& m, int64_t N, int prec, in
 hess_status topk_workspace(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int64_t K,
                            const hess_eig_opts* o, size_t* bytes);
 hess_status predvar_workspace(hess_ctx* ctx, const Model& m, int prec, int64_t nq, size_t* bytes);
+hess_status batched_workspace(hess_ctx* ctx, int64_t M, const hess_mlp* models, const hess_data* datas,
+                              size_t* bytes);
 
 }  // namespace hs

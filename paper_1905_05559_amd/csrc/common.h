@@ -105,6 +105,15 @@ struct KrgArgs {
 };
 template <typename T, typename TOut>
 void krg(Exec& ex, const KrgArgs<T, TOut>& a);
+// Several contractions (FP32) through one persistent launch; jobs_dev is a device array.
+struct KrgJob {
+  KrgArgs<float, float> a;
+  int64_t tiles_c, first;  // column tiles; index of the job's first tile in the global order
+  int32_t mode;            // KRG_* weight mode
+};
+int64_t krg_tiles(const KrgArgs<float, float>& a, int64_t* tiles_c);
+void krg_persistent_launch(Exec& ex, const KrgJob* jobs_dev, int njobs, int64_t total, unsigned long long* counter,
+                           double flops, double bytes);
 // Tile-configuration variants (tuning and tests): 1..4 = (K chunk, LDS stages) in
 // {(16,1), (16,2), (32,1), (32,2)}; 0 = the default for the precision.
 template <typename T, typename TOut>

@@ -323,12 +323,7 @@ KrgSide<T> side_layer(const Model& m, int l, const T* abar, int64_t lda, const T
 // ---------------------------------------------------------------------------
 // OPG.
 // ---------------------------------------------------------------------------
-template <typename T>
-struct OpgBufs {
-  std::vector<T*> abar, delta;
-  __bf16* Jt = nullptr;
-  int64_t ldk = 0;
-};
+
 
 template <typename T>
 void plan_opg_ops(Arena& ar, const Model& m, int64_t N, const Prep& p, OpgBufs<T>& b) {
@@ -419,9 +414,7 @@ size_t plan_opg(const Model& m, int64_t N, int prec, void* ws, Prep& p, void* op
 //                                                      + [l > m] delta^(l)_{ni'} K^(l-1,m)_n[j',i] ]
 // (the K term has no bias row).  Blocks with l < m follow by symmetry.
 // ---------------------------------------------------------------------------
-struct HFactors {
-  std::vector<double*> F, K, G;   // indexed by layer, layout [T_a][T_m][N]
-};
+
 template <typename T>
 struct HOps {
   OpgBufs<T> base;                // abar and delta in operand precision
@@ -463,6 +456,26 @@ size_t plan_exact(const Model& m, int64_t N, void* ws, Prep& p, HOps<T>& ops, st
   return ar.used;
 }
 
+// FP64 factors F, K, G of column layer mm (layout [T_a][T_m][N]) from the per-example caches.
+void compute_factors(Exec& ex, const Model& m, int64_t N, Prep& p, HFactors& f, int mm) {
+  const int L = m.L;
+  const int64_t Tm = m.T[mm - 1];
+  // forward factors
+  if (mm < L) factor_first(ex, p.W64[mm - 1], m.T[mm], Tm, p.D1T[mm], N, f.F[mm + 1]);
+  for (int l = mm + 2; l <= L; ++l) {
+    factor_rowscale(ex, f.F[l - 1], m.T[l - 2], Tm, p.D1T[l - 1], N, f.K[l - 1]);
+    gemm_rm<double>(ex, false, false, m.T[l - 1], Tm * N, m.T[l - 2], 1.0, p.W64[l - 2], m.T[l - 2], f.K[l - 1],
+                    Tm * N, 0.0, f.F[l], Tm * N);
+  }
+  // backward factors
+  factor_softmax(ex, mm < L ? f.F[L] : nullptr, m.T[L - 1], Tm, p.PT, N, f.G[L]);
+  for (int l = L - 1; l >= mm; --l) {
+    gemm_rm<double>(ex, true, false, m.T[l - 1], Tm * N, m.T[l], 1.0, p.W64[l - 1], m.T[l - 1], f.G[l + 1],
+                    Tm * N, 0.0, f.G[l], Tm * N);
+    factor_combine(ex, f.G[l], m.T[l - 1], Tm, p.D1T[l], p.CT[l], l == mm ? nullptr : f.F[l], N);
+  }
+}
+
 template <typename T, typename TOut>
 void run_exact(Exec& ex, const Model& m, int64_t N, Prep& p, HOps<T>& ops, std::vector<HFactors>& fac,
                void* ws, size_t base_used_hint, TOut* H, bool same_type) {
@@ -481,20 +494,7 @@ void run_exact(Exec& ex, const Model& m, int64_t N, Prep& p, HOps<T>& ops, std::
   for (int mm = 2; mm <= L; ++mm) {
     HFactors& f = fac[mm];
     const int64_t Tm = m.T[mm - 1];
-    // forward factors
-    if (mm < L) factor_first(ex, p.W64[mm - 1], m.T[mm], Tm, p.D1T[mm], N, f.F[mm + 1]);
-    for (int l = mm + 2; l <= L; ++l) {
-      factor_rowscale(ex, f.F[l - 1], m.T[l - 2], Tm, p.D1T[l - 1], N, f.K[l - 1]);
-      gemm_rm<double>(ex, false, false, m.T[l - 1], Tm * N, m.T[l - 2], 1.0, p.W64[l - 2], m.T[l - 2],
-                      f.K[l - 1], Tm * N, 0.0, f.F[l], Tm * N);
-    }
-    // backward factors
-    factor_softmax(ex, mm < L ? f.F[L] : nullptr, m.T[L - 1], Tm, p.PT, N, f.G[L]);
-    for (int l = L - 1; l >= mm; --l) {
-      gemm_rm<double>(ex, true, false, m.T[l - 1], Tm * N, m.T[l], 1.0, p.W64[l - 1], m.T[l - 1], f.G[l + 1],
-                      Tm * N, 0.0, f.G[l], Tm * N);
-      factor_combine(ex, f.G[l], m.T[l - 1], Tm, p.D1T[l], p.CT[l], l == mm ? nullptr : f.F[l], N);
-    }
+    compute_factors(ex, m, N, p, f, mm);
     // operand-precision weights
     std::vector<const T*> Gw(L + 1, nullptr), Kw(L + 1, nullptr);
     const T* D1w = nullptr;
@@ -707,6 +707,8 @@ hess_status hess_workspace_size(hess_ctx* ctx, int op, const hess_mlp* mlp, cons
     case HESS_OP_PREDVAR:
       if ((s = validate_mlp(ctx, mlp, m, false)) != HESS_OK) return s;
       return predvar_workspace(ctx, m, prec, arg, bytes);
+    case HESS_OP_BATCHED:
+      return batched_workspace(ctx, arg, mlp, d, bytes);
   }
   return fail(ctx, HESS_E_ARG, "unknown op");
 }
@@ -786,3 +788,9 @@ hess_status hess_exact(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, i
 }
 
 }  // extern "C"
+
+namespace hs {
+template KrgSide<float> side_layer<float>(const Model&, int, const float*, int64_t, const float*, int64_t);
+template void plan_opg_ops<float>(Arena&, const Model&, int64_t, const Prep&, OpgBufs<float>&);
+template void cast_ops<float>(Exec&, const Model&, const Prep&, OpgBufs<float>&);
+}  // namespace hs

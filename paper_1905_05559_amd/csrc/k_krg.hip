@@ -37,17 +37,42 @@ __device__ __forceinline__ int64_t flat_index(int32_t perm, int64_t off, int32_t
   return j < Tin ? off + i * Tin + j : off + (int64_t)Tout * Tin + i;
 }
 
-__device__ __forceinline__ void tile_of(int64_t t, bool symmetric, int64_t tiles_c, int64_t& tr, int64_t& tc) {
-  if (symmetric) {
-    int64_t r = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while (r * (r + 1) / 2 > t) --r;
-    while ((r + 1) * (r + 2) / 2 <= t) ++r;
-    tr = r;
-    tc = t - r * (r + 1) / 2;
-  } else {
-    tr = t / tiles_c;
-    tc = t % tiles_c;
+// Grouped tile order: consecutive tile ids walk GROUP row panels column by column, so
+// the ~64 tiles an XCD runs at once share 8 row panels and 8 column panels in its L2
+// instead of one row panel and 64 column panels.  Symmetric blocks enumerate only
+// tiles with tc <= tr: group g (rows gG .. gG+Gg-1) holds gG full columns of Gg tiles
+// and then a lower triangle of Gg columns.
+constexpr int64_t GROUP = 8;
+
+__device__ __forceinline__ void tile_of(int64_t t, bool symmetric, int64_t tiles_c, int64_t tiles_r, int64_t& tr,
+                                        int64_t& tc) {
+  if (!symmetric) {
+    const int64_t g = t / (GROUP * tiles_c), u = t - g * GROUP * tiles_c;
+    const int64_t Gg = min(GROUP, tiles_r - g * GROUP);
+    tc = u / Gg;
+    tr = g * GROUP + u % Gg;
+    return;
   }
+  // tiles before group g (all full): G^2 g (g - 1) / 2 + g G (G + 1) / 2
+  auto before = [](int64_t g) { return GROUP * GROUP * g * (g - 1) / 2 + g * GROUP * (GROUP + 1) / 2; };
+  int64_t g = (int64_t)(sqrt(2.0 * (double)t) / (double)GROUP);
+  while (g > 0 && before(g) > t) --g;
+  while (before(g + 1) <= t && (g + 1) * GROUP < tiles_r) ++g;
+  int64_t u = t - before(g);
+  const int64_t Gg = min(GROUP, tiles_r - g * GROUP), r0 = g * GROUP;
+  if (u < r0 * Gg) {
+    tc = u / Gg;
+    tr = r0 + u % Gg;
+    return;
+  }
+  u -= r0 * Gg;
+  int64_t c = 0;
+  while (u >= Gg - c) {
+    u -= Gg - c;
+    ++c;
+  }
+  tc = r0 + c;
+  tr = r0 + c + u;
 }
 
 template <typename TOut>
@@ -58,24 +83,32 @@ __device__ __forceinline__ void store_out(TOut* out, int64_t idx, double v, int3
     out[idx] = (TOut)v;
 }
 
+template <typename T, int WMODE, int KC, int STAGES>
+struct KrgSmem {
+  static constexpr int KP = KC + 4;
+  static constexpr int WSZ = (WMODE == KRG_RANK1) ? 4 : MAXU * MAXU * KC;
+  static constexpr int A = 0, B = STAGES * BM * KP, W = B + STAGES * BN * KP;
+  static constexpr int SIZE = W + STAGES * WSZ;
+};
+
+// One 128 x 128 output tile t of the contraction described by `a` (smem: KrgSmem::SIZE elements).
 template <typename T, typename TOut, int WMODE, bool SYM, int KC, int STAGES>
-// FP32 with K chunk 16 is held to two wavefronts per SIMD (228 registers, no spills):
-// the kernel is latency-sensitive and the second wavefront hides the staging loads.
-__global__ __launch_bounds__(256, (sizeof(T) == 4 && KC == 16) ? 2 : 1) void krg_kernel(KrgArgs<T, TOut> a,
-                                                                                         int64_t tiles_c,
-                                                                                         int64_t ntiles) {
+__device__ __forceinline__ void krg_tile(const KrgArgs<T, TOut>& a, int64_t t, int64_t tiles_c, T* smem) {
   using Op = MfmaOp<T>;
   using acc_t = typename Op::acc_t;
-  constexpr int KP = KC + 4;
-  constexpr int WSZ = (WMODE == KRG_RANK1) ? 4 : MAXU * MAXU * KC;
-  __shared__ __attribute__((aligned(16))) T As[STAGES][BM * KP];
-  __shared__ __attribute__((aligned(16))) T Bs[STAGES][BN * KP];
-  __shared__ __attribute__((aligned(16))) T Ws[STAGES][WSZ];
+  using SM = KrgSmem<T, WMODE, KC, STAGES>;
+  constexpr int KP = SM::KP;
+  constexpr int WSZ = SM::WSZ;
+  T* As_ = smem + SM::A;
+  T* Bs_ = smem + SM::B;
+  T* Ws_ = smem + SM::W;
+  auto As = [&](int s) { return As_ + s * BM * KP; };
+  auto Bs = [&](int s) { return Bs_ + s * BN * KP; };
+  auto Ws = [&](int s) { return Ws_ + s * WSZ; };
 
-  const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
-  if (t < 0) return;
   int64_t tr, tc;
-  tile_of(t, SYM, tiles_c, tr, tc);
+  const int64_t tiles_r = ((int64_t)a.r.n_units * a.r.pad + BM - 1) / BM;
+  tile_of(t, SYM, tiles_c, tiles_r, tr, tc);
   const int64_t r0 = tr * BM, c0 = tc * BN;
   const int64_t ur_lo = r0 / a.r.pad, uc_lo = c0 / a.c.pad;
   const int64_t ur_hi = min((int64_t)a.r.n_units - 1, (r0 + BM - 1) / a.r.pad);
@@ -142,8 +175,8 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && KC == 16) ? 2 : 1) void krg
   auto store = [&](int s) {
 #pragma unroll
     for (int i = 0; i < SK; ++i) {
-      As[s][srow * KP + sk0 + i] = ra[i];
-      Bs[s][srow * KP + sk0 + i] = rbv[i];
+      As(s)[srow * KP + sk0 + i] = ra[i];
+      Bs(s)[srow * KP + sk0 + i] = rbv[i];
     }
     if (WMODE != KRG_RANK1) {
 #pragma unroll
@@ -151,7 +184,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && KC == 16) ? 2 : 1) void krg
         const int e = tid + i * 256;
         if (e < nw) {
           const int kk = e % KC, p = e / KC;
-          Ws[s][((p / nuc) * MAXU + (p % nuc)) * KC + kk] = rw[i];
+          Ws(s)[((p / nuc) * MAXU + (p % nuc)) * KC + kk] = rw[i];
         }
       }
     }
@@ -184,11 +217,11 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && KC == 16) ? 2 : 1) void krg
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) av[i][u] = As[s][(wr * 64 + i * 16 + row) * KP + ko + u];
+        for (int u = 0; u < 4; ++u) av[i][u] = As(s)[(wr * 64 + i * 16 + row) * KP + ko + u];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) bv[j][u] = Bs[s][(wc * 64 + j * 16 + row) * KP + ko + u];
+        for (int u = 0; u < 4; ++u) bv[j][u] = Bs(s)[(wc * 64 + j * 16 + row) * KP + ko + u];
       if (WMODE == KRG_RANK1) {
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -201,7 +234,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && KC == 16) ? 2 : 1) void krg
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const bool live = WMODE != KRG_PAIR_DIAG || (pu[i] + ur_lo) == (pc[0] + uc_lo);
-          const T* wp = &Ws[s][(pu[i] * MAXU + pc[0]) * KC + ko];
+          const T* wp = &Ws(s)[(pu[i] * MAXU + pc[0]) * KC + ko];
 #pragma unroll
           for (int u = 0; u < 4; ++u) w[i][u] = live ? wp[u] : T(0);
         }
@@ -219,7 +252,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && KC == 16) ? 2 : 1) void krg
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             if (WMODE == KRG_PAIR_DIAG && (pu[i] + ur_lo) != (pc[j] + uc_lo)) continue;
-            const T* wp = &Ws[s][(pu[i] * MAXU + pc[j]) * KC + ko];
+            const T* wp = &Ws(s)[(pu[i] * MAXU + pc[j]) * KC + ko];
 #pragma unroll
             for (int u = 0; u < 4; ++u) acc[i][j] = Op::mma(av[i][u], bv[j][u] * wp[u], acc[i][j]);
           }
@@ -279,6 +312,53 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && KC == 16) ? 2 : 1) void krg
     }
 }
 
+// FP32 with K chunk 16 is held to two wavefronts per SIMD (228 registers, no spills):
+// the kernel is latency-sensitive and the second wavefront hides the staging loads.
+template <typename T, typename TOut, int WMODE, bool SYM, int KC, int STAGES>
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && KC == 16) ? 2 : 1) void krg_kernel(KrgArgs<T, TOut> a,
+                                                                                         int64_t tiles_c,
+                                                                                         int64_t ntiles) {
+  __shared__ __attribute__((aligned(16))) T smem[KrgSmem<T, WMODE, KC, STAGES>::SIZE];
+  const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
+  if (t < 0) return;
+  krg_tile<T, TOut, WMODE, SYM, KC, STAGES>(a, t, tiles_c, smem);
+}
+
+// Persistent form for many contractions (several networks): every workgroup takes the
+// next tile from a global counter until all tiles of all jobs are done; a tile's job is
+// found by binary search over the jobs' first-tile offsets.  Each tile is computed by
+// exactly one workgroup, so results do not depend on the schedule.
+__global__ __launch_bounds__(256, 2) void krg_persistent(const KrgJob* jobs, int njobs, int64_t total,
+                                                         unsigned long long* counter) {
+  constexpr int SZ = KrgSmem<float, KRG_PAIR_FULL, 16, 1>::SIZE;
+  __shared__ __attribute__((aligned(16))) float smem[SZ];
+  __shared__ int64_t tsh;
+  for (;;) {
+    if (threadIdx.x == 0) tsh = (int64_t)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const int64_t t = tsh;
+    __syncthreads();
+    if (t >= total) break;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (jobs[mid].first <= t) lo = mid; else hi = mid - 1;
+    }
+    const KrgJob& J = jobs[lo];
+    const int64_t lt = t - J.first;
+    switch (J.mode * 2 + (J.a.symmetric ? 1 : 0)) {
+      case KRG_RANK1 * 2 + 0: krg_tile<float, float, KRG_RANK1, false, 16, 1>(J.a, lt, J.tiles_c, smem); break;
+      case KRG_RANK1 * 2 + 1: krg_tile<float, float, KRG_RANK1, true, 16, 1>(J.a, lt, J.tiles_c, smem); break;
+      case KRG_PAIR_FULL * 2 + 0: krg_tile<float, float, KRG_PAIR_FULL, false, 16, 1>(J.a, lt, J.tiles_c, smem); break;
+      case KRG_PAIR_FULL * 2 + 1: krg_tile<float, float, KRG_PAIR_FULL, true, 16, 1>(J.a, lt, J.tiles_c, smem); break;
+      default: krg_tile<float, float, KRG_PAIR_DIAG, false, 16, 1>(J.a, lt, J.tiles_c, smem); break;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_counter(unsigned long long* c) { *c = 0ull; }
+
 template <typename T, typename TOut, int KC, int STAGES>
 void launch_cfg(Exec& ex, const KrgArgs<T, TOut>& a, dim3 grid, int64_t tc, int64_t nt) {
 #define KRG_LAUNCH(MODE, SYMV) \
@@ -334,6 +414,27 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
       default: launch_cfg<T, TOut, 32, 2>(ex, a, grid, tc, nt); break;
     }
   }
+  prof_end(ex, tok);
+}
+
+int64_t krg_tiles(const KrgArgs<float, float>& a, int64_t* tiles_c) {
+  const int64_t rows = (int64_t)a.r.n_units * a.r.pad, cols = (int64_t)a.c.n_units * a.c.pad;
+  const int64_t tr = (rows + BM - 1) / BM, tc = (cols + BN - 1) / BN;
+  *tiles_c = tc;
+  return a.symmetric ? tr * (tr + 1) / 2 : tr * tc;
+}
+
+void krg_persistent_launch(Exec& ex, const KrgJob* jobs_dev, int njobs, int64_t total, unsigned long long* counter,
+                           double flops, double bytes) {
+  if (total <= 0) return;
+  if (!launch_ok(ex)) return;
+  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, ex.stream, counter);
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t grid = std::min<int64_t>(total, (int64_t)cus * 2);
+  const int tok = prof_begin(ex, "krg_f32_persistent", flops, bytes);
+  hipLaunchKernelGGL(krg_persistent, dim3((unsigned)grid), dim3(256), 0, ex.stream, jobs_dev, njobs, total, counter);
   prof_end(ex, tok);
 }
 

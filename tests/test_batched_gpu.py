@@ -1,0 +1,83 @@
+"""GPU tests of hess_batched: many networks of uneven shapes in one call.
+
+Each network's H and OPG must equal the single-network entry points bitwise (same
+tile arithmetic, different schedule) and the FP64 oracle within the FP32 tolerance.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp
+from paper_1905_05559_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_05559_amd import api as A
+    return A
+
+
+def _dev(api, w):
+    model = api.MLP.from_workload(w, dtype=torch.float32)
+    return model, torch.from_numpy(w.X).cuda(), torch.from_numpy(w.Y).cuda()
+
+
+def _relf(a, r):
+    return float(np.linalg.norm(a - r) / np.linalg.norm(r))
+
+
+NETS = [([5, 3], [], 37, 1), ([4, 8, 3], ["tanh"], 64, 2), ([33, 40, 10], ["tanh"], 129, 3),
+        ([7, 20, 13, 5], ["sigmoid", "relu"], 100, 4), ([150, 30, 4], ["sigmoid"], 50, 5),
+        ([12, 17, 9, 3], ["tanh", "tanh"], 333, 6)]
+
+
+def test_batched_matches_single_and_oracle(api):
+    ws = [workloads.mlp_gaussian(T, a, N, s, dtype="float32") for T, a, N, s in NETS]
+    devs = [_dev(api, w) for w in ws]
+    Hs, Gs = api.hess_batched([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs])
+    for w, (model, X, Y), Hb, Gb in zip(ws, devs, Hs, Gs):
+        Hs1 = api.hess_exact(model, X, Y, "f32")
+        Gs1 = api.hess_opg(model, X, Y, "f32")
+        assert torch.equal(Hb, Hs1) and torch.equal(Gb, Gs1), w.T
+        om = mlp.model_from(w.T, w.acts, w.W, w.b)
+        Xo, Yo = w.X.astype(np.float64), w.Y.astype(np.float64)
+        eh = _relf(Hb.double().cpu().numpy(), mlp.hessian(om, Xo, Yo))
+        eg = _relf(Gb.double().cpu().numpy(), mlp.opg(om, Xo, Yo))
+        print("batched %-16s H relF %.2e  OPG relF %.2e" % (w.T, eh, eg), flush=True)
+        assert eh <= 1e-5 and eg <= 1e-5
+
+
+def test_batched_partial_outputs(api):
+    ws = [workloads.mlp_gaussian(T, a, N, s, dtype="float32") for T, a, N, s in NETS[:3]]
+    devs = [_dev(api, w) for w in ws]
+    Hs, Gs = api.hess_batched([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs], with_G=False)
+    assert Gs is None
+    for (model, X, Y), Hb in zip(devs, Hs):
+        assert torch.equal(Hb, api.hess_exact(model, X, Y, "f32"))
+
+
+def test_batched_model_distribution_subset(api):
+    """Networks drawn from the 256-network distribution (the smallest 6 of the first 40)."""
+    cand = []
+    for m in range(40):
+        w = workloads.batched_model(m)
+        cand.append((w.P, m, w))
+    cand.sort()
+    ws = [w for _, _, w in cand[:6]]
+    devs = [_dev(api, w) for w in ws]
+    Hs, Gs = api.hess_batched([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs])
+    for w, (model, X, Y), Hb, Gb in zip(ws, devs, Hs, Gs):
+        assert torch.equal(Hb, api.hess_exact(model, X, Y, "f32"))
+        assert torch.equal(Gb, api.hess_opg(model, X, Y, "f32"))
+        om = mlp.model_from(w.T, w.acts, w.W, w.b)
+        Xo, Yo = w.X.astype(np.float64), w.Y.astype(np.float64)
+        cols = list(range(0, w.P, max(1, w.P // 24)))[:24]
+        ref = mlp.hessian_cols(om, Xo, Yo, 0, w.P, block=256)[:, cols] if w.P <= 3000 else None
+        if ref is not None:
+            e = _relf(Hb.double().cpu().numpy()[:, cols], ref)
+            print("batch model %s P=%d N=%d: sampled H relF %.2e" % (w.T, w.P, w.N, e), flush=True)
+            assert e <= 1e-5
