@@ -209,6 +209,51 @@ hess_status hess_predvar(hess_ctx* ctx, const hess_mlp* m, int64_t K, const doub
 hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* models, const hess_data* datas, int prec,
                          void* const* H, void* const* G, void* ws, size_t ws_bytes);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of curvature requests on one device.
+ * A server owns n_slots worker slots (each with its own context and HIP stream)
+ * and carves every request's workspace from the caller's device pool.  A request is
+ * admitted when a slot is free and its footprint fits in the unused pool, so requests
+ * that arrive while others run overlap with them on the device.  With coalesce = 1 a
+ * slot that takes a damped query also takes the queued queries against the same model
+ * and eigenpairs (up to 4096 inputs) and answers them with one hess_predvar call; each
+ * query is computed independently, so its result does not depend on the mix.
+ * Requests are computed in FP32 (H, OPG, matrix-free top-k) or as hess_predvar.
+ * The caller keeps every device buffer a request names alive until hess_server_wait
+ * returns for it; host arrays of the model are copied at submission.
+ * --------------------------------------------------------------------------- */
+typedef struct hess_server hess_server;
+typedef enum { HESS_REQ_FULL = 0, HESS_REQ_TOPK = 1, HESS_REQ_PREDVAR = 2 } hess_req_kind;
+typedef struct {
+  int32_t kind;          /* hess_req_kind */
+  hess_mlp model;
+  hess_data data;        /* FULL, TOPK: the network's data set */
+  void* H;               /* FULL: P x P FP32 output, or NULL */
+  void* G;               /* FULL: P x P FP32 OPG output, or NULL */
+  int64_t K;             /* TOPK: pairs wanted; PREDVAR: pairs held in lambda, Q */
+  double* lambda;        /* TOPK: output (K); PREDVAR: input (K), device FP64 */
+  double* Q;             /* TOPK: output (K x P); PREDVAR: input (K x P), device FP64 */
+  double tol;            /* TOPK: relative residual tolerance */
+  uint64_t seed;         /* TOPK: start-block seed */
+  double delta;          /* PREDVAR: damping */
+  int64_t nq;            /* PREDVAR: number of query inputs */
+  const void* Xq;        /* PREDVAR: nq x T_1 (model dtype), device */
+  const int32_t* cls;    /* PREDVAR: classes (device) or NULL for arg-max */
+  double* s;             /* PREDVAR: nq outputs, device FP64 */
+} hess_request;
+
+hess_status hess_server_create(hess_server** srv, int device, int n_slots, void* pool, size_t pool_bytes,
+                               int coalesce);
+/* Queue a request; HESS_E_BUDGET if its footprint exceeds the whole pool. */
+hess_status hess_server_submit(hess_server* srv, const hess_request* req, uint64_t* id);
+/* Block until request `id` completes; returns its status and the submit-to-result
+ * latency (results in device memory) in milliseconds. */
+hess_status hess_server_wait(hess_server* srv, uint64_t id, double* latency_ms);
+/* out[0..3] = submitted, completed, failed, coalesced query batches. */
+hess_status hess_server_stats(hess_server* srv, int64_t* out);
+/* Finish all queued requests, then stop the slots. */
+hess_status hess_server_destroy(hess_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,7 @@ EXPORTS = (
     "hess_create", "hess_destroy", "hess_status_str", "hess_last_error", "hess_set_option",
     "hess_num_params", "hess_workspace_size", "hess_exact", "hess_opg", "hess_hvp",
     "hess_topk_eig", "hess_predvar", "hess_profile_read", "hess_profile_reset", "hess_batched",
+    "hess_server_create", "hess_server_submit", "hess_server_wait", "hess_server_stats", "hess_server_destroy",
 )
 
 
@@ -45,6 +46,12 @@ class HessEigOpts(C.Structure):
 class HessEigInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("applies", C.c_int32), ("max_rel_residual", C.c_double),
                 ("shift_used", C.c_double)]
+
+
+class HessRequest(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("model", HessMlp), ("data", HessData), ("H", C.c_void_p), ("G", C.c_void_p),
+                ("K", C.c_int64), ("lam", C.c_void_p), ("Q", C.c_void_p), ("tol", C.c_double), ("seed", C.c_uint64),
+                ("delta", C.c_double), ("nq", C.c_int64), ("Xq", C.c_void_p), ("cls", C.c_void_p), ("s", C.c_void_p)]
 
 
 class HessProfEntry(C.Structure):
@@ -83,6 +90,11 @@ def load(path: str = LIB_PATH):
         "hess_profile_read": (C.c_int, [vp, C.POINTER(HessProfEntry), C.c_int]),
         "hess_profile_reset": (st, [vp]),
         "hess_batched": (st, [vp, i64, pm, pd, C.c_int, C.POINTER(vp), C.POINTER(vp), vp, C.c_size_t]),
+        "hess_server_create": (st, [C.POINTER(vp), C.c_int, C.c_int, vp, C.c_size_t, C.c_int]),
+        "hess_server_submit": (st, [vp, C.POINTER(HessRequest), C.POINTER(C.c_uint64)]),
+        "hess_server_wait": (st, [vp, C.c_uint64, C.POINTER(C.c_double)]),
+        "hess_server_stats": (st, [vp, C.POINTER(C.c_int64)]),
+        "hess_server_destroy": (st, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

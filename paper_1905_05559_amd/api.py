@@ -291,3 +291,80 @@ def hess_batched(models: List[MLP], Xs: List[torch.Tensor], Ys: List[torch.Tenso
     ws = ctx.workspace(nb.value)
     ctx._check(ctx.lib.hess_batched(ctx.h, M, ms, ds, L.PREC["f32"], hp, gp, ws.data_ptr(), ws.numel()))
     return Hs, Gs
+
+
+class Server:
+    """Continuous-batching server of curvature requests (hess_server_* in include/hess.h).
+
+    pool_bytes of device memory (a torch buffer owned by this object) back every
+    request's workspace; n_slots worker slots run requests concurrently on their own
+    streams; coalesce merges queued damped queries against the same target."""
+
+    REQ = {"full": 0, "topk": 1, "predvar": 2}
+
+    def __init__(self, pool_bytes: int, n_slots: int = 4, coalesce: bool = True, device: int = 0):
+        self.lib = L.load()
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda:%d" % device)
+        h = C.c_void_p()
+        st = self.lib.hess_server_create(C.byref(h), device, int(n_slots), C.c_void_p(self.pool.data_ptr()),
+                                         self.pool.numel(), 1 if coalesce else 0)
+        if st != L.HESS_OK:
+            raise HessError(st, "hess_server_create failed")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, kind: str, model: MLP, X=None, Y=None, H=None, G=None, K=0, lam=None, Q=None, tol=1e-5,
+               seed=0, delta=0.0, Xq=None, cls=None, s=None) -> int:
+        r = L.HessRequest()
+        r.kind = self.REQ[kind]
+        m = model.struct()
+        r.model = m
+        keep = [m, model]
+        if X is not None:
+            d = _data(X, Y)
+            r.data = d
+            keep.append(d)
+        r.H = H.data_ptr() if H is not None else None
+        r.G = G.data_ptr() if G is not None else None
+        r.K = int(K)
+        r.lam = lam.data_ptr() if lam is not None else None
+        r.Q = Q.data_ptr() if Q is not None else None
+        r.tol = float(tol)
+        r.seed = int(seed)
+        r.delta = float(delta)
+        if Xq is not None:
+            r.nq = int(Xq.shape[0])
+            r.Xq = Xq.data_ptr()
+        r.cls = cls.data_ptr() if cls is not None else None
+        r.s = s.data_ptr() if s is not None else None
+        keep += [H, G, lam, Q, Xq, cls, s, X, Y]
+        rid = C.c_uint64()
+        st = self.lib.hess_server_submit(self.h, C.byref(r), C.byref(rid))
+        if st != L.HESS_OK:
+            raise HessError(st, "submit failed")
+        self._keep[rid.value] = keep
+        return rid.value
+
+    def wait(self, rid: int):
+        """Returns (status name, latency in ms)."""
+        lat = C.c_double()
+        st = self.lib.hess_server_wait(self.h, C.c_uint64(rid), C.byref(lat))
+        self._keep.pop(rid, None)
+        return L.STATUS_NAMES.get(st, str(st)), lat.value
+
+    def stats(self) -> dict:
+        a = (C.c_int64 * 4)()
+        self.lib.hess_server_stats(self.h, a)
+        return {"submitted": a[0], "completed": a[1], "failed": a[2], "coalesced_batches": a[3]}
+
+    def close(self):
+        if self.h:
+            self.lib.hess_server_destroy(self.h)
+            self.h = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
