@@ -237,6 +237,27 @@ def opg_tile(model: Model, X, Y, rows: Sequence[int], cols: Sequence[int]):
     return Jr.T @ Jc / X.shape[0]
 
 
+def opg_cols(model: Model, X, Y, cols: Sequence[int]):
+    """Columns OPG[:, cols] = J^T J[:, cols] / N without forming J (Sec. 3).
+
+    For a weight vector v = J[:, c], J^T v is sum_n v_n grad C_n; its block for layer l
+    is (delta^(l) * v)^T [A^(l-1), 1] (the per-example outer products of the gradient
+    definition, summed).  Returns P x len(cols).
+    """
+    _, A, delta, _ = backprop(model, X, Y)
+    Jc = jacobian_cols(model, X, Y, cols)
+    N = X.shape[0]
+    out = np.empty((num_params(model.T), len(cols)))
+    for c in range(len(cols)):
+        parts = []
+        for l in range(2, model.L + 1):
+            dv = delta[l] * Jc[:, c:c + 1]                   # rows v_n delta^(l)_n
+            parts.append((dv.T @ A[l - 1]).reshape(-1))      # W^(l-1) block, row-major
+            parts.append(dv.sum(axis=0))                     # b^(l) block
+        out[:, c] = np.concatenate(parts)
+    return out / N
+
+
 # ---------------------------------------------------------------------------
 # Hessian-vector products by the R-operator (Appendix A.1, Sec. 5.1).
 # ---------------------------------------------------------------------------

@@ -112,6 +112,8 @@ struct KrgJob {
   int32_t mode;            // KRG_* weight mode
 };
 int64_t krg_tiles(const KrgArgs<float, float>& a, int64_t* tiles_c);
+// Whether a contraction can run in the persistent launch (its copy offsets fit 32 bits).
+bool krg_persistent_fits(const KrgArgs<float, float>& a);
 void krg_persistent_launch(Exec& ex, const KrgJob* jobs_dev, int njobs, int64_t total, unsigned long long* counter,
                            double flops, double bytes);
 // Tile-configuration variants (tuning and tests): 1..4 = (K chunk, LDS stages) in

@@ -160,7 +160,12 @@ extern "C" hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* mo
   // per-network passes and FP32 factors; tile jobs
   std::vector<KrgJob> jobsA, jobsB;
   double flopsA = 0, flopsB = 0;
+  std::vector<KrgArgs<float, float>> missA, missB;  // contractions too large for the persistent launch
   auto add = [&](std::vector<KrgJob>& v, const KrgArgs<float, float>& a, double& flops) {
+    if (!krg_persistent_fits(a)) {
+      (&v == &jobsA ? missA : missB).push_back(a);
+      return;
+    }
     KrgJob j;
     j.a = a;
     j.mode = a.wmode;
@@ -272,9 +277,11 @@ extern "C" hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* mo
     hipMemcpyAsync(bp.jobs, jobsA.data(), nA * sizeof(KrgJob), hipMemcpyHostToDevice, ex.stream);
     krg_persistent_launch(ex, bp.jobs, (int)nA, totA, bp.counter, flopsA, 0.0);
   }
+  for (const auto& a : missA) krg<float, float>(ex, a);
   if (nB) {
     hipMemcpyAsync(bp.jobs + nA, jobsB.data(), nB * sizeof(KrgJob), hipMemcpyHostToDevice, ex.stream);
     krg_persistent_launch(ex, bp.jobs + nA, (int)nB, totB, bp.counter, flopsB, 0.0);
   }
+  for (const auto& a : missB) krg<float, float>(ex, a);
   return finish(ex, "hess_batched");
 }

@@ -22,6 +22,9 @@
 // one is read and one barrier per chunk suffices.  Symmetric blocks enumerate only
 // the lower triangle of tiles and mirror every stored entry, so the result is
 // exactly symmetric.
+#include <algorithm>
+#include <type_traits>
+
 #include "mfma.h"
 
 namespace hs {
@@ -312,6 +315,338 @@ __device__ __forceinline__ void krg_tile(const KrgArgs<T, TOut>& a, int64_t t, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 tile with direct HBM -> LDS staging (buffer_load ... lds).
+//
+// The operands never pass through registers on their way to LDS: every chunk of
+// DKC examples is copied by the vector memory unit straight into one of DST LDS
+// stages, so the K loop issues only the copies, the LDS operand reads, the pair
+// weight products and the MFMAs.  A stage holds A and B k-major (As[k][r], row
+// stride DLD floats; DLD = 132 puts the four lane groups of a 16x16x4 MFMA step,
+// which read k = 4q + s, on disjoint LDS banks) and the per-chunk pair weights
+// (PAIR_FULL: [row unit][column unit][k], PAIR_DIAG: [unit][k], RANK1: the row
+// and column scale factors [unit][k]).  Each lane copies one float: its address
+// clamps the slot to the unit's valid range (so every read stays inside the
+// source row), and the buffer range check (num_records = the chunk's valid
+// examples) turns examples past N into zeros.  Weights read past N are replaced
+// by zeros in registers.  Units beyond a side's last unit are clamped: they only
+// feed outputs that the epilogue discards.
+//
+// Wavefront tile 64 x 64 = 4 x 4 MFMA blocks.  When the wavefront's 64 columns lie
+// in one column unit (the common case for wide units) the pair weight depends on
+// the row only: A is read interleaved (block i holds rows 4 * row16 + i, so one
+// 128-bit read gives all four blocks) and the weight is applied to A.  Otherwise A
+// blocks are 16 consecutive rows (one row unit each) and the weight, which then
+// depends on the block's row unit and the lane's column unit, is applied to B.
+// B is always read interleaved (lane columns 4 * col16 + j, one column unit).
+// ---------------------------------------------------------------------------
+constexpr int DKC = 16, DLD = 132, DST = 3;
+
+template <int WMODE, int MAXU>
+struct DmaSmem {
+  static constexpr int AB = DKC * DLD;
+  static constexpr int WN1 = WMODE == KRG_PAIR_FULL ? MAXU * MAXU * DKC : MAXU * DKC;  // floats per weight array
+  static constexpr int NW = WMODE == KRG_RANK1 ? 2 : 1;                              // weight arrays
+  static constexpr int WI1 = (WN1 + 63) / 64;                                         // copies per array
+  static constexpr int WI = NW * WI1;
+  static constexpr int STAGE = 2 * AB + NW * WN1;
+  static constexpr int SIZE = DST * STAGE;
+  // copies every wavefront issues per chunk: 8 for A, 8 for B, and its share of the
+  // weight copies (a lower bound when RANK1 scale factors may be absent)
+  static constexpr int VMC = 16 + (WMODE == KRG_RANK1 ? 0 : WI / 4);
+  static constexpr int WPW = (WI + 3) / 4;  // weight copies one wavefront may issue
+};
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+__device__ __forceinline__ int64_t mn64(int64_t x, int64_t y) { return x < y ? x : y; }
+
+// Raw buffer over `elems` (>= 0) floats from base; the byte count is capped below 2^31
+// (copy offsets are checked on the host to stay below the cap).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* base, int64_t elems) {
+  const uint64_t e = (uint64_t)elems;
+  const uint32_t nrec = e >= 0x1ffffffcull ? 0x7ffffff0u : (uint32_t)e * 4u;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)nrec, 0x00020000);
+}
+
+__device__ __forceinline__ void copy_lds(__amdgpu_buffer_rsrc_t r, float* dst, int voff) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr_t)dst, 4, voff, 0, 0, 0);
+}
+
+__device__ __forceinline__ void wait_vm(int n) {
+  // s_waitcnt vmcnt(n) with expcnt and lgkmcnt left free (gfx9 encoding)
+  switch (n) {
+    case 0: __builtin_amdgcn_s_waitcnt(0x0f70); break;
+    case 16: __builtin_amdgcn_s_waitcnt(0x4f70); break;
+    case 17: __builtin_amdgcn_s_waitcnt(0x4f71); break;
+    case 18: __builtin_amdgcn_s_waitcnt(0x4f72); break;
+    case 19: __builtin_amdgcn_s_waitcnt(0x4f73); break;
+    case 20: __builtin_amdgcn_s_waitcnt(0x4f74); break;
+    case 21: __builtin_amdgcn_s_waitcnt(0x4f75); break;
+    default: __builtin_amdgcn_s_waitcnt(0x0f70); break;
+  }
+}
+
+template <int WMODE, bool SYM, int MAXU>
+__device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int64_t t, int64_t tiles_c,
+                                             float* smem) {
+  using SM = DmaSmem<WMODE, MAXU>;
+  int64_t tr, tc;
+  const int64_t tiles_r = ((int64_t)a.r.n_units * a.r.pad + BM - 1) / BM;
+  tile_of(t, SYM, tiles_c, tiles_r, tr, tc);
+  const int64_t r0 = tr * BM, c0 = tc * BN;
+  const int ur_lo = (int)(r0 / a.r.pad), uc_lo = (int)(c0 / a.c.pad);
+  const int ur_hi = (int)min((int64_t)a.r.n_units - 1, (r0 + BM - 1) / a.r.pad);
+  const int uc_hi = (int)min((int64_t)a.c.n_units - 1, (c0 + BN - 1) / a.c.pad);
+  if (WMODE == KRG_PAIR_DIAG && (ur_hi < uc_lo || uc_hi < ur_lo)) return;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int row16 = lane & 15, q = lane >> 4;
+
+  // ---- per-lane copy offsets (bytes, relative to the chunk's base pointers) ----
+  int voffA[8], voffB[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int k = 4 * wave + (m >> 1);
+    const int64_t r = r0 + (m & 1) * 64 + lane, c = c0 + (m & 1) * 64 + lane;
+    const int sr = (int)mn64(r % a.r.pad, a.r.len - 1), sc = (int)mn64(c % a.c.pad, a.c.len - 1);
+    voffA[m] = (int)((k * a.r.ld + sr) * 4);
+    voffB[m] = (int)((k * a.c.ld + sc) * 4);
+  }
+  int voffW[SM::WPW];
+  bool wlive[SM::WPW];
+#pragma unroll
+  for (int x = 0; x < SM::WPW; ++x) {
+    const int g = wave + 4 * x;              // copy index over all weight arrays
+    const int arr = g / SM::WI1;             // RANK1: 0 = row scales, 1 = column scales
+    const int e = (g % SM::WI1) * 64 + lane;  // element within the array
+    wlive[x] = g < SM::WI && e < SM::WN1;
+    int off = 0;
+    if (WMODE == KRG_PAIR_FULL) {
+      const int p = e / DKC, k = e % DKC;
+      const int ur = min(ur_lo + p / MAXU, a.r.n_units - 1), uc = min(uc_lo + p % MAXU, a.c.n_units - 1);
+      off = (int)((((int64_t)(ur - ur_lo) * a.c.n_units + (uc - uc_lo)) * a.ldw + k) * 4);
+    } else if (WMODE == KRG_PAIR_DIAG) {
+      const int d = e / DKC, k = e % DKC;
+      const int u = min(ur_lo + d, min(a.r.n_units, a.c.n_units) - 1);
+      off = (int)(((int64_t)(u - ur_lo) * a.ldw + k) * 4);
+    } else {
+      const int d = e / DKC, k = e % DKC;
+      if (arr == 0) {
+        const int u = min(ur_lo + d, a.r.n_units - 1);
+        off = (int)((k * a.r.ld_scale + (u - ur_lo)) * 4);
+      } else {
+        const int u = min(uc_lo + d, a.c.n_units - 1);
+        off = (int)((k * a.c.ld_scale + (u - uc_lo)) * 4);
+      }
+    }
+    voffW[x] = off;
+  }
+  const bool has_sa = WMODE == KRG_RANK1 && a.r.scale != nullptr;
+  const bool has_sb = WMODE == KRG_RANK1 && a.c.scale != nullptr;
+  int64_t wtot = 0;  // elements of the weight buffer (for the range check)
+  if (WMODE == KRG_PAIR_FULL) wtot = ((int64_t)a.r.n_units * a.c.n_units - 1) * a.ldw + a.N;
+  if (WMODE == KRG_PAIR_DIAG) wtot = ((int64_t)min(a.r.n_units, a.c.n_units) - 1) * a.ldw + a.N;
+
+  // ---- one chunk's copies into stage st ----
+  auto issue = [&](int st, int64_t n0) {
+    const int kv = (int)mn64(DKC, a.N - n0);
+    float* S = smem + st * SM::STAGE;
+    const __amdgpu_buffer_rsrc_t ra = rsrc_of(a.r.src + n0 * a.r.ld, (int64_t)kv * a.r.ld);
+    const __amdgpu_buffer_rsrc_t rb = rsrc_of(a.c.src + n0 * a.c.ld, (int64_t)kv * a.c.ld);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) copy_lds(ra, S + (4 * wave + (m >> 1)) * DLD + (m & 1) * 64, voffA[m]);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) copy_lds(rb, S + SM::AB + (4 * wave + (m >> 1)) * DLD + (m & 1) * 64, voffB[m]);
+    float* W = S + 2 * SM::AB;
+    if (WMODE == KRG_PAIR_FULL || WMODE == KRG_PAIR_DIAG) {
+      const int64_t base = (WMODE == KRG_PAIR_FULL ? ((int64_t)ur_lo * a.c.n_units + uc_lo) : (int64_t)ur_lo) * a.ldw + n0;
+      const __amdgpu_buffer_rsrc_t rw = rsrc_of(a.wts + base, wtot - base);
+#pragma unroll
+      for (int x = 0; x < SM::WPW; ++x) {
+        const int g = wave + 4 * x;
+        if (g < SM::WI && wlive[x]) copy_lds(rw, W + g * 64, voffW[x]);
+      }
+    } else {
+      const __amdgpu_buffer_rsrc_t rsa =
+          rsrc_of(has_sa ? a.r.scale + n0 * a.r.ld_scale + ur_lo : a.r.src, has_sa ? (int64_t)kv * a.r.ld_scale - ur_lo : 0);
+      const __amdgpu_buffer_rsrc_t rsb =
+          rsrc_of(has_sb ? a.c.scale + n0 * a.c.ld_scale + uc_lo : a.c.src, has_sb ? (int64_t)kv * a.c.ld_scale - uc_lo : 0);
+#pragma unroll
+      for (int x = 0; x < SM::WPW; ++x) {
+        const int g = wave + 4 * x;
+        if (g >= SM::WI) continue;
+        const int arr = g / SM::WI1;
+        if ((arr == 0 ? has_sa : has_sb) && wlive[x]) copy_lds(arr == 0 ? rsa : rsb, W + g * 64 - arr * (SM::WI1 * 64 - SM::WN1), voffW[x]);
+      }
+    }
+  };
+
+  // weights of (row unit urel, column unit ucrel) for this lane's k = 4q .. 4q + 3
+  auto wt4 = [&](const float* W, int urel, int ucrel, int kv) -> f4_t {
+    f4_t w;
+    if (WMODE == KRG_PAIR_FULL) {
+      w = *(const f4_t*)&W[(urel * MAXU + ucrel) * DKC + 4 * q];
+    } else if (WMODE == KRG_PAIR_DIAG) {
+      w = (ur_lo + urel == uc_lo + ucrel) ? *(const f4_t*)&W[urel * DKC + 4 * q] : f4_t{0.f, 0.f, 0.f, 0.f};
+    } else {
+      w = f4_t{1.f, 1.f, 1.f, 1.f};
+      if (has_sa) w *= *(const f4_t*)&W[urel * DKC + 4 * q];
+      if (has_sb) w *= *(const f4_t*)&W[SM::WN1 + ucrel * DKC + 4 * q];
+    }
+    if (kv < DKC) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (4 * q + s >= kv) w[s] = 0.f;
+    }
+    return w;
+  };
+
+  f4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+  // column unit of this lane's interleaved columns (4 * col16 + j share it)
+  const int uc_lane = (int)((c0 + wc * 64 + 4 * row16) / a.c.pad) - uc_lo;
+  const bool one_cunit = (c0 + wc * 64) / a.c.pad == (c0 + wc * 64 + 63) / a.c.pad;
+  const int ur_lane = (int)((r0 + wr * 64 + 4 * row16) / a.r.pad) - ur_lo;  // rows 4 * row16 + i share it
+  int ur_blk[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) ur_blk[i] = (int)((r0 + wr * 64 + 16 * i) / a.r.pad) - ur_lo;
+
+  const int64_t nk = (a.N + DKC - 1) / DKC;
+  auto kloop = [&](auto oc) {
+    constexpr bool ONE = decltype(oc)::value;
+    if (nk > 0) issue(0, 0);
+    if (nk > 1) issue(1, DKC);
+    for (int64_t kc = 0; kc < nk; ++kc) {
+      if (kc + 1 < nk) wait_vm(SM::VMC); else wait_vm(0);
+      __builtin_amdgcn_s_barrier();
+      if (kc + 2 < nk) issue((int)((kc + 2) % DST), (kc + 2) * DKC);
+      const int st = (int)(kc % DST);
+      const float* As = smem + st * SM::STAGE;
+      const float* Bs = As + SM::AB;
+      const float* W = As + 2 * SM::AB;
+      const int kv = (int)mn64(DKC, a.N - kc * DKC);
+      if (ONE) {
+        const f4_t w = wt4(W, ur_lane, uc_lane, kv);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = 4 * q + s;
+          const f4_t av = *(const f4_t*)&As[k * DLD + wr * 64 + 4 * row16] * w[s];
+          const f4_t bv = *(const f4_t*)&Bs[k * DLD + wc * 64 + 4 * row16];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+      } else {
+        f4_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = wt4(W, ur_blk[i], uc_lane, kv);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = 4 * q + s;
+          const f4_t bv = *(const f4_t*)&Bs[k * DLD + wc * 64 + 4 * row16];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float av = As[k * DLD + wr * 64 + 16 * i + row16];
+            const f4_t bw = bv * w[i][s];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bw[j], acc[i][j], 0, 0, 0);
+          }
+        }
+      }
+    }
+  };
+  if (one_cunit) kloop(std::integral_constant<bool, true>());
+  else kloop(std::integral_constant<bool, false>());
+
+  // ---- epilogue: 1/N scale, flat indices, symmetric mirror ----
+  int64_t fcol[4];
+  bool cok[4];
+  int64_t ccomp[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t c = c0 + wc * 64 + 4 * row16 + j;
+    const int64_t uc = c / a.c.pad, sc = c % a.c.pad;
+    ccomp[j] = c;
+    cok[j] = uc < a.c.n_units && sc < a.c.len;
+    fcol[j] = cok[j] ? flat_index(a.c.perm, a.c.off, a.c.Tin, a.c.Tout, uc, sc) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = r0 + wr * 64 + (one_cunit ? 16 * q + 4 * v + i : 16 * i + 4 * q + v);
+      const int64_t ur = r / a.r.pad, sr = r % a.r.pad;
+      if (!(ur < a.r.n_units && sr < a.r.len)) continue;
+      const int64_t fr = flat_index(a.r.perm, a.r.off, a.r.Tin, a.r.Tout, ur, sr);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!cok[j]) continue;
+        if (SYM && r < ccomp[j]) continue;
+        const double val = a.scale * (double)acc[i][j][v];
+        store_out<float>(a.out, fr * a.ldo + fcol[j], val, a.accumulate);
+        if (a.mirror && !(SYM && r == ccomp[j])) store_out<float>(a.out, fcol[j] * a.ldo + fr, val, a.accumulate);
+      }
+    }
+}
+
+extern __shared__ __attribute__((aligned(16))) float dma_smem[];
+
+template <int WMODE, bool SYM, int MAXU>
+__global__ __launch_bounds__(256, 2) void krg_kernel_dma(KrgArgs<float, float> a, int64_t tiles_c, int64_t ntiles) {
+  const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
+  if (t < 0) return;
+  krg_tile_dma<WMODE, SYM, MAXU>(a, t, tiles_c, dma_smem);
+}
+
+// Units of one side that a 128-row tile can touch: pad >= 128 -> 2, >= 32 -> 5, else 9.
+int dma_maxu(int pad) { return pad >= 128 ? 2 : (pad >= 32 ? 5 : 9); }
+
+// The copy offsets of the LDS-staged tile are signed 32-bit byte offsets from
+// per-chunk base pointers; contractions whose offsets could exceed that use the
+// register-staged tile.
+bool dma_fits(const KrgArgs<float, float>& a, int maxu) {
+  const int64_t lim = 0x7fff0000;
+  if (a.r.len > a.r.ld || a.c.len > a.c.ld) return false;
+  if ((int64_t)DKC * std::max(a.r.ld, a.c.ld) * 4 > lim) return false;
+  if (a.wmode == KRG_PAIR_FULL && (((int64_t)(maxu - 1) * a.c.n_units + maxu) * a.ldw + DKC) * 4 > lim) return false;
+  if (a.wmode == KRG_PAIR_DIAG && ((int64_t)maxu * a.ldw + DKC) * 4 > lim) return false;
+  if (a.wmode == KRG_RANK1 && ((int64_t)DKC * std::max(a.r.ld_scale, a.c.ld_scale) + maxu) * 4 > lim) return false;
+  return true;
+}
+
+template <int WMODE, bool SYM, int MAXU>
+void launch_dma_one(Exec& ex, const KrgArgs<float, float>& a, dim3 grid, int64_t tc, int64_t nt) {
+  constexpr int bytes = DmaSmem<WMODE, MAXU>::SIZE * 4;
+  static const bool attr = [] {  // once per process (thread-safe static initialisation)
+    (void)hipFuncSetAttribute((const void*)krg_kernel_dma<WMODE, SYM, MAXU>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return true;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL((krg_kernel_dma<WMODE, SYM, MAXU>), grid, dim3(256), bytes, ex.stream, a, tc, nt);
+}
+
+template <int MAXU>
+void launch_dma(Exec& ex, const KrgArgs<float, float>& a, dim3 grid, int64_t tc, int64_t nt) {
+  if (a.wmode == KRG_RANK1) {
+    if (a.symmetric) launch_dma_one<KRG_RANK1, true, MAXU>(ex, a, grid, tc, nt);
+    else launch_dma_one<KRG_RANK1, false, MAXU>(ex, a, grid, tc, nt);
+  } else if (a.wmode == KRG_PAIR_FULL) {
+    if (a.symmetric) launch_dma_one<KRG_PAIR_FULL, true, MAXU>(ex, a, grid, tc, nt);
+    else launch_dma_one<KRG_PAIR_FULL, false, MAXU>(ex, a, grid, tc, nt);
+  } else {
+    launch_dma_one<KRG_PAIR_DIAG, false, MAXU>(ex, a, grid, tc, nt);
+  }
+}
+
 // FP32 with K chunk 16 is held to two wavefronts per SIMD (228 registers, no spills):
 // the kernel is latency-sensitive and the second wavefront hides the staging loads.
 template <typename T, typename TOut, int WMODE, bool SYM, int KC, int STAGES>
@@ -327,11 +662,13 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && KC == 16) ? 2 : 1) void krg
 // Persistent form for many contractions (several networks): every workgroup takes the
 // next tile from a global counter until all tiles of all jobs are done; a tile's job is
 // found by binary search over the jobs' first-tile offsets.  Each tile is computed by
-// exactly one workgroup, so results do not depend on the schedule.
+// exactly one workgroup, so results do not depend on the schedule; the tile code is
+// the single-launch one, so results equal single-contraction launches bitwise.
+constexpr int PERSIST_LDS = std::max(std::max(DmaSmem<KRG_PAIR_FULL, 9>::SIZE, DmaSmem<KRG_RANK1, 9>::SIZE),
+                                     DmaSmem<KRG_PAIR_DIAG, 9>::SIZE) * 4;
+
 __global__ __launch_bounds__(256, 2) void krg_persistent(const KrgJob* jobs, int njobs, int64_t total,
                                                          unsigned long long* counter) {
-  constexpr int SZ = KrgSmem<float, KRG_PAIR_FULL, 16, 1>::SIZE;
-  __shared__ __attribute__((aligned(16))) float smem[SZ];
   __shared__ int64_t tsh;
   for (;;) {
     if (threadIdx.x == 0) tsh = (int64_t)atomicAdd(counter, 1ull);
@@ -347,11 +684,11 @@ __global__ __launch_bounds__(256, 2) void krg_persistent(const KrgJob* jobs, int
     const KrgJob& J = jobs[lo];
     const int64_t lt = t - J.first;
     switch (J.mode * 2 + (J.a.symmetric ? 1 : 0)) {
-      case KRG_RANK1 * 2 + 0: krg_tile<float, float, KRG_RANK1, false, 16, 1>(J.a, lt, J.tiles_c, smem); break;
-      case KRG_RANK1 * 2 + 1: krg_tile<float, float, KRG_RANK1, true, 16, 1>(J.a, lt, J.tiles_c, smem); break;
-      case KRG_PAIR_FULL * 2 + 0: krg_tile<float, float, KRG_PAIR_FULL, false, 16, 1>(J.a, lt, J.tiles_c, smem); break;
-      case KRG_PAIR_FULL * 2 + 1: krg_tile<float, float, KRG_PAIR_FULL, true, 16, 1>(J.a, lt, J.tiles_c, smem); break;
-      default: krg_tile<float, float, KRG_PAIR_DIAG, false, 16, 1>(J.a, lt, J.tiles_c, smem); break;
+      case KRG_RANK1 * 2 + 0: krg_tile_dma<KRG_RANK1, false, 9>(J.a, lt, J.tiles_c, dma_smem); break;
+      case KRG_RANK1 * 2 + 1: krg_tile_dma<KRG_RANK1, true, 9>(J.a, lt, J.tiles_c, dma_smem); break;
+      case KRG_PAIR_FULL * 2 + 0: krg_tile_dma<KRG_PAIR_FULL, false, 9>(J.a, lt, J.tiles_c, dma_smem); break;
+      case KRG_PAIR_FULL * 2 + 1: krg_tile_dma<KRG_PAIR_FULL, true, 9>(J.a, lt, J.tiles_c, dma_smem); break;
+      default: krg_tile_dma<KRG_PAIR_DIAG, false, 9>(J.a, lt, J.tiles_c, dma_smem); break;
     }
     __syncthreads();
   }
@@ -400,7 +737,18 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
   const int tok = prof_begin(ex, names[sizeof(T) == 8][a.wmode][a.symmetric ? 1 : 0], 2.0 * a.N * entries,
                              src + wbytes + obytes);
   dim3 grid((unsigned)xcd_grid(nt));
-  if (variant == 0) variant = 1;  // measured best on the MNIST-shaped H block (K chunk 16, one stage)
+  if constexpr (sizeof(T) == 4) {
+    // default FP32 path: the LDS-staged tile
+    const int maxu = dma_maxu(std::min(a.r.pad, a.c.pad));
+    if (variant == 0 && dma_fits(a, maxu)) {
+      if (maxu == 2) launch_dma<2>(ex, a, grid, tc, nt);
+      else if (maxu == 5) launch_dma<5>(ex, a, grid, tc, nt);
+      else launch_dma<9>(ex, a, grid, tc, nt);
+      prof_end(ex, tok);
+      return;
+    }
+  }
+  if (variant == 0) variant = 1;  // register-staged tile: K chunk 16, one stage
   if constexpr (sizeof(T) == 8) {  // FP64 tiles need twice the LDS: K chunk 16 only
     if (variant == 2)
       launch_cfg<T, TOut, 16, 2>(ex, a, grid, tc, nt);
@@ -416,6 +764,8 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
   }
   prof_end(ex, tok);
 }
+
+bool krg_persistent_fits(const KrgArgs<float, float>& a) { return dma_fits(a, 9); }
 
 int64_t krg_tiles(const KrgArgs<float, float>& a, int64_t* tiles_c) {
   const int64_t rows = (int64_t)a.r.n_units * a.r.pad, cols = (int64_t)a.c.n_units * a.c.pad;
@@ -434,7 +784,13 @@ void krg_persistent_launch(Exec& ex, const KrgJob* jobs_dev, int njobs, int64_t 
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const int64_t grid = std::min<int64_t>(total, (int64_t)cus * 2);
   const int tok = prof_begin(ex, "krg_f32_persistent", flops, bytes);
-  hipLaunchKernelGGL(krg_persistent, dim3((unsigned)grid), dim3(256), 0, ex.stream, jobs_dev, njobs, total, counter);
+  static const bool attr = [] {
+    (void)hipFuncSetAttribute((const void*)krg_persistent, hipFuncAttributeMaxDynamicSharedMemorySize, PERSIST_LDS);
+    return true;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL(krg_persistent, dim3((unsigned)grid), dim3(256), PERSIST_LDS, ex.stream, jobs_dev, njobs, total,
+                     counter);
   prof_end(ex, tok);
 }
 

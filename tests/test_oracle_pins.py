@@ -275,6 +275,12 @@ def test_sampled_helpers_match_full_matrices():
     rows, cols = [0, 3, 34, 35, P - 1], [1, 2, 40, P - 4]
     np.testing.assert_allclose(mlp.opg_tile(model, X, Y, rows, cols), G[np.ix_(rows, cols)],
                                rtol=1e-13, atol=1e-16)
+    # OPG columns from delta-weighted sums, against J^T J / N (two hidden layers)
+    model2, X2, Y2 = _small([6, 9, 7, 4], ["tanh", "sigmoid"], 25, 31)
+    G2 = mlp.opg(model2, X2, Y2)
+    cols2 = [0, 5, 53, 62, 63, 64, 120, G2.shape[0] - 1]
+    np.testing.assert_allclose(mlp.opg_cols(model2, X2, Y2, cols2), G2[:, cols2],
+                               rtol=0, atol=1e-14 * np.abs(G2).max())
 
 
 # ---------------------------------------------------------------------------

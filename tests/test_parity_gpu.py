@@ -137,6 +137,57 @@ def test_sigmoid64_reduced_n_exact_full(api):
         assert report("sigmoid64 N=600 H %s" % prec, H, Href) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_wide_units_exact_and_opg(api, prec):
+    # 301 inputs per hidden unit: tiles touch at most two units per side; N = 300 leaves a
+    # ragged last chunk of examples
+    print("case wide units [300, 20, 6] tanh N=300 prec=%s" % prec, flush=True)
+    w = workloads.mlp_gaussian([300, 20, 6], ["tanh"], 300, 8, dtype="float64" if prec == "f64" else "float32")
+    model, X, Y = to_dev(api, w, w.dtype)
+    om, Xo, Yo = oracle_of(w)
+    Href = mlp.hessian(om, Xo, Yo, block=256)
+    Gref = mlp.opg(om, Xo, Yo)
+    H = api.hess_exact(model, X, Y, prec).double().cpu().numpy()
+    G = api.hess_opg(model, X, Y, prec).double().cpu().numpy()
+    assert np.array_equal(H, H.T) and np.array_equal(G, G.T)
+    assert report("H   wide %s" % prec, H, Href) <= TOL[prec]
+    assert report("OPG wide %s" % prec, G, Gref) <= TOL[prec]
+
+
+# Column blocks of the MNIST-shaped network (P = 79510): the first inputs of unit 0, the
+# boundary between hidden units 37 and 38, the last hidden biases and first output
+# weights, and the output layer's tail with its biases.
+MNIST_BLOCKS = [(0, 16), (29784, 29800), (78490, 78506), (79494, 79510)]
+
+
+def test_mnist_shaped_full_size_sampled_columns(api):
+    # the configuration the bench times: full N = 60000, FP32 H and OPG, BF16 OPG
+    print("case mnist-shaped [784, 100, 10] relu N=60000, column blocks %s" % MNIST_BLOCKS, flush=True)
+    w = workloads.mnist_relu()
+    om, Xo, Yo = oracle_of(w)
+    model = api.MLP.from_workload(w, dtype=torch.float32)
+    X = torch.from_numpy(w.X).to("cuda")
+    Y = torch.from_numpy(w.Y).to("cuda")
+    H = api.hess_exact(model, X, Y, "f32")
+    rowsH = {b: H[b[0]:b[1], :].double().cpu().numpy() for b in MNIST_BLOCKS}
+    colsH = {b: H[:, b[0]:b[1]].double().cpu().numpy() for b in MNIST_BLOCKS[:2]}
+    del H
+    torch.cuda.empty_cache()
+    for b in MNIST_BLOCKS[:2]:
+        assert np.array_equal(rowsH[b], colsH[b].T)
+    for b in MNIST_BLOCKS[:3]:
+        ref = mlp.hessian_cols(om, Xo, Yo, b[0], b[1])
+        assert report("mnist H[:, %d:%d] f32" % b, rowsH[b].T, ref) <= TOL["f32"]
+    cols = [c for b in MNIST_BLOCKS for c in range(b[0], b[1])]
+    Gref = mlp.opg_cols(om, Xo, Yo, cols)
+    for prec in ("f32", "bf16"):
+        G = api.hess_opg(model, X, Y, prec)
+        Gc = G[:, cols].double().cpu().numpy()
+        del G
+        torch.cuda.empty_cache()
+        assert report("mnist OPG[:, blocks] %s" % prec, Gc, Gref) <= TOL[prec]
+
+
 def test_run_twice_bitwise(api):
     """No atomics in any reduction: two runs give bitwise-identical results."""
     w = workloads.mlp_gaussian([33, 40, 10], ["tanh"], 300, 9, dtype="float32")
