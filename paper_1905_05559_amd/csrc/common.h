@@ -102,6 +102,11 @@ struct KrgArgs {
   int32_t symmetric, accumulate, mirror;
   double scale;
   int64_t N;
+  // Split over examples: slice s covers examples [s * kslice, min(N, (s + 1) * kslice))
+  // and writes its partial result at out + s * out_split (one launch for all slices).
+  int32_t ksplit = 1;
+  int64_t kslice = 0, out_split = 0;
+  const char* label = nullptr;  // profile name (default: by weight mode and precision)
 };
 template <typename T, typename TOut>
 void krg(Exec& ex, const KrgArgs<T, TOut>& a);
@@ -116,8 +121,9 @@ int64_t krg_tiles(const KrgArgs<float, float>& a, int64_t* tiles_c);
 bool krg_persistent_fits(const KrgArgs<float, float>& a);
 void krg_persistent_launch(Exec& ex, const KrgJob* jobs_dev, int njobs, int64_t total, unsigned long long* counter,
                            double flops, double bytes);
-// Tile-configuration variants (tuning and tests): 1..4 = (K chunk, LDS stages) in
-// {(16,1), (16,2), (32,1), (32,2)}; 0 = the default for the precision.
+// Tile-configuration variants (tuning and tests): register-staged tile 1..4 = (K chunk,
+// LDS stages) in {(16,1), (16,2), (32,1), (32,2)}; FP32 LDS-staged tile 5 = (32, 2),
+// 6 = (16, 3); 0 = the default for the precision (FP32: LDS-staged (16, 2)).
 template <typename T, typename TOut>
 void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant);
 // BF16 OPG: materialise Jt (P x ldk, BF16, p-major) then one symmetric Gram product.

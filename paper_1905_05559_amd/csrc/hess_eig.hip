@@ -80,6 +80,31 @@ __global__ void k_f32_to_f64_2d(const float* src, int64_t rows, int64_t cols, in
   }
 }
 
+// dst (cols x rows, FP32) = src^T, src rows x cols FP64 with leading dimension lds
+__global__ void k_cast_t(const double* src, int64_t rows, int64_t cols, int64_t lds, float* dst) {
+  __shared__ float tile[32][33];
+  const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = r0 + y, c = c0 + tx;
+    if (r < rows && c < cols) tile[y][tx] = (float)src[r * lds + c];
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t c = c0 + y, r = r0 + tx;
+    if (r < rows && c < cols) dst[c * rows + r] = tile[tx][y];
+  }
+}
+
+// Y (rows x cols, FP64, leading dimension ldy) = sum_s part[s] (FP32 rows x cols), in split order
+__global__ void k_sum_splits_f32(const float* part, int64_t S, int64_t rows, int64_t cols, double* Y, int64_t ldy) {
+  GRID_STRIDE(i, rows * cols) {
+    double v = 0.0;
+    for (int64_t k = 0; k < S; ++k) v += (double)part[k * rows * cols + i];
+    Y[(i / cols) * ldy + i % cols] = v;
+  }
+}
+
 // out[i] = sum_s part[s * n + i], summed in split order (deterministic)
 __global__ void k_sum_splits(const double* part, int64_t S, int64_t n, double* out) {
   GRID_STRIDE(i, n) {
@@ -338,6 +363,8 @@ struct EigBufs {
   int64_t b = 0, P = 0, ldp = 0, S = 0;
   double *Q, *Y, *Yp, *Z, *MQ, *X, *MX;
   float *Qf, *Yf;
+  float* Ypart = nullptr;      // dense FP32 operator: per-slice partial products
+  int64_t ks = 1, kslice = 0;  // slices of the contraction over P
   double *part, *W, *Linv, *T, *U, *theta, *res;
   int* info;
   Prep p;
@@ -347,8 +374,17 @@ struct EigBufs {
 
 }  // namespace
 
+// Slices of the dense FP32 apply (b x P times P x P): enough workgroups to fill the
+// device when the output alone has few 128 x 128 tiles.
+static void dense_slices(int64_t P, int64_t b, int64_t& ks, int64_t& kslice) {
+  const int64_t tiles = ((b + 127) / 128) * ((P + 127) / 128);
+  ks = std::max<int64_t>(1, std::min<int64_t>(8, (2048 + tiles - 1) / tiles));
+  kslice = rup((P + ks - 1) / ks, 32);
+  ks = (P + kslice - 1) / kslice;
+}
+
 static size_t plan_eig(Arena& ar, const Model* m, int64_t N, int64_t P, int64_t b, int source, int prec,
-                       EigBufs& e) {
+                       int mdtype, EigBufs& e) {
   e.b = b;
   e.P = P;
   e.ldp = rup(P, KSPLIT);
@@ -358,6 +394,10 @@ static size_t plan_eig(Arena& ar, const Model* m, int64_t N, int64_t P, int64_t 
   e.Qf = ar.take<float>(b * P);
   e.Yf = ar.take<float>(b * P);
   e.part = ar.take<double>(e.S * b * b);
+  if (source == 1 && mdtype == HESS_F32) {
+    dense_slices(P, b, e.ks, e.kslice);
+    e.Ypart = ar.take<float>(e.ks * b * P);
+  }
   for (double** x : {&e.W, &e.Linv, &e.T, &e.U}) *x = ar.take<double>(b * b);
   e.theta = ar.take<double>(b);
   e.res = ar.take<double>(b);
@@ -401,9 +441,33 @@ void op_apply(EigRun& r, const double* Q, double* Y) {
     if (r.Mdtype == HESS_F64) {
       gemm_rm<double>(ex, false, false, b, P, P, 1.0, Q, ldp, static_cast<const double*>(r.M), P, 0.0, Y, ldp);
     } else {
-      cast_2d<float>(ex, Q, b, P, ldp, e.Qf, P);
-      gemm_rm<float>(ex, false, false, b, P, P, 1.0f, e.Qf, P, static_cast<const float*>(r.M), P, 0.0f, e.Yf, P);
-      LAUNCH(k_f32_to_f64_2d, b * P, e.Yf, b, P, P, Y, ldp);
+      // Y = Q M through the Khatri-Rao contraction with one unit per side: rows are the
+      // b block vectors (source Q^T, P x b), columns the P columns of M (source M: row k
+      // of M holds M[k][c] for all c); the contraction over k is split into slices whose
+      // partial products are summed in slice order.
+      if (!launch_ok(ex)) return;
+      hipLaunchKernelGGL(k_cast_t, dim3((unsigned)((P + 31) / 32), (unsigned)((b + 31) / 32)), dim3(256), 0,
+                         ex.stream, Q, b, P, ldp, e.Qf);
+      KrgArgs<float, float> a;
+      a.r = KrgSide<float>{e.Qf, b, 1, (int32_t)b, (int32_t)rup(b, 16), nullptr, 0, 0, 0, (int32_t)b, 1};
+      a.c = KrgSide<float>{static_cast<const float*>(r.M), P, 1, (int32_t)P, (int32_t)rup(P, 16), nullptr, 0, 0, 0,
+                           (int32_t)P, 1};
+      a.wmode = KRG_RANK1;
+      a.wts = nullptr;
+      a.ldw = 0;
+      a.out = e.Ypart;
+      a.ldo = P;
+      a.symmetric = 0;
+      a.accumulate = 0;
+      a.mirror = 0;
+      a.scale = 1.0;
+      a.N = P;
+      a.ksplit = (int32_t)e.ks;
+      a.kslice = e.kslice;
+      a.out_split = b * P;
+      a.label = "dense_apply_f32";
+      krg<float, float>(ex, a);
+      LAUNCH(k_sum_splits_f32, b * P, e.Ypart, e.ks, b, P, Y, ldp);
     }
     return;
   }
@@ -531,7 +595,7 @@ hess_status topk_workspace(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* 
   if (s != HESS_OK) return s;
   Arena ar(nullptr);
   EigBufs e;
-  *bytes = plan_eig(ar, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, e);
+  *bytes = plan_eig(ar, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, t.Mdtype, e);
   return HESS_OK;
 }
 
@@ -550,11 +614,11 @@ extern "C" hess_status hess_topk_eig(hess_ctx* ctx, const hess_mlp* mlp, const h
   if (!lambda || !Qout) return fail(ctx, HESS_E_ARG, "lambda or Q is NULL");
   Arena probe(nullptr);
   EigBufs e0;
-  const size_t need = plan_eig(probe, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, e0);
+  const size_t need = plan_eig(probe, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, t.Mdtype, e0);
   if ((s = check_ws(ctx, need, ws, ws_bytes, (size_t)K * (t.P + 1) * 8)) != HESS_OK) return s;
   Arena ar(ws);
   EigBufs e;
-  plan_eig(ar, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, e);
+  plan_eig(ar, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, t.Mdtype, e);
   if (t.source == 0) {
     if ((s = check_inputs(ex, t.m, d, e.p)) != HESS_OK) return s;
     run_prep(ex, t.m, d, e.p, false);

@@ -319,11 +319,13 @@ __device__ __forceinline__ void krg_tile(const KrgArgs<T, TOut>& a, int64_t t, i
 // FP32 tile with direct HBM -> LDS staging (buffer_load ... lds).
 //
 // The operands never pass through registers on their way to LDS: every chunk of
-// DKC examples is copied by the vector memory unit straight into one of DST LDS
-// stages, so the K loop issues only the copies, the LDS operand reads, the pair
-// weight products and the MFMAs.  A stage holds A and B k-major (As[k][r], row
+// KC examples is copied by the vector memory unit straight into one of NST LDS
+// stages (the copies of chunk c + NST - 1 are issued right after the barrier that
+// opens chunk c), so the K loop issues only the copies, the LDS operand reads, the
+// pair weight products and the MFMAs.  Example ranges can be split into slices that
+// run in the same launch and write separate partial results.  A stage holds A and B k-major (As[k][r], row
 // stride DLD floats; DLD = 132 puts the four lane groups of a 16x16x4 MFMA step,
-// which read k = 4q + s, on disjoint LDS banks) and the per-chunk pair weights
+// which read k = 16 g + 4q + s, on disjoint LDS banks) and the per-chunk pair weights
 // (PAIR_FULL: [row unit][column unit][k], PAIR_DIAG: [unit][k], RANK1: the row
 // and column scale factors [unit][k]).  Each lane copies one float: its address
 // clamps the slot to the unit's valid range (so every read stays inside the
@@ -340,20 +342,28 @@ __device__ __forceinline__ void krg_tile(const KrgArgs<T, TOut>& a, int64_t t, i
 // depends on the block's row unit and the lane's column unit, is applied to B.
 // B is always read interleaved (lane columns 4 * col16 + j, one column unit).
 // ---------------------------------------------------------------------------
-constexpr int DKC = 16, DLD = 132, DST = 3;
+constexpr int DLD = 132;
 
-template <int WMODE, int MAXU>
+// chunk of examples per stage and number of LDS stages (prefetch distance NST - 1)
+template <int KC_, int NST_>
+struct DmaCfg {
+  static constexpr int KC = KC_, NST = NST_;
+};
+using DmaDefault = DmaCfg<16, 2>;  // measured: (16, 2) 131, (16, 3) 129, (32, 2) 126 TFLOP/s
+
+template <int WMODE, int MAXU, class C = DmaDefault>
 struct DmaSmem {
+  static constexpr int DKC = C::KC;
   static constexpr int AB = DKC * DLD;
   static constexpr int WN1 = WMODE == KRG_PAIR_FULL ? MAXU * MAXU * DKC : MAXU * DKC;  // floats per weight array
   static constexpr int NW = WMODE == KRG_RANK1 ? 2 : 1;                              // weight arrays
   static constexpr int WI1 = (WN1 + 63) / 64;                                         // copies per array
   static constexpr int WI = NW * WI1;
   static constexpr int STAGE = 2 * AB + NW * WN1;
-  static constexpr int SIZE = DST * STAGE;
-  // copies every wavefront issues per chunk: 8 for A, 8 for B, and its share of the
-  // weight copies (a lower bound when RANK1 scale factors may be absent)
-  static constexpr int VMC = 16 + (WMODE == KRG_RANK1 ? 0 : WI / 4);
+  static constexpr int SIZE = C::NST * STAGE;
+  // copies every wavefront issues per chunk: KC / 2 for A, KC / 2 for B, and its share
+  // of the weight copies (a lower bound when RANK1 scale factors may be absent)
+  static constexpr int VMC = DKC + (WMODE == KRG_RANK1 ? 0 : WI / 4);
   static constexpr int WPW = (WI + 3) / 4;  // weight copies one wavefront may issue
 };
 
@@ -373,24 +383,18 @@ __device__ __forceinline__ void copy_lds(__amdgpu_buffer_rsrc_t r, float* dst, i
   __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr_t)dst, 4, voff, 0, 0, 0);
 }
 
-__device__ __forceinline__ void wait_vm(int n) {
-  // s_waitcnt vmcnt(n) with expcnt and lgkmcnt left free (gfx9 encoding)
-  switch (n) {
-    case 0: __builtin_amdgcn_s_waitcnt(0x0f70); break;
-    case 16: __builtin_amdgcn_s_waitcnt(0x4f70); break;
-    case 17: __builtin_amdgcn_s_waitcnt(0x4f71); break;
-    case 18: __builtin_amdgcn_s_waitcnt(0x4f72); break;
-    case 19: __builtin_amdgcn_s_waitcnt(0x4f73); break;
-    case 20: __builtin_amdgcn_s_waitcnt(0x4f74); break;
-    case 21: __builtin_amdgcn_s_waitcnt(0x4f75); break;
-    default: __builtin_amdgcn_s_waitcnt(0x0f70); break;
-  }
+// s_waitcnt vmcnt(N) with expcnt and lgkmcnt left free (gfx9 encoding: vmcnt bits 3:0 and 15:14)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0f70);
 }
 
-template <int WMODE, bool SYM, int MAXU>
+template <int WMODE, bool SYM, int MAXU, class C = DmaDefault>
 __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int64_t t, int64_t tiles_c,
                                              float* smem) {
-  using SM = DmaSmem<WMODE, MAXU>;
+  using SM = DmaSmem<WMODE, MAXU, C>;
+  constexpr int DKC = C::KC, DST = C::NST, KH = DKC / 2;
   int64_t tr, tc;
   const int64_t tiles_r = ((int64_t)a.r.n_units * a.r.pad + BM - 1) / BM;
   tile_of(t, SYM, tiles_c, tiles_r, tr, tc);
@@ -406,10 +410,10 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
   const int row16 = lane & 15, q = lane >> 4;
 
   // ---- per-lane copy offsets (bytes, relative to the chunk's base pointers) ----
-  int voffA[8], voffB[8];
+  int voffA[KH], voffB[KH];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const int k = 4 * wave + (m >> 1);
+  for (int m = 0; m < KH; ++m) {
+    const int k = (DKC / 4) * wave + (m >> 1);
     const int64_t r = r0 + (m & 1) * 64 + lane, c = c0 + (m & 1) * 64 + lane;
     const int sr = (int)mn64(r % a.r.pad, a.r.len - 1), sc = (int)mn64(c % a.c.pad, a.c.len - 1);
     voffA[m] = (int)((k * a.r.ld + sr) * 4);
@@ -457,9 +461,10 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
     const __amdgpu_buffer_rsrc_t ra = rsrc_of(a.r.src + n0 * a.r.ld, (int64_t)kv * a.r.ld);
     const __amdgpu_buffer_rsrc_t rb = rsrc_of(a.c.src + n0 * a.c.ld, (int64_t)kv * a.c.ld);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) copy_lds(ra, S + (4 * wave + (m >> 1)) * DLD + (m & 1) * 64, voffA[m]);
+    for (int m = 0; m < KH; ++m) copy_lds(ra, S + ((DKC / 4) * wave + (m >> 1)) * DLD + (m & 1) * 64, voffA[m]);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) copy_lds(rb, S + SM::AB + (4 * wave + (m >> 1)) * DLD + (m & 1) * 64, voffB[m]);
+    for (int m = 0; m < KH; ++m)
+      copy_lds(rb, S + SM::AB + ((DKC / 4) * wave + (m >> 1)) * DLD + (m & 1) * 64, voffB[m]);
     float* W = S + 2 * SM::AB;
     if (WMODE == KRG_PAIR_FULL || WMODE == KRG_PAIR_DIAG) {
       const int64_t base = (WMODE == KRG_PAIR_FULL ? ((int64_t)ur_lo * a.c.n_units + uc_lo) : (int64_t)ur_lo) * a.ldw + n0;
@@ -484,22 +489,23 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
     }
   };
 
-  // weights of (row unit urel, column unit ucrel) for this lane's k = 4q .. 4q + 3
-  auto wt4 = [&](const float* W, int urel, int ucrel, int kv) -> f4_t {
+  // weights of (row unit urel, column unit ucrel) for this lane's k = k0 + 4q .. k0 + 4q + 3
+  auto wt4 = [&](const float* W, int urel, int ucrel, int k0, int kv) -> f4_t {
+    const int kk = k0 + 4 * q;
     f4_t w;
     if (WMODE == KRG_PAIR_FULL) {
-      w = *(const f4_t*)&W[(urel * MAXU + ucrel) * DKC + 4 * q];
+      w = *(const f4_t*)&W[(urel * MAXU + ucrel) * DKC + kk];
     } else if (WMODE == KRG_PAIR_DIAG) {
-      w = (ur_lo + urel == uc_lo + ucrel) ? *(const f4_t*)&W[urel * DKC + 4 * q] : f4_t{0.f, 0.f, 0.f, 0.f};
+      w = (ur_lo + urel == uc_lo + ucrel) ? *(const f4_t*)&W[urel * DKC + kk] : f4_t{0.f, 0.f, 0.f, 0.f};
     } else {
       w = f4_t{1.f, 1.f, 1.f, 1.f};
-      if (has_sa) w *= *(const f4_t*)&W[urel * DKC + 4 * q];
-      if (has_sb) w *= *(const f4_t*)&W[SM::WN1 + ucrel * DKC + 4 * q];
+      if (has_sa) w *= *(const f4_t*)&W[urel * DKC + kk];
+      if (has_sb) w *= *(const f4_t*)&W[SM::WN1 + ucrel * DKC + kk];
     }
     if (kv < DKC) {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        if (4 * q + s >= kv) w[s] = 0.f;
+        if (kk + s >= kv) w[s] = 0.f;
     }
     return w;
   };
@@ -521,43 +527,52 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
   const int64_t nk = (a.N + DKC - 1) / DKC;
   auto kloop = [&](auto oc) {
     constexpr bool ONE = decltype(oc)::value;
-    if (nk > 0) issue(0, 0);
-    if (nk > 1) issue(1, DKC);
+#pragma unroll
+    for (int c = 0; c < DST - 1; ++c)
+      if (c < nk) issue(c, (int64_t)c * DKC);
     for (int64_t kc = 0; kc < nk; ++kc) {
-      if (kc + 1 < nk) wait_vm(SM::VMC); else wait_vm(0);
-      __builtin_amdgcn_s_barrier();
-      if (kc + 2 < nk) issue((int)((kc + 2) % DST), (kc + 2) * DKC);
+      // wait for this chunk's copies; with three stages the next chunk may stay in flight
+      if (DST > 2 && kc + 1 < nk) wait_vm<(DST > 2 ? SM::VMC : 0)>(); else wait_vm<0>();
+      // every wavefront's copies of this chunk have landed and its reads of the stage
+      // about to be refilled are complete
+      asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      if (kc + DST - 1 < nk) issue((int)((kc + DST - 1) % DST), (kc + DST - 1) * DKC);
       const int st = (int)(kc % DST);
       const float* As = smem + st * SM::STAGE;
       const float* Bs = As + SM::AB;
       const float* W = As + 2 * SM::AB;
       const int kv = (int)mn64(DKC, a.N - kc * DKC);
-      if (ONE) {
-        const f4_t w = wt4(W, ur_lane, uc_lane, kv);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int k = 4 * q + s;
-          const f4_t av = *(const f4_t*)&As[k * DLD + wr * 64 + 4 * row16] * w[s];
-          const f4_t bv = *(const f4_t*)&Bs[k * DLD + wc * 64 + 4 * row16];
+      for (int k0 = 0; k0 < DKC; k0 += 16) {
+        if (ONE) {
+          const f4_t w = wt4(W, ur_lane, uc_lane, k0, kv);
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int s = 0; s < 4; ++s) {
+            const int k = k0 + 4 * q + s;
+            const f4_t av = *(const f4_t*)&As[k * DLD + wr * 64 + 4 * row16] * w[s];
+            const f4_t bv = *(const f4_t*)&Bs[k * DLD + wc * 64 + 4 * row16];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-        }
-      } else {
-        f4_t w[4];
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) w[i] = wt4(W, ur_blk[i], uc_lane, kv);
+              for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+          }
+        } else {
+          f4_t w[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int k = 4 * q + s;
-          const f4_t bv = *(const f4_t*)&Bs[k * DLD + wc * 64 + 4 * row16];
+          for (int i = 0; i < 4; ++i) w[i] = wt4(W, ur_blk[i], uc_lane, k0, kv);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float av = As[k * DLD + wr * 64 + 16 * i + row16];
-            const f4_t bw = bv * w[i][s];
+          for (int s = 0; s < 4; ++s) {
+            const int k = k0 + 4 * q + s;
+            const f4_t bv = *(const f4_t*)&Bs[k * DLD + wc * 64 + 4 * row16];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bw[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 4; ++i) {
+              const float av = As[k * DLD + wr * 64 + 16 * i + row16];
+              const f4_t bw = bv * w[i][s];
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bw[j], acc[i][j], 0, 0, 0);
+            }
           }
         }
       }
@@ -599,11 +614,22 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
 
 extern __shared__ __attribute__((aligned(16))) float dma_smem[];
 
-template <int WMODE, bool SYM, int MAXU>
+template <int WMODE, bool SYM, int MAXU, class C>
 __global__ __launch_bounds__(256, 2) void krg_kernel_dma(KrgArgs<float, float> a, int64_t tiles_c, int64_t ntiles) {
-  const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
+  int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles * a.ksplit);
   if (t < 0) return;
-  krg_tile_dma<WMODE, SYM, MAXU>(a, t, tiles_c, dma_smem);
+  if (a.ksplit > 1) {  // slice of the example range: shift every per-example operand
+    const int64_t sp = t / ntiles, k0 = sp * a.kslice;
+    t -= sp * ntiles;
+    a.r.src += k0 * a.r.ld;
+    a.c.src += k0 * a.c.ld;
+    if (a.r.scale) a.r.scale += k0 * a.r.ld_scale;
+    if (a.c.scale) a.c.scale += k0 * a.c.ld_scale;
+    if (a.wts) a.wts += k0;
+    a.N = mn64(a.kslice, a.N - k0);
+    a.out += sp * a.out_split;
+  }
+  krg_tile_dma<WMODE, SYM, MAXU, C>(a, t, tiles_c, dma_smem);
 }
 
 // Units of one side that a 128-row tile can touch: pad >= 128 -> 2, >= 32 -> 5, else 9.
@@ -613,7 +639,7 @@ int dma_maxu(int pad) { return pad >= 128 ? 2 : (pad >= 32 ? 5 : 9); }
 // per-chunk base pointers; contractions whose offsets could exceed that use the
 // register-staged tile.
 bool dma_fits(const KrgArgs<float, float>& a, int maxu) {
-  const int64_t lim = 0x7fff0000;
+  const int64_t lim = 0x7fff0000, DKC = 32;  // largest chunk of any configuration
   if (a.r.len > a.r.ld || a.c.len > a.c.ld) return false;
   if ((int64_t)DKC * std::max(a.r.ld, a.c.ld) * 4 > lim) return false;
   if (a.wmode == KRG_PAIR_FULL && (((int64_t)(maxu - 1) * a.c.n_units + maxu) * a.ldw + DKC) * 4 > lim) return false;
@@ -622,28 +648,28 @@ bool dma_fits(const KrgArgs<float, float>& a, int maxu) {
   return true;
 }
 
-template <int WMODE, bool SYM, int MAXU>
+template <int WMODE, bool SYM, int MAXU, class C>
 void launch_dma_one(Exec& ex, const KrgArgs<float, float>& a, dim3 grid, int64_t tc, int64_t nt) {
-  constexpr int bytes = DmaSmem<WMODE, MAXU>::SIZE * 4;
+  constexpr int bytes = DmaSmem<WMODE, MAXU, C>::SIZE * 4;
   static const bool attr = [] {  // once per process (thread-safe static initialisation)
-    (void)hipFuncSetAttribute((const void*)krg_kernel_dma<WMODE, SYM, MAXU>,
+    (void)hipFuncSetAttribute((const void*)krg_kernel_dma<WMODE, SYM, MAXU, C>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return true;
   }();
   (void)attr;
-  hipLaunchKernelGGL((krg_kernel_dma<WMODE, SYM, MAXU>), grid, dim3(256), bytes, ex.stream, a, tc, nt);
+  hipLaunchKernelGGL((krg_kernel_dma<WMODE, SYM, MAXU, C>), grid, dim3(256), bytes, ex.stream, a, tc, nt);
 }
 
-template <int MAXU>
+template <int MAXU, class C = DmaDefault>
 void launch_dma(Exec& ex, const KrgArgs<float, float>& a, dim3 grid, int64_t tc, int64_t nt) {
   if (a.wmode == KRG_RANK1) {
-    if (a.symmetric) launch_dma_one<KRG_RANK1, true, MAXU>(ex, a, grid, tc, nt);
-    else launch_dma_one<KRG_RANK1, false, MAXU>(ex, a, grid, tc, nt);
+    if (a.symmetric) launch_dma_one<KRG_RANK1, true, MAXU, C>(ex, a, grid, tc, nt);
+    else launch_dma_one<KRG_RANK1, false, MAXU, C>(ex, a, grid, tc, nt);
   } else if (a.wmode == KRG_PAIR_FULL) {
-    if (a.symmetric) launch_dma_one<KRG_PAIR_FULL, true, MAXU>(ex, a, grid, tc, nt);
-    else launch_dma_one<KRG_PAIR_FULL, false, MAXU>(ex, a, grid, tc, nt);
+    if (a.symmetric) launch_dma_one<KRG_PAIR_FULL, true, MAXU, C>(ex, a, grid, tc, nt);
+    else launch_dma_one<KRG_PAIR_FULL, false, MAXU, C>(ex, a, grid, tc, nt);
   } else {
-    launch_dma_one<KRG_PAIR_DIAG, false, MAXU>(ex, a, grid, tc, nt);
+    launch_dma_one<KRG_PAIR_DIAG, false, MAXU, C>(ex, a, grid, tc, nt);
   }
 }
 
@@ -712,7 +738,8 @@ void launch_cfg(Exec& ex, const KrgArgs<T, TOut>& a, dim3 grid, int64_t tc, int6
 
 }  // namespace
 
-// variant: 0 = default for the precision; 1 = (KC 16, 1 stage); 2 = (16, 2); 3 = (32, 1); 4 = (32, 2)
+// variant: 0 = default for the precision; register-staged tile 1 = (KC 16, 1 stage), 2 = (16, 2),
+// 3 = (32, 1), 4 = (32, 2); FP32 LDS-staged tile 5 = (32 examples, 2 stages), 6 = (16, 3)
 template <typename T, typename TOut>
 void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
   const int64_t rows = (int64_t)a.r.n_units * a.r.pad, cols = (int64_t)a.c.n_units * a.c.pad;
@@ -734,19 +761,45 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
                                  {"krg_f32_pairdiag", "krg_f32_pairdiag_sym"}},
                                 {{"krg_f64_rank1", "krg_f64_rank1_sym"}, {"krg_f64_pair", "krg_f64_pair_sym"},
                                  {"krg_f64_pairdiag", "krg_f64_pairdiag_sym"}}};
-  const int tok = prof_begin(ex, names[sizeof(T) == 8][a.wmode][a.symmetric ? 1 : 0], 2.0 * a.N * entries,
-                             src + wbytes + obytes);
-  dim3 grid((unsigned)xcd_grid(nt));
+  const int ks = std::max(1, a.ksplit);
+  const int tok = prof_begin(ex, a.label ? a.label : names[sizeof(T) == 8][a.wmode][a.symmetric ? 1 : 0],
+                             2.0 * a.N * entries, src + wbytes + obytes * ks);
+  dim3 grid((unsigned)xcd_grid(nt * ks));
   if constexpr (sizeof(T) == 4) {
     // default FP32 path: the LDS-staged tile
     const int maxu = dma_maxu(std::min(a.r.pad, a.c.pad));
-    if (variant == 0 && dma_fits(a, maxu)) {
-      if (maxu == 2) launch_dma<2>(ex, a, grid, tc, nt);
-      else if (maxu == 5) launch_dma<5>(ex, a, grid, tc, nt);
-      else launch_dma<9>(ex, a, grid, tc, nt);
+    if ((variant == 0 || variant >= 5) && dma_fits(a, maxu)) {
+      auto go = [&](auto cfg) {
+        using C = decltype(cfg);
+        if (maxu == 2) launch_dma<2, C>(ex, a, grid, tc, nt);
+        else if (maxu == 5) launch_dma<5, C>(ex, a, grid, tc, nt);
+        else launch_dma<9, C>(ex, a, grid, tc, nt);
+      };
+      if (variant == 5) go(DmaCfg<32, 2>());
+      else if (variant == 6) go(DmaCfg<16, 3>());
+      else go(DmaDefault());
       prof_end(ex, tok);
       return;
     }
+  }
+  if (ks > 1) {  // register-staged tile: one launch per slice of the example range
+    grid = dim3((unsigned)xcd_grid(nt));
+    for (int sp = 0; sp < ks; ++sp) {
+      KrgArgs<T, TOut> b = a;
+      const int64_t k0 = sp * a.kslice;
+      b.ksplit = 1;
+      b.r.src += k0 * a.r.ld;
+      b.c.src += k0 * a.c.ld;
+      if (b.r.scale) b.r.scale += k0 * a.r.ld_scale;
+      if (b.c.scale) b.c.scale += k0 * a.c.ld_scale;
+      if (b.wts) b.wts += k0;
+      b.N = std::max<int64_t>(0, std::min(a.kslice, a.N - k0));
+      b.out += sp * a.out_split;
+      if (variant == 2) launch_cfg<T, TOut, 16, 2>(ex, b, grid, tc, nt);
+      else launch_cfg<T, TOut, 16, 1>(ex, b, grid, tc, nt);
+    }
+    prof_end(ex, tok);
+    return;
   }
   if (variant == 0) variant = 1;  // register-staged tile: K chunk 16, one stage
   if constexpr (sizeof(T) == 8) {  // FP64 tiles need twice the LDS: K chunk 16 only
