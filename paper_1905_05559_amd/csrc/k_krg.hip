@@ -40,42 +40,12 @@ __device__ __forceinline__ int64_t flat_index(int32_t perm, int64_t off, int32_t
   return j < Tin ? off + i * Tin + j : off + (int64_t)Tout * Tin + i;
 }
 
-// Grouped tile order: consecutive tile ids walk GROUP row panels column by column, so
-// the ~64 tiles an XCD runs at once share 8 row panels and 8 column panels in its L2
-// instead of one row panel and 64 column panels.  Symmetric blocks enumerate only
-// tiles with tc <= tr: group g (rows gG .. gG+Gg-1) holds gG full columns of Gg tiles
-// and then a lower triangle of Gg columns.
-constexpr int64_t GROUP = 8;
-
 __device__ __forceinline__ void tile_of(int64_t t, bool symmetric, int64_t tiles_c, int64_t tiles_r, int64_t& tr,
                                         int64_t& tc) {
-  if (!symmetric) {
-    const int64_t g = t / (GROUP * tiles_c), u = t - g * GROUP * tiles_c;
-    const int64_t Gg = min(GROUP, tiles_r - g * GROUP);
-    tc = u / Gg;
-    tr = g * GROUP + u % Gg;
-    return;
-  }
-  // tiles before group g (all full): G^2 g (g - 1) / 2 + g G (G + 1) / 2
-  auto before = [](int64_t g) { return GROUP * GROUP * g * (g - 1) / 2 + g * GROUP * (GROUP + 1) / 2; };
-  int64_t g = (int64_t)(sqrt(2.0 * (double)t) / (double)GROUP);
-  while (g > 0 && before(g) > t) --g;
-  while (before(g + 1) <= t && (g + 1) * GROUP < tiles_r) ++g;
-  int64_t u = t - before(g);
-  const int64_t Gg = min(GROUP, tiles_r - g * GROUP), r0 = g * GROUP;
-  if (u < r0 * Gg) {
-    tc = u / Gg;
-    tr = r0 + u % Gg;
-    return;
-  }
-  u -= r0 * Gg;
-  int64_t c = 0;
-  while (u >= Gg - c) {
-    u -= Gg - c;
-    ++c;
-  }
-  tc = r0 + c;
-  tr = r0 + c + u;
+  if (symmetric)
+    grouped_lower_tile(t, tiles_r, tr, tc);
+  else
+    grouped_full_tile(t, tiles_c, tiles_r, tr, tc);
 }
 
 template <typename TOut>

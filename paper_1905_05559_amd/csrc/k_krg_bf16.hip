@@ -10,6 +10,8 @@
 //    256 x 256 tiles, mirrored, FP32 accumulation (v_mfma_f32_16x16x32_bf16).
 //    4 wavefronts (2 x 2), each 128 x 128 = 8 x 8 MFMA blocks; K staged through LDS
 //    in chunks of 64 with 16-byte vector loads prefetched one chunk ahead.
+#include <algorithm>
+
 #include "mfma.h"
 
 namespace hs {
@@ -161,6 +163,118 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(const __bf16* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Gram product with direct HBM -> LDS staging (buffer_load_dwordx4 ... lds).
+//
+// Same 256 x 256 tiles and wavefront layout as above, K chunks of GD = 32 examples in
+// GS = 4 LDS stages (one barrier per chunk; the copies of a chunk are issued three chunks
+// ahead).  Tiles are visited in the grouped lower-triangle order, so the tiles an XCD
+// runs at once share eight row panels and a few column panels in its L2.  A stage holds the two 256-row panels, 64 bytes (4 segments of 8 BF16) per
+// row.  Each lane copies one 16-byte segment; segments are stored at position
+// row * 4 + (seg ^ ((row >> 2) & 3)) so that the 16 lanes of an MFMA operand read
+// (rows row16 = 0..15, one segment) fall on 16 different 4-bank groups.  Rows past P
+// are clamped to row P - 1 (their outputs are discarded); Jt columns n >= N are zero.
+// ---------------------------------------------------------------------------
+constexpr int GD = 32, GS = 4;
+constexpr int GSTAGE = 2 * GB * GD;  // BF16 elements per stage
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0f70);
+}
+
+__global__ __launch_bounds__(256) void gram_bf16_dma_kernel(const __bf16* __restrict__ Jt, int64_t P, int64_t ldk,
+                                                            float scale, float* __restrict__ C, int64_t ldc,
+                                                            int64_t ntiles) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __bf16* S = reinterpret_cast<__bf16*>(smem);
+
+  const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
+  if (t < 0) return;
+  int64_t tr, tc;
+  grouped_lower_tile(t, (P + GB - 1) / GB, tr, tc);
+  const int64_t r0 = tr * GB, c0 = tc * GB;
+  const bool diag = (tr == tc);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int row16 = lane & 15, q = lane >> 4;
+
+  // copy m (0..3) of this wavefront moves rows 16 * (4 * wave + m) .. + 15 of a panel
+  int voffA[4], voffB[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int row = 16 * (4 * wave + m) + (lane >> 2);
+    const int seg = (lane & 3) ^ ((row >> 2) & 3);
+    const int64_t ra = std::min<int64_t>(r0 + row, P - 1) - r0, rb = std::min<int64_t>(c0 + row, P - 1) - c0;
+    voffA[m] = (int)((ra * ldk + seg * 8) * 2);
+    voffB[m] = (int)((rb * ldk + seg * 8) * 2);
+  }
+  const int64_t nk = ldk / GD;
+  auto issue = [&](int st, int64_t k0) {
+    __bf16* D = S + st * GSTAGE;
+    const __amdgpu_buffer_rsrc_t ra =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16*>(Jt + r0 * ldk + k0), (short)0, 0x7ffffff0, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16*>(Jt + c0 * ldk + k0), (short)0, 0x7ffffff0, 0x00020000);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (__attribute__((address_space(3))) void*)(D + (4 * wave + m) * 16 * GD),
+                                               16, voffA[m], 0, 0, 0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rb, (__attribute__((address_space(3))) void*)(D + GB * GD + (4 * wave + m) * 16 * GD), 16, voffB[m], 0, 0, 0);
+  };
+
+  f4_t acc[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int sw = (q ^ ((row16 >> 2) & 3)) * 8;  // swizzled segment of this lane's k = 8q .. 8q + 7
+#pragma unroll
+  for (int c = 0; c < GS - 1; ++c)
+    if (c < nk) issue(c, (int64_t)c * GD);
+  for (int64_t kc = 0; kc < nk; ++kc) {
+    // chunk kc's copies are the oldest in flight: up to two later chunks may stay pending
+    const int64_t later = std::min<int64_t>(GS - 2, nk - 1 - kc);
+    if (later >= 2) wait_vmcnt<16>(); else if (later == 1) wait_vmcnt<8>(); else wait_vmcnt<0>();
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (kc + GS - 1 < nk) issue((int)((kc + GS - 1) % GS), (kc + GS - 1) * GD);
+    const __bf16* As = S + (kc % GS) * GSTAGE;
+    const __bf16* Bs = diag ? As : As + GB * GD;
+    bf8_t av[8], bv[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) av[i] = *reinterpret_cast<const bf8_t*>(&As[(wr * 128 + i * 16 + row16) * GD + sw]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bv[j] = *reinterpret_cast<const bf8_t*>(&Bs[(wc * 128 + j * 16 + row16) * GD + sw]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[i][j] = mma_bf16(av[i], bv[j], acc[i][j]);
+  }
+
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = r0 + wr * 128 + i * 16 + 4 * q + v;
+      if (r >= P) continue;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t c = c0 + wc * 128 + j * 16 + row16;
+        if (c >= P || (diag && r < c)) continue;
+        const float val = scale * acc[i][j][v];
+        C[r * ldc + c] = val;
+        if (r != c) C[c * ldc + r] = val;
+      }
+    }
+}
+
 }  // namespace
 
 void jt_bf16(Exec& ex, const JtArgs& a) {
@@ -174,23 +288,41 @@ void jt_bf16(Exec& ex, const JtArgs& a) {
 
 int64_t jt_ld(int64_t N) { return (N + GK - 1) / GK * GK; }
 
-void gram_bf16(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64_t N, float scale, float* C,
-               int64_t ldc) {
+void gram_bf16_variant(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64_t N, float scale, float* C,
+                       int64_t ldc, int variant) {
   const int64_t tr = (P + GB - 1) / GB;
   const int64_t nt = tr * (tr + 1) / 2;
   if (nt <= 0) return;
   if (!launch_ok(ex)) return;
-  const size_t shm = 2 * GB * GKP * sizeof(__bf16);
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void*)gram_bf16_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    attr = true;
-  }
   const double entries = (double)P * (P + 1) / 2;
   const int tok = prof_begin(ex, "gram_bf16_sym", 2.0 * N * entries, (double)P * ldk * 2.0 + (double)P * P * 4.0);
-  hipLaunchKernelGGL(gram_bf16_kernel, dim3((unsigned)xcd_grid(nt)), dim3(256), shm, ex.stream, Jt, P, ldk,
-                     ldk / GK, scale, C, ldc, nt);
+  // LDS-staged form needs every copy offset below 2^31 bytes (255 rows of ldk BF16)
+  if (variant != 1 && (int64_t)GB * ldk * 2 < 0x7fff0000) {
+    const size_t shm = (size_t)GS * GSTAGE * sizeof(__bf16);
+    static const bool attr = [shm] {
+      (void)hipFuncSetAttribute((const void*)gram_bf16_dma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm);
+      return true;
+    }();
+    (void)attr;
+    hipLaunchKernelGGL(gram_bf16_dma_kernel, dim3((unsigned)xcd_grid(nt)), dim3(256), shm, ex.stream, Jt, P, ldk,
+                       scale, C, ldc, nt);
+  } else {
+    const size_t shm = 2 * GB * GKP * sizeof(__bf16);
+    static const bool attr = [shm] {
+      (void)hipFuncSetAttribute((const void*)gram_bf16_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      return true;
+    }();
+    (void)attr;
+    hipLaunchKernelGGL(gram_bf16_kernel, dim3((unsigned)xcd_grid(nt)), dim3(256), shm, ex.stream, Jt, P, ldk,
+                       ldk / GK, scale, C, ldc, nt);
+  }
   prof_end(ex, tok);
+}
+
+void gram_bf16(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64_t N, float scale, float* C,
+               int64_t ldc) {
+  gram_bf16_variant(ex, Jt, P, ldk, N, scale, C, ldc, 0);
 }
 
 }  // namespace hs

@@ -50,4 +50,45 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t grid, int64_t n
 
 inline int64_t xcd_grid(int64_t ntiles) { return (ntiles + 7) & ~int64_t(7); }
 
+// Grouped tile orders: consecutive tile ids walk TILE_GROUP row panels column by column,
+// so the tiles an XCD runs at once (a contiguous id range, see xcd_tile) share a few row
+// and column panels in its L2 instead of one row panel and many column panels.
+constexpr int64_t TILE_GROUP = 8;
+
+// Full tiles_r x tiles_c grid.
+__device__ __forceinline__ void grouped_full_tile(int64_t t, int64_t tiles_c, int64_t tiles_r, int64_t& tr,
+                                                  int64_t& tc) {
+  const int64_t G = TILE_GROUP;
+  const int64_t g = t / (G * tiles_c), u = t - g * G * tiles_c;
+  const int64_t Gg = tiles_r - g * G < G ? tiles_r - g * G : G;
+  tc = u / Gg;
+  tr = g * G + u % Gg;
+}
+
+// Lower triangle (tc <= tr) of a tiles_r x tiles_r grid: group g (rows gG .. gG + Gg - 1)
+// holds gG full columns of Gg tiles and then a lower triangle of Gg columns.
+__device__ __forceinline__ void grouped_lower_tile(int64_t t, int64_t tiles_r, int64_t& tr, int64_t& tc) {
+  const int64_t G = TILE_GROUP;
+  // tiles before group g (all full): G^2 g (g - 1) / 2 + g G (G + 1) / 2
+  auto before = [G](int64_t g) { return G * G * g * (g - 1) / 2 + g * G * (G + 1) / 2; };
+  int64_t g = (int64_t)(sqrt(2.0 * (double)t) / (double)G);
+  while (g > 0 && before(g) > t) --g;
+  while (before(g + 1) <= t && (g + 1) * G < tiles_r) ++g;
+  int64_t u = t - before(g);
+  const int64_t Gg = tiles_r - g * G < G ? tiles_r - g * G : G, r0 = g * G;
+  if (u < r0 * Gg) {
+    tc = u / Gg;
+    tr = r0 + u % Gg;
+    return;
+  }
+  u -= r0 * Gg;
+  int64_t c = 0;
+  while (u >= Gg - c) {
+    u -= Gg - c;
+    ++c;
+  }
+  tc = r0 + c;
+  tr = r0 + c + u;
+}
+
 }  // namespace hs
