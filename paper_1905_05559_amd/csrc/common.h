@@ -137,7 +137,8 @@ struct JtArgs {
 void jt_bf16(Exec& ex, const JtArgs& a);
 int64_t jt_ld(int64_t N);
 void gram_bf16(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64_t N, float scale, float* C, int64_t ldc);
-// variant 1: register-staged Gram kernel; otherwise the LDS-staged one (default)
+// variant 1: register-staged Gram kernel; 2: LDS-staged with 32-example chunks in 4 stages;
+// otherwise LDS-staged with 64-example chunks in 2 stages (default)
 void gram_bf16_variant(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64_t N, float scale, float* C,
                        int64_t ldc, int variant);
 

@@ -166,29 +166,40 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(const __bf16* __restrict
 // ---------------------------------------------------------------------------
 // Gram product with direct HBM -> LDS staging (buffer_load_dwordx4 ... lds).
 //
-// Same 256 x 256 tiles and wavefront layout as above, K chunks of GD = 32 examples in
-// GS = 4 LDS stages (one barrier per chunk; the copies of a chunk are issued three chunks
-// ahead).  Tiles are visited in the grouped lower-triangle order, so the tiles an XCD
-// runs at once share eight row panels and a few column panels in its L2.  A stage holds the two 256-row panels, 64 bytes (4 segments of 8 BF16) per
-// row.  Each lane copies one 16-byte segment; segments are stored at position
-// row * 4 + (seg ^ ((row >> 2) & 3)) so that the 16 lanes of an MFMA operand read
-// (rows row16 = 0..15, one segment) fall on 16 different 4-bank groups.  Rows past P
+// Same 256 x 256 tiles and wavefront layout as above; K chunks of GD examples in GS LDS
+// stages, one barrier per chunk, the copies of a chunk issued GS - 1 chunks ahead.  Tiles
+// are visited in the grouped lower-triangle order, so the tiles an XCD runs at once share
+// eight row panels and a few column panels in its L2.  A stage holds the two 256-row
+// panels, GD / 8 segments of 8 BF16 (16 bytes) per row.  Each lane copies one segment,
+// stored at position row * (GD / 8) + (seg ^ swz(row)): the swizzle puts the lanes of an
+// MFMA operand read (16 consecutive rows, one segment) on distinct bank groups whether
+// the LDS serves 8 lanes per 128-byte cycle or 16 lanes per 256-byte cycle.  Rows past P
 // are clamped to row P - 1 (their outputs are discarded); Jt columns n >= N are zero.
 // ---------------------------------------------------------------------------
-constexpr int GD = 32, GS = 4;
-constexpr int GSTAGE = 2 * GB * GD;  // BF16 elements per stage
-
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
   static_assert(N >= 0 && N < 64, "vmcnt range");
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0f70);
 }
 
-__global__ __launch_bounds__(256) void gram_bf16_dma_kernel(const __bf16* __restrict__ Jt, int64_t P, int64_t ldk,
-                                                            float scale, float* __restrict__ C, int64_t ldc,
-                                                            int64_t ntiles) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __bf16* S = reinterpret_cast<__bf16*>(smem);
+// Segment swizzle of a row (tile-local row index, bits 0..3 used): with GD = 32 (4
+// segments) and GD = 64 (8 segments) the 8 lanes of a 128-byte LDS cycle and the 16 lanes
+// of a 256-byte cycle both hit distinct bank groups.
+template <int GD>
+__device__ __forceinline__ int seg_swz(int row) {
+  return GD == 32 ? (((row >> 1) ^ ((row >> 3) & 1)) & 3) : ((row ^ ((row >> 3) & 1)) & 7);
+}
+
+extern __shared__ __attribute__((aligned(16))) unsigned char gram_smem[];
+
+template <int GD, int GS>
+__device__ __forceinline__ void gram_dma_tile(const __bf16* __restrict__ Jt, int64_t P, int64_t ldk, float scale,
+                                              float* __restrict__ C, int64_t ldc, int64_t ntiles) {
+  constexpr int NSEG = GD / 8;            // 16-byte segments per row and chunk
+  constexpr int RPC = 64 / NSEG;          // rows per copy (64 lanes)
+  constexpr int CPW = GB / RPC / 4;       // copies per panel and wavefront
+  constexpr int GSTAGE = 2 * GB * GD;     // BF16 elements per stage
+  __bf16* S = reinterpret_cast<__bf16*>(gram_smem);
 
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
   if (t < 0) return;
@@ -202,12 +213,12 @@ __global__ __launch_bounds__(256) void gram_bf16_dma_kernel(const __bf16* __rest
   const int wr = wave >> 1, wc = wave & 1;
   const int row16 = lane & 15, q = lane >> 4;
 
-  // copy m (0..3) of this wavefront moves rows 16 * (4 * wave + m) .. + 15 of a panel
-  int voffA[4], voffB[4];
+  // copy m of this wavefront moves rows RPC * (CPW * wave + m) .. + RPC - 1 of a panel
+  int voffA[CPW], voffB[CPW];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int row = 16 * (4 * wave + m) + (lane >> 2);
-    const int seg = (lane & 3) ^ ((row >> 2) & 3);
+  for (int m = 0; m < CPW; ++m) {
+    const int row = RPC * (CPW * wave + m) + lane / NSEG;
+    const int seg = (lane % NSEG) ^ seg_swz<GD>(row);
     const int64_t ra = std::min<int64_t>(r0 + row, P - 1) - r0, rb = std::min<int64_t>(c0 + row, P - 1) - c0;
     voffA[m] = (int)((ra * ldk + seg * 8) * 2);
     voffB[m] = (int)((rb * ldk + seg * 8) * 2);
@@ -220,13 +231,14 @@ __global__ __launch_bounds__(256) void gram_bf16_dma_kernel(const __bf16* __rest
     const __amdgpu_buffer_rsrc_t rb =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16*>(Jt + c0 * ldk + k0), (short)0, 0x7ffffff0, 0x00020000);
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (__attribute__((address_space(3))) void*)(D + (4 * wave + m) * 16 * GD),
-                                               16, voffA[m], 0, 0, 0);
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < CPW; ++m)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rb, (__attribute__((address_space(3))) void*)(D + GB * GD + (4 * wave + m) * 16 * GD), 16, voffB[m], 0, 0, 0);
+          ra, (__attribute__((address_space(3))) void*)(D + (CPW * wave + m) * RPC * GD), 16, voffA[m], 0, 0, 0);
+#pragma unroll
+    for (int m = 0; m < CPW; ++m)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rb, (__attribute__((address_space(3))) void*)(D + GB * GD + (CPW * wave + m) * RPC * GD), 16, voffB[m], 0, 0,
+          0);
   };
 
   f4_t acc[8][8];
@@ -235,27 +247,31 @@ __global__ __launch_bounds__(256) void gram_bf16_dma_kernel(const __bf16* __rest
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-  const int sw = (q ^ ((row16 >> 2) & 3)) * 8;  // swizzled segment of this lane's k = 8q .. 8q + 7
+  const int sw = seg_swz<GD>(row16);  // operand rows r satisfy r % 16 == row16
 #pragma unroll
   for (int c = 0; c < GS - 1; ++c)
     if (c < nk) issue(c, (int64_t)c * GD);
   for (int64_t kc = 0; kc < nk; ++kc) {
-    // chunk kc's copies are the oldest in flight: up to two later chunks may stay pending
+    // chunk kc's copies are the oldest in flight; up to GS - 2 later chunks may stay pending
     const int64_t later = std::min<int64_t>(GS - 2, nk - 1 - kc);
-    if (later >= 2) wait_vmcnt<16>(); else if (later == 1) wait_vmcnt<8>(); else wait_vmcnt<0>();
+    if (later >= 2) wait_vmcnt<4 * CPW>(); else if (later == 1) wait_vmcnt<2 * CPW>(); else wait_vmcnt<0>();
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
     if (kc + GS - 1 < nk) issue((int)((kc + GS - 1) % GS), (kc + GS - 1) * GD);
     const __bf16* As = S + (kc % GS) * GSTAGE;
     const __bf16* Bs = diag ? As : As + GB * GD;
-    bf8_t av[8], bv[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) av[i] = *reinterpret_cast<const bf8_t*>(&As[(wr * 128 + i * 16 + row16) * GD + sw]);
+    for (int ks = 0; ks < GD / 32; ++ks) {
+      const int off = ((4 * ks + q) ^ sw) * 8;  // segment of k = 32 ks + 8q .. + 7
+      bf8_t av[8], bv[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) bv[j] = *reinterpret_cast<const bf8_t*>(&Bs[(wc * 128 + j * 16 + row16) * GD + sw]);
+      for (int i = 0; i < 8; ++i) av[i] = *reinterpret_cast<const bf8_t*>(&As[(wr * 128 + i * 16 + row16) * GD + off]);
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j) bv[j] = *reinterpret_cast<const bf8_t*>(&Bs[(wc * 128 + j * 16 + row16) * GD + off]);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) acc[i][j] = mma_bf16(av[i], bv[j], acc[i][j]);
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = mma_bf16(av[i], bv[j], acc[i][j]);
+    }
   }
 
 #pragma unroll
@@ -273,6 +289,27 @@ __global__ __launch_bounds__(256) void gram_bf16_dma_kernel(const __bf16* __rest
         if (r != c) C[c * ldc + r] = val;
       }
     }
+}
+
+template <int GD, int GS>
+__global__ __launch_bounds__(256) void gram_bf16_dma_kernel(const __bf16* __restrict__ Jt, int64_t P, int64_t ldk,
+                                                            float scale, float* __restrict__ C, int64_t ldc,
+                                                            int64_t ntiles) {
+  gram_dma_tile<GD, GS>(Jt, P, ldk, scale, C, ldc, ntiles);
+}
+
+template <int GD, int GS>
+void launch_gram_dma(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, float scale, float* C, int64_t ldc,
+                     int64_t nt) {
+  constexpr int shm = GS * 2 * GB * GD * (int)sizeof(__bf16);
+  static const bool attr = [] {
+    (void)hipFuncSetAttribute((const void*)gram_bf16_dma_kernel<GD, GS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              shm);
+    return true;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL((gram_bf16_dma_kernel<GD, GS>), dim3((unsigned)xcd_grid(nt)), dim3(256), shm, ex.stream, Jt, P,
+                     ldk, scale, C, ldc, nt);
 }
 
 }  // namespace
@@ -298,15 +335,8 @@ void gram_bf16_variant(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64
   const int tok = prof_begin(ex, "gram_bf16_sym", 2.0 * N * entries, (double)P * ldk * 2.0 + (double)P * P * 4.0);
   // LDS-staged form needs every copy offset below 2^31 bytes (255 rows of ldk BF16)
   if (variant != 1 && (int64_t)GB * ldk * 2 < 0x7fff0000) {
-    const size_t shm = (size_t)GS * GSTAGE * sizeof(__bf16);
-    static const bool attr = [shm] {
-      (void)hipFuncSetAttribute((const void*)gram_bf16_dma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)shm);
-      return true;
-    }();
-    (void)attr;
-    hipLaunchKernelGGL(gram_bf16_dma_kernel, dim3((unsigned)xcd_grid(nt)), dim3(256), shm, ex.stream, Jt, P, ldk,
-                       scale, C, ldc, nt);
+    if (variant == 2) launch_gram_dma<32, 4>(ex, Jt, P, ldk, scale, C, ldc, nt);
+    else launch_gram_dma<64, 2>(ex, Jt, P, ldk, scale, C, ldc, nt);
   } else {
     const size_t shm = 2 * GB * GKP * sizeof(__bf16);
     static const bool attr = [shm] {
