@@ -374,12 +374,29 @@ struct EigBufs {
 
 }  // namespace
 
-// Slices of the dense FP32 apply (b x P times P x P): enough workgroups to fill the
-// device when the output alone has few 128 x 128 tiles.
+// Slices of the dense FP32 apply (b x P times P x P): the output alone has few 128 x 128
+// tiles, so the contraction over P is split into slices; the count is chosen so that the
+// workgroups fill whole rounds of the device's resident slots (three per compute unit).
 static void dense_slices(int64_t P, int64_t b, int64_t& ks, int64_t& kslice) {
+  static const int64_t slots = [] {
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return 3 * (int64_t)std::max(cus, 1);
+  }();
   const int64_t tiles = ((b + 127) / 128) * ((P + 127) / 128);
-  ks = std::max<int64_t>(1, std::min<int64_t>(8, (2048 + tiles - 1) / tiles));
-  kslice = rup((P + ks - 1) / ks, 32);
+  int64_t best = 1;
+  double best_eff = -1.0;
+  for (int64_t k = 1; k <= 12 && (k == 1 || P / k >= 1024); ++k) {
+    const int64_t w = tiles * k, rounds = (w + slots - 1) / slots;
+    // fraction of slot time doing work; one round or fewer is charged as under-filled
+    const double eff = (double)w / (double)(std::max<int64_t>(rounds, 2) * slots);
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = k;
+    }
+  }
+  kslice = rup((P + best - 1) / best, 32);
   ks = (P + kslice - 1) / kslice;
 }
 

@@ -23,6 +23,7 @@
 // the lower triangle of tiles and mirror every stored entry, so the result is
 // exactly symmetric.
 #include <algorithm>
+#include <string>
 #include <type_traits>
 
 #include "mfma.h"
@@ -732,13 +733,17 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
                                 {{"krg_f64_rank1", "krg_f64_rank1_sym"}, {"krg_f64_pair", "krg_f64_pair_sym"},
                                  {"krg_f64_pairdiag", "krg_f64_pairdiag_sym"}}};
   const int ks = std::max(1, a.ksplit);
-  const int tok = prof_begin(ex, a.label ? a.label : names[sizeof(T) == 8][a.wmode][a.symmetric ? 1 : 0],
-                             2.0 * a.N * entries, src + wbytes + obytes * ks);
+  // FP32 default: the LDS-staged tile, one kernel instance per units-per-tile bound; the
+  // profile name carries that bound so that a profile class is one kernel instance
+  const int maxu = dma_maxu(std::min(a.r.pad, a.c.pad));
+  bool dma = false;
+  if constexpr (sizeof(T) == 4) dma = (variant == 0 || variant >= 5) && dma_fits(a, maxu);
+  std::string label = a.label ? a.label : names[sizeof(T) == 8][a.wmode][a.symmetric ? 1 : 0];
+  if (dma && !a.label) label += "_u" + std::to_string(maxu);
+  const int tok = prof_begin(ex, label.c_str(), 2.0 * a.N * entries, src + wbytes + obytes * ks);
   dim3 grid((unsigned)xcd_grid(nt * ks));
   if constexpr (sizeof(T) == 4) {
-    // default FP32 path: the LDS-staged tile
-    const int maxu = dma_maxu(std::min(a.r.pad, a.c.pad));
-    if ((variant == 0 || variant >= 5) && dma_fits(a, maxu)) {
+    if (dma) {
       auto go = [&](auto cfg) {
         using C = decltype(cfg);
         if (maxu == 2) launch_dma<2, C>(ex, a, grid, tc, nt);
