@@ -7,8 +7,8 @@ Networks m = 0..M-1 follow the batch distribution (seed 4000 + m: T_1 ~ U{8..128
 H and OPG (FP32, P_m^2 entries each) total more than the device holds, so networks are
 packed into waves whose outputs plus workspace fit in the budget; each wave is one
 hess_batched call (one persistent contraction launch over all its networks' tiles).
-After a wave, every output is reduced to (trace, Frobenius norm) and the memory is
-reused.  Prints one JSON line with P^2-entries/s and algorithmic TFLOP/s.
+Outputs are views into one buffer allocated once; after a wave, every output is
+reduced to (trace, Frobenius norm) and the buffer is reused by the next wave.  Prints one JSON line with P^2-entries/s and algorithmic TFLOP/s.
 """
 from __future__ import annotations
 
@@ -49,28 +49,41 @@ def main():
     if cur:
         waves.append(cur)
     summary = []
+    # outputs of every wave are views into one buffer allocated once (no per-wave
+    # allocation or release of tens of GB); the library workspace only grows
+    cap = max(sum(2 * n[0] * n[0] for n in wv) for wv in waves)
+    pool = torch.empty(cap, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     flops = 0.0
     entries = 0.0
     for i, wv in enumerate(waves):
         tw = time.perf_counter()
-        Hs, Gs = api.hess_batched([n[2] for n in wv], [n[3] for n in wv], [n[4] for n in wv], ctx=ctx)
+        outs, off = [], 0
+        for n in wv:
+            P2 = n[0] * n[0]
+            outs.append((pool[off:off + P2].view(n[0], n[0]), pool[off + P2:off + 2 * P2].view(n[0], n[0])))
+            off += 2 * P2
+        Hs, Gs = api.hess_batched([n[2] for n in wv], [n[3] for n in wv], [n[4] for n in wv],
+                                  outs_H=[o[0] for o in outs], outs_G=[o[1] for o in outs], ctx=ctx)
+        torch.cuda.synchronize()
+        t_call = time.perf_counter() - tw
         red = [(float(torch.trace(H)), float(H.norm()), float(torch.trace(G)), float(G.norm())) for H, G in zip(Hs, Gs)]
-        del Hs, Gs
-        ctx.release_workspace()
-        torch.cuda.empty_cache()
+        t_red = time.perf_counter() - tw - t_call
+        del Hs, Gs, outs
         dt = time.perf_counter() - tw
         for (P, N, _, _, _) in wv:
             flops += 2 * 2.0 * N * P * (P + 1) / 2
             entries += 2.0 * P * P
-        summary.append({"wave": i, "networks": len(wv), "seconds": dt, "P_max": wv[0][0]})
+        summary.append({"wave": i, "networks": len(wv), "seconds": dt, "call_s": t_call, "reduce_s": t_red,
+                        "P_max": wv[0][0]})
         print("wave %d: %d networks (P <= %d) in %.2f s" % (i, len(wv), wv[0][0], dt), file=sys.stderr, flush=True)
     total = time.perf_counter() - t0
     prof = ctx.profile()
     out = {"metric": "batched exact-H+OPG P^2-entries/s", "networks": len(nets), "waves": len(waves),
            "seconds": total, "p2_entries_per_s": entries / total, "algorithmic_tflops": flops / total / 1e12,
            "persistent_launch_tflops": {k: v["flops"] / v["ms"] / 1e9 for k, v in prof.items() if "persistent" in k},
+           "kernel_ms": {k: round(v["ms"], 1) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])},
            "wave_detail": summary}
     print(json.dumps(out), flush=True)
 
