@@ -83,7 +83,7 @@ typedef struct {
 /* Operation codes for hess_workspace_size. */
 typedef enum {
   HESS_OP_EXACT = 0, HESS_OP_OPG = 1, HESS_OP_HVP = 2, HESS_OP_TOPK = 3, HESS_OP_PREDVAR = 4,
-  HESS_OP_BATCHED = 5
+  HESS_OP_BATCHED = 5, HESS_OP_EXACT_COLS = 6
 } hess_op;
 
 /* Create a context on `device`; `stream` is a hipStream_t (NULL = the null stream). */
@@ -99,10 +99,28 @@ const char* hess_last_error(const hess_ctx* ctx);
  * HESS_E_BUDGET before launching anything.  HESS_OPT_FAULT_AFTER: test hook; when
  * >= 0, the call during which that many kernel launches have been issued on this
  * context reports HESS_E_DEVICE (no kernel faults; the launch is skipped). */
+/* HESS_OPT_GRAPHS (default 1): inside hess_topk_eig, the operator application (the
+ * sweep of Hessian-vector products, OPG products or the dense product) for each pair
+ * of block buffers is captured once as a HIP graph and replayed for every later
+ * application; results are bitwise the same as without graphs.  Graphs are not used
+ * while HESS_OPT_PROFILE or HESS_OPT_FAULT_AFTER is active.
+ * HESS_OPT_AUTOTUNE (default 0): the first FP32 contraction launch and the first BF16
+ * Gram product of each shape class times every tile configuration of that kernel
+ * (example chunk and LDS stage count) on a bounded sample of its tiles, synchronising
+ * the stream, and caches the fastest for the context (contractions that accumulate into
+ * their output keep the default); all configurations give bitwise identical results.
+ * hess_autotune_report lists the decisions. */
 typedef enum {
-  HESS_OPT_CHECK_INPUTS = 0, HESS_OPT_HBM_BUDGET = 1, HESS_OPT_FAULT_AFTER = 2, HESS_OPT_PROFILE = 3
+  HESS_OPT_CHECK_INPUTS = 0, HESS_OPT_HBM_BUDGET = 1, HESS_OPT_FAULT_AFTER = 2, HESS_OPT_PROFILE = 3,
+  HESS_OPT_GRAPHS = 4, HESS_OPT_AUTOTUNE = 5
 } hess_opt;
 hess_status hess_set_option(hess_ctx* ctx, int opt, int64_t value);
+
+/* Text report of the autotuning decisions of this context, one line per shape class
+ * (candidate times in ms and the choice).  Writes at most len bytes including the
+ * terminating NUL into buf (host memory, may be NULL); *needed (may be NULL) receives
+ * the full length + 1. */
+hess_status hess_autotune_report(hess_ctx* ctx, char* buf, size_t len, size_t* needed);
 
 /* Per-kernel timing.  With HESS_OPT_PROFILE = 1 every P x P contraction and every
  * GEMM launch is bracketed by HIP events on the context stream; the elapsed times
@@ -124,7 +142,8 @@ hess_status hess_profile_reset(hess_ctx* ctx);
 /* P of the model (Sec. 2).  Host-only; validates the widths. */
 hess_status hess_num_params(const hess_mlp* m, int64_t* P);
 
-/* Bytes of workspace `op` needs.  `arg` is B for HESS_OP_HVP, K for HESS_OP_TOPK,
+/* Bytes of workspace `op` needs.  `arg` is B for HESS_OP_HVP, ncols for
+ * HESS_OP_EXACT_COLS, K for HESS_OP_TOPK,
  * the number of queries for HESS_OP_PREDVAR, the number of networks M for
  * HESS_OP_BATCHED (then `m` and `d` point to arrays of M entries), unused otherwise.
  * For HESS_OP_TOPK `opts` is a const hess_eig_opts*, else NULL.  `data` may be NULL
@@ -155,6 +174,14 @@ hess_status hess_opg(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int p
  * for HESS_P_F64 else FP32.  prec: HESS_P_F64 or HESS_P_F32. */
 hess_status hess_hvp(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int prec,
                      int64_t B, const void* V, void* HV, void* ws, size_t ws_bytes);
+
+/* Columns col0 .. col0 + ncols - 1 of the exact H (paper, Sec. 5.1: the Hessian-vector
+ * product with the j-th unit vector is column j of H), computed as HVPs with basis
+ * directions in blocks of up to 512 columns.  Hcols: device, P x ncols row-major, FP64
+ * for HESS_P_F64 else FP32.  prec: HESS_P_F64 or HESS_P_F32.  Errors: HESS_E_SHAPE if
+ * the column range is empty or leaves [0, P); otherwise as hess_hvp. */
+hess_status hess_exact_cols(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int prec,
+                            int64_t col0, int64_t ncols, void* Hcols, void* ws, size_t ws_bytes);
 
 typedef struct {
   int32_t which;        /* 0 = H, 1 = OPG (used when source == 0) */

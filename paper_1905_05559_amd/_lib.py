@@ -16,13 +16,13 @@ STATUS_NAMES = {
 ACT = {"tanh": 0, "sigmoid": 1, "relu": 2}
 DTYPE = {"float64": 0, "float32": 1}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
-OP = {"exact": 0, "opg": 1, "hvp": 2, "topk": 3, "predvar": 4, "batched": 5}
-OPT = {"check_inputs": 0, "hbm_budget": 1, "fault_after": 2, "profile": 3}
+OP = {"exact": 0, "opg": 1, "hvp": 2, "topk": 3, "predvar": 4, "batched": 5, "exact_cols": 6}
+OPT = {"check_inputs": 0, "hbm_budget": 1, "fault_after": 2, "profile": 3, "graphs": 4, "autotune": 5}
 
 # Every symbol include/hess.h declares.
 EXPORTS = (
-    "hess_create", "hess_destroy", "hess_status_str", "hess_last_error", "hess_set_option",
-    "hess_num_params", "hess_workspace_size", "hess_exact", "hess_opg", "hess_hvp",
+    "hess_create", "hess_destroy", "hess_status_str", "hess_last_error", "hess_set_option", "hess_autotune_report",
+    "hess_num_params", "hess_workspace_size", "hess_exact", "hess_opg", "hess_hvp", "hess_exact_cols",
     "hess_topk_eig", "hess_predvar", "hess_profile_read", "hess_profile_reset", "hess_batched",
     "hess_server_create", "hess_server_submit", "hess_server_wait", "hess_server_stats", "hess_server_destroy",
 )
@@ -84,6 +84,8 @@ def load(path: str = LIB_PATH):
         "hess_exact": (st, [vp, pm, pd, C.c_int, vp, vp, C.c_size_t]),
         "hess_opg": (st, [vp, pm, pd, C.c_int, vp, vp, C.c_size_t]),
         "hess_hvp": (st, [vp, pm, pd, C.c_int, i64, vp, vp, vp, C.c_size_t]),
+        "hess_exact_cols": (st, [vp, pm, pd, C.c_int, i64, i64, vp, vp, C.c_size_t]),
+        "hess_autotune_report": (st, [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
         "hess_topk_eig": (st, [vp, pm, pd, i64, C.POINTER(HessEigOpts), vp, vp,
                                C.POINTER(HessEigInfo), vp, C.c_size_t]),
         "hess_predvar": (st, [vp, pm, i64, vp, vp, C.c_double, i64, vp, vp, vp, vp, C.c_size_t]),

@@ -56,6 +56,14 @@ class Context:
     def set_option(self, name: str, value: int):
         self._check(self.lib.hess_set_option(self.h, L.OPT[name], int(value)))
 
+    def autotune_report(self) -> str:
+        """The autotuning decisions of this context (see hess_autotune_report)."""
+        need = C.c_size_t()
+        self._check(self.lib.hess_autotune_report(self.h, None, 0, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        self._check(self.lib.hess_autotune_report(self.h, buf, need.value, None))
+        return buf.value.decode()
+
     def profile(self) -> dict:
         """Per-kernel-class aggregates {name: {launches, ms, flops, bytes}} since the last reset."""
         buf = (L.HessProfEntry * 64)()
@@ -198,6 +206,21 @@ def hess_hvp(model: MLP, X: torch.Tensor, Y: torch.Tensor, V: torch.Tensor, prec
     ws = ctx.workspace(nb)
     ctx._check(ctx.lib.hess_hvp(ctx.h, C.byref(m), C.byref(d), L.PREC[prec], B, V.data_ptr(),
                                 out.data_ptr(), ws.data_ptr(), ws.numel()))
+    return out
+
+
+def hess_exact_cols(model: MLP, X: torch.Tensor, Y: torch.Tensor, col0: int, ncols: int, prec: str = "f32",
+                    out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """Columns col0 .. col0+ncols-1 of H (P x ncols), see hess_exact_cols in include/hess.h."""
+    ctx = ctx or default_context()
+    if out is None:
+        out = torch.empty((model.P, ncols), dtype=torch.float64 if prec == "f64" else torch.float32,
+                          device=X.device)
+    m, d = model.struct(), _data(X, Y)
+    nb = workspace_size("exact_cols", model, X, Y, prec, arg=ncols, ctx=ctx)
+    ws = ctx.workspace(nb)
+    ctx._check(ctx.lib.hess_exact_cols(ctx.h, C.byref(m), C.byref(d), L.PREC[prec], int(col0), int(ncols),
+                                       out.data_ptr(), ws.data_ptr(), ws.numel()))
     return out
 
 

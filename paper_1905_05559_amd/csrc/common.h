@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,12 @@ struct Exec {
 };
 
 bool launch_ok(Exec& ex);   // fault-injection hook + hipGetLastError check
+
+// Autotuning: for a shape-class key, run each candidate launch (in-bounds, on a bounded
+// sample of the work) twice, time the second run with HIP events on the call's stream
+// and keep the fastest; the decision is cached per context.  Returns the candidate index.
+int autotune_pick(Exec& ex, const std::string& key, int ncand, const char* const* names,
+                  const std::function<void(int)>& launch);
 
 // Profiling brackets around one launch (no-ops unless HESS_OPT_PROFILE is set).
 int prof_begin(Exec& ex, const char* name, double flops, double bytes);
@@ -212,4 +219,9 @@ struct hess_ctx {
   int64_t fault_after = -1;
   int64_t launches = 0;
   bool fault_hit = false;
+  int graphs = 1;                       // capture repeated operator applications as HIP graphs
+  int autotune = 0;                     // time the tile configurations per shape class
+  std::vector<std::pair<std::string, int>> tuned;  // shape class -> chosen configuration
+  std::string tune_log;                 // one line per decision
+  hipStream_t capture_stream = nullptr;  // created on first capture (graphs cannot be captured on the null stream)
 };

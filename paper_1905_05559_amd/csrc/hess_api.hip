@@ -23,6 +23,41 @@ bool launch_ok(Exec& ex) {
   return true;
 }
 
+int autotune_pick(Exec& ex, const std::string& key, int ncand, const char* const* names,
+                  const std::function<void(int)>& launch) {
+  hess_ctx* c = ex.ctx;
+  for (const auto& kv : c->tuned)
+    if (kv.first == key) return kv.second;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return 0;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return 0;
+  }
+  int best = 0;
+  float best_ms = 0.f;
+  std::string line = key + ":";
+  for (int i = 0; i < ncand; ++i) {
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+      (void)hipEventRecord(e0, ex.stream);
+      launch(i);
+      (void)hipEventRecord(e1, ex.stream);
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 1e30f;
+    }
+    line += " " + std::string(names[i]) + "=" + std::to_string(ms) + "ms";
+    if (i == 0 || ms < best_ms) {
+      best = i;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tuned.emplace_back(key, best);
+  c->tune_log += line + " -> " + names[best] + "\n";
+  return best;
+}
+
 int prof_begin(Exec& ex, const char* name, double flops, double bytes) {
   hess_ctx* c = ex.ctx;
   if (!c->profile) return -1;
@@ -606,6 +641,7 @@ hess_status hess_destroy(hess_ctx* ctx) {
       prof_collect(ctx);
     }
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   }
   delete ctx;
   return HESS_OK;
@@ -657,8 +693,22 @@ hess_status hess_set_option(hess_ctx* ctx, int opt, int64_t value) {
     case HESS_OPT_HBM_BUDGET: ctx->hbm_budget = value; return HESS_OK;
     case HESS_OPT_FAULT_AFTER: ctx->fault_after = value; ctx->launches = 0; return HESS_OK;
     case HESS_OPT_PROFILE: ctx->profile = value != 0; return HESS_OK;
+    case HESS_OPT_GRAPHS: ctx->graphs = value != 0; return HESS_OK;
+    case HESS_OPT_AUTOTUNE: ctx->autotune = value != 0; return HESS_OK;
   }
   return fail(ctx, HESS_E_ARG, "unknown option");
+}
+
+hess_status hess_autotune_report(hess_ctx* ctx, char* buf, size_t len, size_t* needed) {
+  if (!ctx) return HESS_E_ARG;
+  const std::string& t = ctx->tune_log;
+  if (needed) *needed = t.size() + 1;
+  if (buf && len) {
+    const size_t n = std::min(len - 1, t.size());
+    std::memcpy(buf, t.data(), n);
+    buf[n] = 0;
+  }
+  return HESS_OK;
 }
 
 hess_status hess_num_params(const hess_mlp* m, int64_t* P) {
@@ -709,6 +759,10 @@ hess_status hess_workspace_size(hess_ctx* ctx, int op, const hess_mlp* mlp, cons
       return predvar_workspace(ctx, m, prec, arg, bytes);
     case HESS_OP_BATCHED:
       return batched_workspace(ctx, arg, mlp, d, bytes);
+    case HESS_OP_EXACT_COLS:
+      if ((s = validate_mlp(ctx, mlp, m, false)) != HESS_OK) return s;
+      if ((s = validate_data(ctx, d, false)) != HESS_OK) return s;
+      return exact_cols_workspace(ctx, m, d->N, prec, arg, bytes);
   }
   return fail(ctx, HESS_E_ARG, "unknown op");
 }

@@ -440,6 +440,8 @@ void set_lds_limits() {
   done = true;
 }
 
+struct GraphCache;
+
 struct EigRun {
   Exec* ex;
   EigBufs* e;
@@ -447,6 +449,7 @@ struct EigRun {
   int64_t N;
   int source, which, prec, Mdtype;
   const void* M;
+  GraphCache* gc = nullptr;  // captured operator applications (nullptr: always eager)
 };
 
 // Y = Op Q (rows), both b x ldp FP64
@@ -503,6 +506,82 @@ void op_apply(EigRun& r, const double* Q, double* Y) {
   }
 }
 
+// Operator applications captured as HIP graphs: the first application for a (Q, Y) pair
+// runs eagerly, the second is captured on the context's capture stream (the null stream
+// cannot be captured) and launched on the call's stream, later ones replay the graph.
+// The captured sequence holds kernel launches only (no memsets, copies or host waits).
+struct GraphCache {
+  struct Ent {
+    const double* q;
+    double* y;
+    int uses;
+    hipGraphExec_t exec;
+  };
+  std::vector<Ent> ents;
+  bool disabled = false;
+  ~GraphCache() {
+    for (auto& e : ents)
+      if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  }
+};
+
+void apply_op(EigRun& r, GraphCache* gc, const double* Q, double* Y) {
+  Exec& ex = *r.ex;
+  hess_ctx* c = ex.ctx;
+  if (!gc || gc->disabled || c->profile || c->fault_after >= 0) {
+    op_apply(r, Q, Y);
+    return;
+  }
+  GraphCache::Ent* ent = nullptr;
+  for (auto& e : gc->ents)
+    if (e.q == Q && e.y == Y) ent = &e;
+  if (!ent) {
+    gc->ents.push_back(GraphCache::Ent{Q, Y, 0, nullptr});
+    ent = &gc->ents.back();
+  }
+  ent->uses++;
+  if (ent->exec) {
+    if (hipGraphLaunch(ent->exec, ex.stream) != hipSuccess) {
+      (void)hipGetLastError();
+      ex.ctx->fault_hit = true;
+    }
+    return;
+  }
+  if (ent->uses == 1) {
+    op_apply(r, Q, Y);
+    return;
+  }
+  if (!c->capture_stream && hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    c->capture_stream = nullptr;
+    gc->disabled = true;
+    op_apply(r, Q, Y);
+    return;
+  }
+  const hipStream_t run = ex.stream;
+  hipGraph_t g = nullptr;
+  bool ok = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    ex.stream = c->capture_stream;
+    op_apply(r, Q, Y);
+    ex.stream = run;
+    ok = hipStreamEndCapture(c->capture_stream, &g) == hipSuccess && g;
+  }
+  if (ok) ok = hipGraphInstantiate(&ent->exec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (!ok) {  // capture unavailable: stay eager for this call
+    (void)hipGetLastError();
+    ent->exec = nullptr;
+    gc->disabled = true;
+    op_apply(r, Q, Y);
+    return;
+  }
+  if (hipGraphLaunch(ent->exec, run) != hipSuccess) {
+    (void)hipGetLastError();
+    ex.ctx->fault_hit = true;
+  }
+}
+
 // C (b x b) = A B^T over ldp columns, split over KSPLIT columns and summed in order
 void gram(EigRun& r, const double* A, const double* B, double* C) {
   Exec& ex = *r.ex;
@@ -539,7 +618,7 @@ void rayleigh_ritz(EigRun& r, int* sweeps) {
   Exec& ex = *r.ex;
   EigBufs& e = *r.e;
   const int b = (int)e.b;
-  op_apply(r, e.Q, e.MQ);
+  apply_op(r, r.gc, e.Q, e.MQ);
   gram(r, e.Q, e.MQ, e.T);
   const int n = (b + 1) & ~1;
   const size_t shm = (size_t)n * (n + 1) * sizeof(double);
@@ -647,6 +726,8 @@ extern "C" hess_status hess_topk_eig(hess_ctx* ctx, const hess_mlp* mlp, const h
   set_lds_limits();
   EigRun r{&ex, &e, t.has_model ? &t.m : nullptr, t.N, t.source, t.which, t.prec, t.Mdtype,
            t.source == 1 ? opts->M : nullptr};
+  GraphCache graphs;  // destroyed after the call has synchronised (finish)
+  if (ctx->graphs) r.gc = &graphs;
   const int64_t nb = e.b * e.ldp;
   if (launch_ok(ex))
     hipLaunchKernelGGL(k_fill, dim3(grid_for(16)), dim3(TPB), 0, ex.stream, reinterpret_cast<double*>(e.info),
@@ -660,7 +741,7 @@ extern "C" hess_status hess_topk_eig(hess_ctx* ctx, const hess_mlp* mlp, const h
   int applies = 0;
   // a few unfiltered block steps: estimate of the spectral radius
   for (int it = 0; it < 3; ++it) {
-    op_apply(r, e.Q, e.Y);
+    apply_op(r, r.gc, e.Q, e.Y);
     ++applies;
     orth(r, e.Y, e.Q);
   }
@@ -696,7 +777,7 @@ extern "C" hess_status hess_topk_eig(hess_ctx* ctx, const hess_mlp* mlp, const h
                          0.0, nullptr, nb, e.Y);
     hipMemcpyAsync(e.Yp, e.X, nb * sizeof(double), hipMemcpyDeviceToDevice, ex.stream);
     for (int j = 1; j < degree; ++j) {
-      op_apply(r, e.Y, e.Z);
+      apply_op(r, r.gc, e.Y, e.Z);
       ++applies;
       // Z <- 2 (Z - c Y) / hw - Yp ; then rotate (Yp, Y) <- (Y, Z)
       if (launch_ok(ex))

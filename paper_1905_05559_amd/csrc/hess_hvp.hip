@@ -355,6 +355,67 @@ template void opg_apply<double>(Exec&, const Model&, int64_t, int64_t, Prep&, Hv
 
 namespace {
 
+// ---- exact H columns through basis-direction HVPs ----
+constexpr int64_t EXC_B = 512;  // columns per block
+
+template <typename T>
+__global__ void k_basis(T* V, int64_t B, int64_t P, int64_t c0) {
+  GRID_STRIDE(i, B * P) { V[i] = (i % P == c0 + i / P) ? T(1) : T(0); }
+}
+
+// out[p * ldo + b] = HV[b * P + p] for b < B, p < P (32 x 32 tiles through LDS)
+template <typename T>
+__global__ void k_cols_from_rows(const T* HV, int64_t B, int64_t P, T* out, int64_t ldo) {
+  __shared__ T tile[32][33];
+  const int64_t p0 = (int64_t)blockIdx.x * 32, b0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t b = b0 + y, p = p0 + tx;
+    if (b < B && p < P) tile[y][tx] = HV[b * P + p];
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t p = p0 + y, b = b0 + tx;
+    if (b < B && p < P) out[p * ldo + b] = tile[tx][y];
+  }
+}
+
+template <typename T>
+size_t plan_exact_cols(Arena& ar, const Model& m, int64_t N, int64_t ncols, Prep& p, HvpBufs<T>& h, T*& V, T*& HV) {
+  const int64_t B = std::min(ncols, EXC_B);
+  plan_hvp<T>(ar, m, N, B, p, h);
+  V = ar.take<T>(B * m.P);
+  HV = ar.take<T>(B * m.P);
+  return ar.used;
+}
+
+template <typename T>
+void run_exact_cols(Exec& ex, const Model& m, int64_t N, Prep& p, HvpBufs<T>& h, T* V, T* HV, int64_t col0,
+                    int64_t ncols, T* out) {
+  hvp_setup<T>(ex, m, N, p, h);
+  for (int64_t cb = 0; cb < ncols; cb += EXC_B) {
+    const int64_t B = std::min(EXC_B, ncols - cb);
+    LAUNCH(k_basis<T>, B * m.P, V, B, m.P, col0 + cb);
+    hvp_apply<T>(ex, m, N, B, p, h, V, m.P, HV);
+    if (!launch_ok(ex)) return;
+    hipLaunchKernelGGL(k_cols_from_rows<T>, dim3((unsigned)((m.P + 31) / 32), (unsigned)((B + 31) / 32)), dim3(256), 0,
+                       ex.stream, HV, B, m.P, out + cb, ncols);
+  }
+}
+
+size_t ws_exact_cols(const Model& m, int64_t N, int prec, int64_t ncols) {
+  Arena ar(nullptr);
+  Prep p;
+  if (prec == HESS_P_F64) {
+    HvpBufs<double> h;
+    double *V, *HV;
+    return plan_exact_cols<double>(ar, m, N, ncols, p, h, V, HV);
+  }
+  HvpBufs<float> h;
+  float *V, *HV;
+  return plan_exact_cols<float>(ar, m, N, ncols, p, h, V, HV);
+}
+
 size_t ws_hvp(const Model& m, int64_t N, int prec, int64_t B) {
   Arena ar(nullptr);
   Prep p;
@@ -367,6 +428,13 @@ size_t ws_hvp(const Model& m, int64_t N, int prec, int64_t B) {
 }
 
 }  // namespace
+
+hess_status exact_cols_workspace(hess_ctx* ctx, const Model& m, int64_t N, int prec, int64_t ncols, size_t* bytes) {
+  if (prec != HESS_P_F64 && prec != HESS_P_F32) return fail(ctx, HESS_E_UNSUPPORTED, "H columns: F64 or F32 only");
+  if (ncols < 1) return fail(ctx, HESS_E_SHAPE, "ncols must be positive");
+  *bytes = ws_exact_cols(m, N, prec, ncols);
+  return HESS_OK;
+}
 
 hess_status hvp_workspace(hess_ctx* ctx, const Model& m, int64_t N, int prec, int64_t B, size_t* bytes) {
   if (prec != HESS_P_F64 && prec != HESS_P_F32) return fail(ctx, HESS_E_UNSUPPORTED, "HVP: F64 or F32 only");
@@ -411,4 +479,38 @@ extern "C" hess_status hess_hvp(hess_ctx* ctx, const hess_mlp* mlp, const hess_d
     hvp_apply<float>(ex, m, d->N, B, p, h, static_cast<const float*>(V), m.P, static_cast<float*>(HV));
   }
   return finish(ex, "hess_hvp");
+}
+
+extern "C" hess_status hess_exact_cols(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int prec, int64_t col0,
+                                       int64_t ncols, void* Hcols, void* ws, size_t ws_bytes) {
+  Exec ex;
+  hess_status s = begin(ctx, ex);
+  if (s != HESS_OK) return s;
+  Model m;
+  if ((s = validate_mlp(ctx, mlp, m, true)) != HESS_OK) return s;
+  if ((s = validate_data(ctx, d, true)) != HESS_OK) return s;
+  if (prec != HESS_P_F64 && prec != HESS_P_F32) return fail(ctx, HESS_E_UNSUPPORTED, "H columns: F64 or F32 only");
+  if (ncols < 1 || col0 < 0 || col0 > m.P - ncols) return fail(ctx, HESS_E_SHAPE, "column range outside [0, P)");
+  if (!Hcols) return fail(ctx, HESS_E_ARG, "Hcols is NULL");
+  const size_t need = ws_exact_cols(m, d->N, prec, ncols);
+  if ((s = check_ws(ctx, need, ws, ws_bytes, (size_t)ncols * m.P * (prec == HESS_P_F64 ? 8 : 4))) != HESS_OK)
+    return s;
+  Arena ar(ws);
+  Prep p;
+  if (prec == HESS_P_F64) {
+    HvpBufs<double> h;
+    double *V, *HV;
+    plan_exact_cols<double>(ar, m, d->N, ncols, p, h, V, HV);
+    if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
+    run_prep(ex, m, d, p, false);
+    run_exact_cols<double>(ex, m, d->N, p, h, V, HV, col0, ncols, static_cast<double*>(Hcols));
+  } else {
+    HvpBufs<float> h;
+    float *V, *HV;
+    plan_exact_cols<float>(ar, m, d->N, ncols, p, h, V, HV);
+    if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
+    run_prep(ex, m, d, p, false);
+    run_exact_cols<float>(ex, m, d->N, p, h, V, HV, col0, ncols, static_cast<float*>(Hcols));
+  }
+  return finish(ex, "hess_exact_cols");
 }

@@ -740,23 +740,48 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
   if constexpr (sizeof(T) == 4) dma = (variant == 0 || variant >= 5) && dma_fits(a, maxu);
   std::string label = a.label ? a.label : names[sizeof(T) == 8][a.wmode][a.symmetric ? 1 : 0];
   if (dma && !a.label) label += "_u" + std::to_string(maxu);
-  const int tok = prof_begin(ex, label.c_str(), 2.0 * a.N * entries, src + wbytes + obytes * ks);
   dim3 grid((unsigned)xcd_grid(nt * ks));
   if constexpr (sizeof(T) == 4) {
     if (dma) {
-      auto go = [&](auto cfg) {
-        using C = decltype(cfg);
-        if (maxu == 2) launch_dma<2, C>(ex, a, grid, tc, nt);
-        else if (maxu == 5) launch_dma<5, C>(ex, a, grid, tc, nt);
-        else launch_dma<9, C>(ex, a, grid, tc, nt);
+      // configuration: 0 = (16 examples, 2 stages), 1 = (16, 3), 2 = (32, 2)
+      auto go = [&](int cfg, dim3 g, int64_t ntl) {
+        auto run = [&](auto c) {
+          using C = decltype(c);
+          if (maxu == 2) launch_dma<2, C>(ex, a, g, tc, ntl);
+          else if (maxu == 5) launch_dma<5, C>(ex, a, g, tc, ntl);
+          else launch_dma<9, C>(ex, a, g, tc, ntl);
+        };
+        if (cfg == 1) run(DmaCfg<16, 3>());
+        else if (cfg == 2) run(DmaCfg<32, 2>());
+        else run(DmaDefault());
       };
-      if (variant == 5) go(DmaCfg<32, 2>());
-      else if (variant == 6) go(DmaCfg<16, 3>());
-      else go(DmaDefault());
+      int cfg = variant == 5 ? 2 : (variant == 6 ? 1 : 0);
+      // Probes write into the output, which the full launch then overwrites; a launch that
+      // accumulates into its output keeps the default configuration.
+      if (variant == 0 && ex.ctx->autotune && !a.accumulate && launch_ok(ex)) {
+        // probe on the first two device rounds of tiles (all of them if fewer)
+        static const int64_t slots = [] {
+          int dev = 0, cus = 256;
+          (void)hipGetDevice(&dev);
+          (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+          return 3 * (int64_t)std::max(cus, 1);
+        }();
+        const int64_t ntp = std::min(nt, std::max<int64_t>(1, 2 * slots / ks));
+        const dim3 gp((unsigned)xcd_grid(ntp * ks));
+        auto lg = [](int64_t v) { int b = 0; while (v > 1) { v >>= 1; ++b; } return b; };
+        const std::string key = "krg_f32 mode" + std::to_string(a.wmode) + (a.symmetric ? " sym" : "") + " u" +
+                                std::to_string(maxu) + " slices" + std::to_string(ks) + " tiles2^" +
+                                std::to_string(lg(nt)) + " N2^" + std::to_string(lg(a.N));
+        static const char* const cfgs[3] = {"chunk16x2", "chunk16x3", "chunk32x2"};
+        cfg = autotune_pick(ex, key, 3, cfgs, [&](int i) { go(i, gp, ntp); });
+      }
+      const int tok = prof_begin(ex, label.c_str(), 2.0 * a.N * entries, src + wbytes + obytes * ks);
+      go(cfg, grid, nt);
       prof_end(ex, tok);
       return;
     }
   }
+  const int tok = prof_begin(ex, label.c_str(), 2.0 * a.N * entries, src + wbytes + obytes * ks);
   if (ks > 1) {  // register-staged tile: one launch per slice of the example range
     grid = dim3((unsigned)xcd_grid(nt));
     for (int sp = 0; sp < ks; ++sp) {

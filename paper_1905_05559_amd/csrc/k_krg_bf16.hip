@@ -11,6 +11,7 @@
 //    4 wavefronts (2 x 2), each 128 x 128 = 8 x 8 MFMA blocks; K staged through LDS
 //    in chunks of 64 with 16-byte vector loads prefetched one chunk ahead.
 #include <algorithm>
+#include <string>
 
 #include "mfma.h"
 
@@ -332,11 +333,28 @@ void gram_bf16_variant(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64
   if (nt <= 0) return;
   if (!launch_ok(ex)) return;
   const double entries = (double)P * (P + 1) / 2;
-  const int tok = prof_begin(ex, "gram_bf16_sym", 2.0 * N * entries, (double)P * ldk * 2.0 + (double)P * P * 4.0);
   // LDS-staged form needs every copy offset below 2^31 bytes (255 rows of ldk BF16)
-  if (variant != 1 && (int64_t)GB * ldk * 2 < 0x7fff0000) {
-    if (variant == 2) launch_gram_dma<32, 4>(ex, Jt, P, ldk, scale, C, ldc, nt);
-    else launch_gram_dma<64, 2>(ex, Jt, P, ldk, scale, C, ldc, nt);
+  const bool dma = variant != 1 && (int64_t)GB * ldk * 2 < 0x7fff0000;
+  // configuration of the LDS-staged form: 0 = (64 examples, 2 stages), 1 = (32, 4)
+  auto go = [&](int cfg, int64_t ntl) {
+    if (cfg == 1) launch_gram_dma<32, 4>(ex, Jt, P, ldk, scale, C, ldc, ntl);
+    else launch_gram_dma<64, 2>(ex, Jt, P, ldk, scale, C, ldc, ntl);
+  };
+  int cfg = variant == 2 ? 1 : 0;
+  if (dma && variant == 0 && ex.ctx->autotune) {
+    // probe on the first two device rounds of tiles (one workgroup per compute unit)
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t ntp = std::min<int64_t>(nt, 2 * (int64_t)std::max(cus, 1));
+    auto lg = [](int64_t v) { int b = 0; while (v > 1) { v >>= 1; ++b; } return b; };
+    const std::string key = "gram_bf16 P2^" + std::to_string(lg(P)) + " N2^" + std::to_string(lg(ldk));
+    static const char* const cfgs[2] = {"chunk64x2", "chunk32x4"};
+    cfg = autotune_pick(ex, key, 2, cfgs, [&](int i) { go(i, ntp); });
+  }
+  const int tok = prof_begin(ex, "gram_bf16_sym", 2.0 * N * entries, (double)P * ldk * 2.0 + (double)P * P * 4.0);
+  if (dma) {
+    go(cfg, nt);
   } else {
     const size_t shm = 2 * GB * GKP * sizeof(__bf16);
     static const bool attr = [shm] {

@@ -76,6 +76,25 @@ def test_workspace_sizes_are_positive_and_monotone():
     assert lib.hess_workspace_size(None, 0, C.byref(m), C.byref(bad), 1, 0, None, C.byref(nb)) == 2
 
 
+def test_exact_cols_workspace_and_errors():
+    lib = _lib()
+    m = _mlp([64, 64, 10], [1])
+    d = L.HessData(1000, 1, None, None)
+    sizes = []
+    for ncols in (1, 100, 512, 513, 4000):
+        nb = C.c_size_t()
+        assert lib.hess_workspace_size(None, L.OP["exact_cols"], C.byref(m), C.byref(d), L.PREC["f32"], ncols,
+                                       None, C.byref(nb)) == 0
+        sizes.append(nb.value)
+    # blocks of at most 512 columns: the workspace stops growing past one block
+    assert sizes[0] < sizes[1] < sizes[2] == sizes[3] == sizes[4]
+    nb = C.c_size_t()
+    assert lib.hess_workspace_size(None, L.OP["exact_cols"], C.byref(m), C.byref(d), L.PREC["f32"], 0, None,
+                                   C.byref(nb)) == 2  # HESS_E_SHAPE
+    assert lib.hess_workspace_size(None, L.OP["exact_cols"], C.byref(m), C.byref(d), L.PREC["bf16"], 10, None,
+                                   C.byref(nb)) == 10  # HESS_E_UNSUPPORTED
+
+
 def test_status_strings():
     lib = _lib()
     for code in L.STATUS_NAMES:

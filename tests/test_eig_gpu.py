@@ -121,3 +121,26 @@ def test_bitwise_repeatable_and_noconv(api):
     o2 = api.eig_opts(which="H", source="matrix_free", prec="f64", tol=1e-30, max_iter=1, seed=9)
     lam, Q, info, st = api.hess_topk_eig(model, X, Y, 6, o2, raise_on_noconv=False)
     assert st == "HESS_E_NOCONV" and info["iters"] == 1
+
+
+@pytest.mark.parametrize("source", ["matrix_free", "dense"])
+def test_graph_replays_equal_eager(api, source):
+    # the operator applications replay captured HIP graphs (default) with eager orthogonalisation
+    # and Rayleigh-Ritz work in between; every result must equal the eager run bitwise
+    w = workloads.sigmoid_64(N=600)
+    model = api.MLP.from_workload(w, dtype=torch.float32)
+    X = torch.from_numpy(w.X).to("cuda", torch.float32)
+    Y = torch.from_numpy(w.Y).to("cuda", torch.float32)
+    M = api.hess_exact(model, X, Y, "f32") if source == "dense" else None
+    out = {}
+    for graphs in (1, 0):
+        ctx = api.Context(0)
+        ctx.set_option("graphs", graphs)
+        o = api.eig_opts(which="H", source=source, M=M, prec="f32", tol=1e-6, seed=11, max_iter=40)
+        lam, Q, info, st = api.hess_topk_eig(model, X, Y, 16, o, ctx=ctx, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        out[graphs] = (lam.clone(), Q.clone(), info, st)
+        print("case graphs=%d source=%s: %s %s" % (graphs, source, info, st), flush=True)
+    assert out[1][2]["applies"] > 6  # several replays of each captured pair
+    assert torch.equal(out[1][0], out[0][0]) and torch.equal(out[1][1], out[0][1])
+    assert out[1][2] == out[0][2] and out[1][3] == out[0][3]

@@ -188,6 +188,63 @@ def test_mnist_shaped_full_size_sampled_columns(api):
         assert report("mnist OPG[:, blocks] %s" % prec, Gc, Gref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_exact_cols_match_oracle(api, prec):
+    for T, acts, N, seed in (SMALL[2], SMALL[4]):
+        print("case exact_cols T=%s N=%d prec=%s" % (T, N, prec), flush=True)
+        w = workloads.mlp_gaussian(T, acts, N, seed, dtype="float64" if prec == "f64" else "float32")
+        model, X, Y = to_dev(api, w, w.dtype)
+        om, Xo, Yo = oracle_of(w)
+        P = model.P
+        for c0, nc in ((0, P), (P // 3, 37), (P - 5, 5)):
+            ref = mlp.hessian_cols(om, Xo, Yo, c0, c0 + nc)
+            Hc = api.hess_exact_cols(model, X, Y, c0, nc, prec).double().cpu().numpy()
+            assert report("H cols %d..%d of %s %s" % (c0, c0 + nc, T, prec), Hc, ref) <= TOL[prec]
+
+
+def test_exact_cols_several_blocks(api):
+    # 600 columns: two blocks of basis HVPs (512 + 88); against the oracle and hess_exact
+    w = workloads.sigmoid_64(N=600)
+    om, Xo, Yo = oracle_of(w)
+    model = api.MLP.from_workload(w, dtype=torch.float32)
+    X = torch.from_numpy(w.X).to("cuda", torch.float32)
+    Y = torch.from_numpy(w.Y).to("cuda", torch.float32)
+    print("case exact_cols sigmoid64 N=600 columns 1000..1600", flush=True)
+    Hc = api.hess_exact_cols(model, X, Y, 1000, 600, "f32").double().cpu().numpy()
+    ref = mlp.hessian_cols(om, Xo, Yo, 1000, 1600, block=256)
+    assert report("sigmoid64 N=600 H[:, 1000:1600] via columns", Hc, ref) <= TOL["f32"]
+    H = api.hess_exact(model, X, Y, "f32")[:, 1000:1600].double().cpu().numpy()
+    assert report("columns vs hess_exact", Hc, H) <= 2 * TOL["f32"]
+    with pytest.raises(api.HessError) as e:
+        api.hess_exact_cols(model, X, Y, model.P - 3, 4, "f32")
+    assert e.value.name == "HESS_E_SHAPE"
+
+
+def test_autotune_keeps_results_bitwise(api):
+    # every tile configuration the tuner may pick gives the same bits as the default
+    w = workloads.sigmoid_64(N=600)
+    model = api.MLP.from_workload(w, dtype=torch.float32)
+    X = torch.from_numpy(w.X).to("cuda", torch.float32)
+    Y = torch.from_numpy(w.Y).to("cuda", torch.float32)
+    ref = {}
+    for tune in (0, 1):
+        ctx = api.Context(0)
+        ctx.set_option("autotune", tune)
+        H = api.hess_exact(model, X, Y, "f32", ctx=ctx).clone()
+        G = api.hess_opg(model, X, Y, "f32", ctx=ctx).clone()
+        Gb = api.hess_opg(model, X, Y, "bf16", ctx=ctx).clone()
+        torch.cuda.synchronize()
+        ref[tune] = (H, G, Gb)
+        rep = ctx.autotune_report()
+        print("case autotune=%d report:\n%s" % (tune, rep), flush=True)
+        if tune:
+            assert "krg_f32" in rep and "gram_bf16" in rep and "->" in rep
+        else:
+            assert rep == ""
+    for a, b in zip(ref[0], ref[1]):
+        assert torch.equal(a, b)
+
+
 def test_run_twice_bitwise(api):
     """No atomics in any reduction: two runs give bitwise-identical results."""
     w = workloads.mlp_gaussian([33, 40, 10], ["tanh"], 300, 9, dtype="float32")
