@@ -82,17 +82,25 @@ def cpu_baseline(w, seconds_hint: float):
     X = w.X.astype(np.float64)
     Y = w.Y.astype(np.float64)
     P = mlp.num_params(w.T)
-    bh = 16
+    bh = 48
     t0 = time.perf_counter()
-    mlp.hessian_cols(om, X, Y, 0, bh, block=bh)
+    mlp.hessian_cols(om, X, Y, 0, bh, block=16)
     th = time.perf_counter() - t0
-    bg, cg = 256, 2048
+    bg, cg = 512, 4096
     t0 = time.perf_counter()
     mlp.opg_tile(om, X, Y, list(range(bg)), list(range(cg)))
     tg = time.perf_counter() - t0
     per_h = th / (bh * P)
     per_g = tg / (bg * cg)
     threads = os.environ.get("OMP_NUM_THREADS") or str(len(os.sched_getaffinity(0)))
+    cpu = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": 2.0 / (per_h + per_g),
         "unit": "P^2-entries/s",
@@ -100,7 +108,7 @@ def cpu_baseline(w, seconds_hint: float):
         "kind": "oracle",
         "sample": "FP64 NumPy oracle, same workload: H columns 0..%d (basis HVPs over all N=%d examples, "
                   "%.1f s) and OPG tile %dx%d from J columns (%.1f s); rate = 2/(s per H entry + s per OPG "
-                  "entry)" % (bh, X.shape[0], th, bg, cg, tg),
+                  "entry); host %s" % (bh, X.shape[0], th, bg, cg, tg, cpu),
     }
 
 
@@ -247,6 +255,28 @@ def main():
         "kernels": {k: {"launches": v["launches"], "ms_per_step": v["ms"] / args.steps,
                         "tflops": v["flops"] / v["ms"] / 1e9 if v["ms"] else 0.0} for k, v in prof.items()},
     }
+    # Dense HVP throughput at several block sizes (outside the timed steps): B directions
+    # per call over all N examples, median of 3 calls after one warm-up call.
+    for Bs in (1, 8, 64):
+        Vb = V[:Bs].contiguous()
+        HVb = torch.empty_like(Vb)
+        api.hess_hvp(model, X, Y, Vb, "f32", out=HVb, ctx=ctx)
+        times = []
+        for _ in range(3):
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(ctx.stream)
+            api.hess_hvp(model, X, Y, Vb, "f32", out=HVb, ctx=ctx)
+            a1.record(ctx.stream)
+            torch.cuda.synchronize()
+            times.append(a0.elapsed_time(a1))
+        out["hvps_per_s"]["dense_B%d" % Bs] = Bs / (sorted(times)[1] / 1e3)
+    # sustained rate of the dominant kernel's MFMA instruction in a register-only stream
+    stream_kind = {"f32": "f32_16x16x4", "bf16": "bf16_16x16x32", "f64": "f64_16x16x4"}[roofline["dtype"]]
+    srate = ctx.mfma_stream_rate(stream_kind)
+    out["roofline"]["mfma_stream_tflops"] = round(srate, 2)
+    out["roofline"]["frac_of_stream"] = round(roofline["achieved"] / srate, 4)
+    log("hvps/s %s; MFMA stream %s %.1f TFLOP/s" % (json.dumps({k: round(v, 1) for k, v in out["hvps_per_s"].items()}),
+                                                    stream_kind, srate))
     del H, G, V, HV
     ctx.release_workspace()
     torch.cuda.empty_cache()

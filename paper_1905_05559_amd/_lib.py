@@ -25,6 +25,7 @@ EXPORTS = (
     "hess_num_params", "hess_workspace_size", "hess_exact", "hess_opg", "hess_hvp", "hess_exact_cols",
     "hess_topk_eig", "hess_predvar", "hess_profile_read", "hess_profile_reset", "hess_batched",
     "hess_server_create", "hess_server_submit", "hess_server_wait", "hess_server_stats", "hess_server_destroy",
+    "hess_mfma_stream_rate",
 )
 
 
@@ -86,6 +87,7 @@ def load(path: str = LIB_PATH):
         "hess_hvp": (st, [vp, pm, pd, C.c_int, i64, vp, vp, vp, C.c_size_t]),
         "hess_exact_cols": (st, [vp, pm, pd, C.c_int, i64, i64, vp, vp, C.c_size_t]),
         "hess_autotune_report": (st, [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+        "hess_mfma_stream_rate": (st, [vp, C.c_int, i64, vp, C.POINTER(C.c_double)]),
         "hess_topk_eig": (st, [vp, pm, pd, i64, C.POINTER(HessEigOpts), vp, vp,
                                C.POINTER(HessEigInfo), vp, C.c_size_t]),
         "hess_predvar": (st, [vp, pm, i64, vp, vp, C.c_double, i64, vp, vp, vp, vp, C.c_size_t]),

@@ -56,6 +56,15 @@ class Context:
     def set_option(self, name: str, value: int):
         self._check(self.lib.hess_set_option(self.h, L.OPT[name], int(value)))
 
+    def mfma_stream_rate(self, kind: str, iters: int = 20000) -> float:
+        """Sustained TFLOP/s of one MFMA instruction in a register-only stream (hess_diag.h).
+        kind: "f32_16x16x4", "bf16_16x16x32", "bf16_32x32x16" or "f64_16x16x4"."""
+        k = {"f32_16x16x4": 0, "bf16_16x16x32": 1, "bf16_32x32x16": 2, "f64_16x16x4": 3}[kind]
+        sink = torch.empty(1, dtype=torch.float32, device="cuda:%d" % self.device)
+        out = C.c_double()
+        self._check(self.lib.hess_mfma_stream_rate(self.h, k, int(iters), C.c_void_p(sink.data_ptr()), C.byref(out)))
+        return out.value
+
     def autotune_report(self) -> str:
         """The autotuning decisions of this context (see hess_autotune_report)."""
         need = C.c_size_t()
