@@ -53,6 +53,26 @@ def low_rank_quadratic(lam, Q, x):
     return float(p @ (lam * p))
 
 
+def low_rank_apply(lam, Q, x):
+    """H~ x = Q^T diag(lam) (Q x) without forming the P x P matrix (Sec. 5.5)."""
+    return Q.T @ (lam * (Q @ x))
+
+
+def full_rank_apply(lam, Q, x, lam_tilde=None):
+    """H~~ x = Q^T diag(lam) Q x + lam~ (x - Q^T Q x), lam~ = lam_K by default (Sec. 5.6)."""
+    lt = lam[-1] if lam_tilde is None else lam_tilde
+    p = Q @ x
+    return Q.T @ (lam * p) + lt * (x - Q.T @ p)
+
+
+def full_rank_inverse_apply(lam, Q, x, lam_tilde=None):
+    """H~~^{-1} x.  H~~ has eigenvalues lam_k on the rows of Q and lam~ on their orthogonal
+    complement (App. A.2), so its inverse replaces them by 1/lam_k and 1/lam~."""
+    lt = lam[-1] if lam_tilde is None else lam_tilde
+    p = Q @ x
+    return Q.T @ (p / lam) + (x - Q.T @ p) / lt
+
+
 def full_rank_quadratic(lam, Q, x, lam_tilde=None):
     """x^T [Q^T diag(lam) Q + lam~ (I - Q^T Q)] x with lam~ = lam_K by default (Sec. 5.6)."""
     lt = lam[-1] if lam_tilde is None else lam_tilde

@@ -287,6 +287,30 @@ def test_sampled_helpers_match_full_matrices():
 # Eigenpairs.
 # ---------------------------------------------------------------------------
 
+def test_curvature_operators_against_formed_matrices():
+    # Sec. 5.5-5.6 and App. A.2: implicit forms against the explicit P x P matrices
+    rng = np.random.default_rng(13)
+    P, K = 40, 6
+    Qf, _ = np.linalg.qr(rng.standard_normal((P, K)))
+    Q = Qf.T                                   # K x P, orthonormal rows
+    lam = np.sort(rng.uniform(0.5, 3.0, K))[::-1]
+    lt = 0.2
+    Hl = Q.T @ np.diag(lam) @ Q
+    Hf = Hl + lt * (np.eye(P) - Q.T @ Q)
+    x = rng.standard_normal(P)
+    np.testing.assert_allclose(eig.low_rank_apply(lam, Q, x), Hl @ x, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(eig.full_rank_apply(lam, Q, x, lt), Hf @ x, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(eig.full_rank_inverse_apply(lam, Q, x, lt), np.linalg.solve(Hf, x), rtol=1e-12)
+    # default lam~ = lam_K, and the quadratic forms are x . (operator x)
+    np.testing.assert_allclose(eig.full_rank_apply(lam, Q, x), (Hl + lam[-1] * (np.eye(P) - Q.T @ Q)) @ x,
+                               rtol=1e-13, atol=1e-13)
+    assert abs(eig.low_rank_quadratic(lam, Q, x) - x @ Hl @ x) < 1e-12
+    assert abs(eig.full_rank_quadratic(lam, Q, x, lt) - x @ Hf @ x) < 1e-12
+    # H~~ is full rank: eigenvalues are lam_k and lam~ (P - K times)
+    w = np.linalg.eigvalsh(Hf)
+    np.testing.assert_allclose(np.sort(w), np.sort(np.concatenate([lam, np.full(P - K, lt)])), rtol=1e-12)
+
+
 def test_topk_eigh_known_spectrum_and_sign():
     rng = np.random.default_rng(4)
     P = 30
