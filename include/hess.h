@@ -83,7 +83,7 @@ typedef struct {
 /* Operation codes for hess_workspace_size. */
 typedef enum {
   HESS_OP_EXACT = 0, HESS_OP_OPG = 1, HESS_OP_HVP = 2, HESS_OP_TOPK = 3, HESS_OP_PREDVAR = 4,
-  HESS_OP_BATCHED = 5, HESS_OP_EXACT_COLS = 6
+  HESS_OP_BATCHED = 5, HESS_OP_EXACT_COLS = 6, HESS_OP_CURVATURE = 7
 } hess_op;
 
 /* Create a context on `device`; `stream` is a hipStream_t (NULL = the null stream). */
@@ -143,7 +143,7 @@ hess_status hess_profile_reset(hess_ctx* ctx);
 hess_status hess_num_params(const hess_mlp* m, int64_t* P);
 
 /* Bytes of workspace `op` needs.  `arg` is B for HESS_OP_HVP, ncols for
- * HESS_OP_EXACT_COLS, K for HESS_OP_TOPK,
+ * HESS_OP_EXACT_COLS, nx for HESS_OP_CURVATURE (opts: const int64_t* K), K for HESS_OP_TOPK,
  * the number of queries for HESS_OP_PREDVAR, the number of networks M for
  * HESS_OP_BATCHED (then `m` and `d` point to arrays of M entries), unused otherwise.
  * For HESS_OP_TOPK `opts` is a const hess_eig_opts*, else NULL.  `data` may be NULL
@@ -174,6 +174,40 @@ hess_status hess_opg(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int p
  * for HESS_P_F64 else FP32.  prec: HESS_P_F64 or HESS_P_F32. */
 hess_status hess_hvp(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int prec,
                      int64_t B, const void* V, void* HV, void* ws, size_t ws_bytes);
+
+/* Curvature operators from K eigenpairs (lambda descending, Q K x P row-major, FP64,
+ * e.g. from hess_topk_eig) applied to nx vectors X (nx x P row-major, FP64), never
+ * forming a P x P matrix.  Low rank (paper, Sec. 5.5): H~ = Q^T diag(lambda) Q.  Full
+ * rank (Sec. 5.6, App. A.2): H~~ = H~ + lt (I - Q^T Q), lt = lam_tilde (the paper's
+ * choice is lambda_K); Q's rows must be orthonormal.  Modes:
+ *   HESS_CURV_LOW_QUAD    out[i] = x_i^T H~ x_i          (out: nx)
+ *   HESS_CURV_FULL_QUAD   out[i] = x_i^T H~~ x_i         (out: nx)
+ *   HESS_CURV_LOW_APPLY   out[i,:] = H~ x_i              (out: nx x P)
+ *   HESS_CURV_FULL_APPLY  out[i,:] = H~~ x_i             (out: nx x P)
+ *   HESS_CURV_FULL_INV    out[i,:] = H~~^{-1} x_i        (out: nx x P)
+ * All device pointers; ws: hess_workspace_size(HESS_OP_CURVATURE, arg = nx, opts = const
+ * int64_t* K).  Errors: HESS_E_SHAPE (K < 1, P < K, nx < 1), HESS_E_NONFINITE (lambda or
+ * lam_tilde), HESS_E_NOTPD (inverse with some lambda_k <= 0 or lam_tilde <= 0). */
+typedef enum {
+  HESS_CURV_LOW_QUAD = 0, HESS_CURV_FULL_QUAD = 1, HESS_CURV_LOW_APPLY = 2, HESS_CURV_FULL_APPLY = 3,
+  HESS_CURV_FULL_INV = 4
+} hess_curv_mode;
+hess_status hess_curvature(hess_ctx* ctx, int mode, int64_t K, int64_t P, const double* lambda, const double* Q,
+                           double lam_tilde, int64_t nx, const double* X, double* out, void* ws, size_t ws_bytes);
+
+/* Prepared HVP operator: the per-example passes of hess_hvp (forward and backward over
+ * all N examples, paper Sec. 2-3) run once, then hess_hvp_apply forms H V for any number
+ * of blocks of up to max_B directions without repeating them (paper, Sec. 5.1 and
+ * Appendix A.1).  ws (device, caller-owned, size hess_workspace_size(HESS_OP_HVP) with
+ * arg = max_B) holds the prepared state and must stay allocated and untouched until
+ * hess_hvp_release; m's weights and d's X, Y are not read after hess_hvp_prepare.
+ * V, HV: device, B x P row-major, FP64 for HESS_P_F64 else FP32, B <= max_B.
+ * Errors: as hess_hvp; HESS_E_SHAPE for B outside 1..max_B. */
+typedef struct hess_hvp_op hess_hvp_op;
+hess_status hess_hvp_prepare(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int prec, int64_t max_B,
+                             void* ws, size_t ws_bytes, hess_hvp_op** op);
+hess_status hess_hvp_apply(hess_ctx* ctx, hess_hvp_op* op, int64_t B, const void* V, void* HV);
+hess_status hess_hvp_release(hess_hvp_op* op);
 
 /* Columns col0 .. col0 + ncols - 1 of the exact H (paper, Sec. 5.1: the Hessian-vector
  * product with the j-th unit vector is column j of H), computed as HVPs with basis
@@ -250,23 +284,25 @@ hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* models, const
  * returns for it; host arrays of the model are copied at submission.
  * --------------------------------------------------------------------------- */
 typedef struct hess_server hess_server;
-typedef enum { HESS_REQ_FULL = 0, HESS_REQ_TOPK = 1, HESS_REQ_PREDVAR = 2 } hess_req_kind;
+typedef enum { HESS_REQ_FULL = 0, HESS_REQ_TOPK = 1, HESS_REQ_PREDVAR = 2, HESS_REQ_CURVATURE = 3 } hess_req_kind;
 typedef struct {
   int32_t kind;          /* hess_req_kind */
   hess_mlp model;
   hess_data data;        /* FULL, TOPK: the network's data set */
   void* H;               /* FULL: P x P FP32 output, or NULL */
   void* G;               /* FULL: P x P FP32 OPG output, or NULL */
-  int64_t K;             /* TOPK: pairs wanted; PREDVAR: pairs held in lambda, Q */
-  double* lambda;        /* TOPK: output (K); PREDVAR: input (K), device FP64 */
-  double* Q;             /* TOPK: output (K x P); PREDVAR: input (K x P), device FP64 */
+  int64_t K;             /* TOPK: pairs wanted; PREDVAR, CURVATURE: pairs held in lambda, Q */
+  double* lambda;        /* TOPK: output (K); PREDVAR, CURVATURE: input (K), device FP64 */
+  double* Q;             /* TOPK: output (K x P); PREDVAR, CURVATURE: input (K x P), device FP64 */
   double tol;            /* TOPK: relative residual tolerance */
   uint64_t seed;         /* TOPK: start-block seed */
   double delta;          /* PREDVAR: damping */
-  int64_t nq;            /* PREDVAR: number of query inputs */
-  const void* Xq;        /* PREDVAR: nq x T_1 (model dtype), device */
+  int64_t nq;            /* PREDVAR: number of query inputs; CURVATURE: number of vectors */
+  const void* Xq;        /* PREDVAR: nq x T_1 (model dtype); CURVATURE: nq x P FP64; device */
   const int32_t* cls;    /* PREDVAR: classes (device) or NULL for arg-max */
-  double* s;             /* PREDVAR: nq outputs, device FP64 */
+  double* s;             /* PREDVAR: nq outputs; CURVATURE: nq or nq x P outputs; device FP64 */
+  int32_t curv_mode;     /* CURVATURE: hess_curv_mode (the model gives P) */
+  double lam_tilde;      /* CURVATURE: full-rank level */
 } hess_request;
 
 hess_status hess_server_create(hess_server** srv, int device, int n_slots, void* pool, size_t pool_bytes,

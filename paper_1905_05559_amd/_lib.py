@@ -16,7 +16,7 @@ STATUS_NAMES = {
 ACT = {"tanh": 0, "sigmoid": 1, "relu": 2}
 DTYPE = {"float64": 0, "float32": 1}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
-OP = {"exact": 0, "opg": 1, "hvp": 2, "topk": 3, "predvar": 4, "batched": 5, "exact_cols": 6}
+OP = {"exact": 0, "opg": 1, "hvp": 2, "topk": 3, "predvar": 4, "batched": 5, "exact_cols": 6, "curvature": 7}
 OPT = {"check_inputs": 0, "hbm_budget": 1, "fault_after": 2, "profile": 3, "graphs": 4, "autotune": 5}
 
 # Every symbol include/hess.h declares.
@@ -25,7 +25,7 @@ EXPORTS = (
     "hess_num_params", "hess_workspace_size", "hess_exact", "hess_opg", "hess_hvp", "hess_exact_cols",
     "hess_topk_eig", "hess_predvar", "hess_profile_read", "hess_profile_reset", "hess_batched",
     "hess_server_create", "hess_server_submit", "hess_server_wait", "hess_server_stats", "hess_server_destroy",
-    "hess_mfma_stream_rate",
+    "hess_mfma_stream_rate", "hess_hvp_prepare", "hess_hvp_apply", "hess_hvp_release", "hess_curvature",
 )
 
 
@@ -52,7 +52,8 @@ class HessEigInfo(C.Structure):
 class HessRequest(C.Structure):
     _fields_ = [("kind", C.c_int32), ("model", HessMlp), ("data", HessData), ("H", C.c_void_p), ("G", C.c_void_p),
                 ("K", C.c_int64), ("lam", C.c_void_p), ("Q", C.c_void_p), ("tol", C.c_double), ("seed", C.c_uint64),
-                ("delta", C.c_double), ("nq", C.c_int64), ("Xq", C.c_void_p), ("cls", C.c_void_p), ("s", C.c_void_p)]
+                ("delta", C.c_double), ("nq", C.c_int64), ("Xq", C.c_void_p), ("cls", C.c_void_p), ("s", C.c_void_p),
+                ("curv_mode", C.c_int32), ("lam_tilde", C.c_double)]
 
 
 class HessProfEntry(C.Structure):
@@ -88,6 +89,10 @@ def load(path: str = LIB_PATH):
         "hess_exact_cols": (st, [vp, pm, pd, C.c_int, i64, i64, vp, vp, C.c_size_t]),
         "hess_autotune_report": (st, [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
         "hess_mfma_stream_rate": (st, [vp, C.c_int, i64, vp, C.POINTER(C.c_double)]),
+        "hess_hvp_prepare": (st, [vp, pm, pd, C.c_int, i64, vp, C.c_size_t, C.POINTER(vp)]),
+        "hess_hvp_apply": (st, [vp, vp, i64, vp, vp]),
+        "hess_hvp_release": (st, [vp]),
+        "hess_curvature": (st, [vp, C.c_int, i64, i64, vp, vp, C.c_double, i64, vp, vp, vp, C.c_size_t]),
         "hess_topk_eig": (st, [vp, pm, pd, i64, C.POINTER(HessEigOpts), vp, vp,
                                C.POINTER(HessEigInfo), vp, C.c_size_t]),
         "hess_predvar": (st, [vp, pm, i64, vp, vp, C.c_double, i64, vp, vp, vp, vp, C.c_size_t]),

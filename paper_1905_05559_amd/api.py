@@ -218,6 +218,70 @@ def hess_hvp(model: MLP, X: torch.Tensor, Y: torch.Tensor, V: torch.Tensor, prec
     return out
 
 
+CURV_MODES = {"low_quad": 0, "full_quad": 1, "low_apply": 2, "full_apply": 3, "full_inverse": 4}
+
+
+def curvature(mode: str, lam: torch.Tensor, Q: torch.Tensor, X: torch.Tensor, lam_tilde: Optional[float] = None,
+              out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """Low/full-rank curvature operator queries from K eigenpairs (hess_curvature in include/hess.h).
+    lam (K,), Q (K x P), X (nx x P), all FP64 on the device; lam_tilde defaults to lam[-1]."""
+    ctx = ctx or default_context()
+    K, P = int(Q.shape[0]), int(Q.shape[1])
+    X = X.contiguous()
+    nx = int(X.shape[0])
+    lt = float(lam[-1].item()) if lam_tilde is None else float(lam_tilde)
+    m = CURV_MODES[mode]
+    if out is None:
+        shape = (nx,) if m in (0, 1) else (nx, P)
+        out = torch.empty(shape, dtype=torch.float64, device=X.device)
+    kk = C.c_int64(K)
+    nb = C.c_size_t()
+    ctx._check(ctx.lib.hess_workspace_size(ctx.h, L.OP["curvature"], None, None, L.PREC["f64"], nx, C.byref(kk),
+                                           C.byref(nb)))
+    ws = ctx.workspace(nb.value)
+    ctx._check(ctx.lib.hess_curvature(ctx.h, m, K, P, lam.data_ptr(), Q.contiguous().data_ptr(), lt, nx,
+                                      X.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel()))
+    return out
+
+
+class HvpOperator:
+    """Prepared HVP operator of (model, X, Y): the per-example passes run once, then
+    apply(V) forms H V for blocks of up to max_B directions (hess_hvp_prepare /
+    hess_hvp_apply in include/hess.h).  Holds its own workspace until close()."""
+
+    def __init__(self, model: MLP, X: torch.Tensor, Y: torch.Tensor, prec: str = "f32", max_B: int = 512,
+                 ctx: Optional[Context] = None):
+        self.ctx = ctx or default_context()
+        self.prec, self.max_B, self.P = prec, int(max_B), model.P
+        nb = workspace_size("hvp", model, X, Y, prec, arg=self.max_B, ctx=self.ctx)
+        self.ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=X.device)
+        m, d = model.struct(), _data(X, Y)
+        h = C.c_void_p()
+        self.ctx._check(self.ctx.lib.hess_hvp_prepare(self.ctx.h, C.byref(m), C.byref(d), L.PREC[prec], self.max_B,
+                                                      self.ws.data_ptr(), self.ws.numel(), C.byref(h)))
+        self.h = h
+
+    def apply(self, V: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        V = V.contiguous()
+        if out is None:
+            out = torch.empty_like(V)
+        self.ctx._check(self.ctx.lib.hess_hvp_apply(self.ctx.h, self.h, int(V.shape[0]), V.data_ptr(),
+                                                    out.data_ptr()))
+        return out
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.hess_hvp_release(self.h)
+            self.h = None
+            self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def hess_exact_cols(model: MLP, X: torch.Tensor, Y: torch.Tensor, col0: int, ncols: int, prec: str = "f32",
                     out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
     """Columns col0 .. col0+ncols-1 of H (P x ncols), see hess_exact_cols in include/hess.h."""
@@ -332,7 +396,7 @@ class Server:
     request's workspace; n_slots worker slots run requests concurrently on their own
     streams; coalesce merges queued damped queries against the same target."""
 
-    REQ = {"full": 0, "topk": 1, "predvar": 2}
+    REQ = {"full": 0, "topk": 1, "predvar": 2, "curvature": 3}
 
     def __init__(self, pool_bytes: int, n_slots: int = 4, coalesce: bool = True, device: int = 0):
         self.lib = L.load()
@@ -346,7 +410,10 @@ class Server:
         self._keep = {}
 
     def submit(self, kind: str, model: MLP, X=None, Y=None, H=None, G=None, K=0, lam=None, Q=None, tol=1e-5,
-               seed=0, delta=0.0, Xq=None, cls=None, s=None) -> int:
+               seed=0, delta=0.0, Xq=None, cls=None, s=None, curv_mode=None, lam_tilde=0.0) -> int:
+        """Queue one request.  kind "curvature": lam, Q (K pairs), Xq = nq x P FP64 vectors,
+        s = outputs (nq for the quadratic forms, nq x P for the products), curv_mode one of
+        CURV_MODES, lam_tilde the full-rank level."""
         r = L.HessRequest()
         r.kind = self.REQ[kind]
         m = model.struct()
@@ -369,6 +436,11 @@ class Server:
             r.Xq = Xq.data_ptr()
         r.cls = cls.data_ptr() if cls is not None else None
         r.s = s.data_ptr() if s is not None else None
+        if kind == "curvature":
+            if Xq is None or Xq.dtype != torch.float64 or not Xq.is_contiguous():
+                raise ValueError("curvature requests take contiguous FP64 vectors Xq (nq x P)")
+            r.curv_mode = CURV_MODES[curv_mode] if isinstance(curv_mode, str) else int(curv_mode)
+            r.lam_tilde = float(lam_tilde)
         keep += [H, G, lam, Q, Xq, cls, s, X, Y]
         rid = C.c_uint64()
         st = self.lib.hess_server_submit(self.h, C.byref(r), C.byref(rid))

@@ -93,6 +93,7 @@ void jv_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T
 
 // Workspace queries of the other translation units.
 hess_status exact_cols_workspace(hess_ctx* ctx, const Model& m, int64_t N, int prec, int64_t ncols, size_t* bytes);
+hess_status curvature_workspace(hess_ctx* ctx, int64_t K, int64_t nx, size_t* bytes);
 hess_status hvp_workspace(hess_ctx* ctx, const Model& m, int64_t N, int prec, int64_t B, size_t* bytes);
 hess_status topk_workspace(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int64_t K,
                            const hess_eig_opts* o, size_t* bytes);

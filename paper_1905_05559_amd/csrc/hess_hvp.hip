@@ -514,3 +514,76 @@ extern "C" hess_status hess_exact_cols(hess_ctx* ctx, const hess_mlp* mlp, const
   }
   return finish(ex, "hess_exact_cols");
 }
+
+struct hess_hvp_op {
+  Model m;
+  int64_t N = 0, maxB = 0;
+  int prec = HESS_P_F32;
+  Prep p;
+  HvpBufs<float> hf;
+  HvpBufs<double> hd;
+};
+
+extern "C" hess_status hess_hvp_prepare(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int prec,
+                                        int64_t max_B, void* ws, size_t ws_bytes, hess_hvp_op** op) {
+  if (!op) return fail(ctx, HESS_E_ARG, "op is NULL");
+  *op = nullptr;
+  Exec ex;
+  hess_status s = begin(ctx, ex);
+  if (s != HESS_OK) return s;
+  Model m;
+  if ((s = validate_mlp(ctx, mlp, m, true)) != HESS_OK) return s;
+  if ((s = validate_data(ctx, d, true)) != HESS_OK) return s;
+  if (prec != HESS_P_F64 && prec != HESS_P_F32) return fail(ctx, HESS_E_UNSUPPORTED, "HVP: F64 or F32 only");
+  if (max_B < 1 || max_B > 65535) return fail(ctx, HESS_E_SHAPE, "max_B out of range (1..65535)");
+  const size_t need = ws_hvp(m, d->N, prec, max_B);
+  if ((s = check_ws(ctx, need, ws, ws_bytes, 0)) != HESS_OK) return s;
+  hess_hvp_op* o = new hess_hvp_op();
+  o->m = m;
+  o->N = d->N;
+  o->maxB = max_B;
+  o->prec = prec;
+  Arena ar(ws);
+  if (prec == HESS_P_F64) {
+    plan_hvp<double>(ar, o->m, d->N, max_B, o->p, o->hd);
+  } else {
+    plan_hvp<float>(ar, o->m, d->N, max_B, o->p, o->hf);
+  }
+  if ((s = check_inputs(ex, o->m, d, o->p)) != HESS_OK) {
+    delete o;
+    return s;
+  }
+  run_prep(ex, o->m, d, o->p, false);
+  if (prec == HESS_P_F64)
+    hvp_setup<double>(ex, o->m, d->N, o->p, o->hd);
+  else
+    hvp_setup<float>(ex, o->m, d->N, o->p, o->hf);
+  s = finish(ex, "hess_hvp_prepare");
+  if (s != HESS_OK) {
+    delete o;
+    return s;
+  }
+  *op = o;
+  return HESS_OK;
+}
+
+extern "C" hess_status hess_hvp_apply(hess_ctx* ctx, hess_hvp_op* op, int64_t B, const void* V, void* HV) {
+  Exec ex;
+  hess_status s = begin(ctx, ex);
+  if (s != HESS_OK) return s;
+  if (!op) return fail(ctx, HESS_E_ARG, "op is NULL");
+  if (B < 1 || B > op->maxB) return fail(ctx, HESS_E_SHAPE, "B outside 1..max_B");
+  if (!V || !HV) return fail(ctx, HESS_E_ARG, "V or HV is NULL");
+  if (op->prec == HESS_P_F64)
+    hvp_apply<double>(ex, op->m, op->N, B, op->p, op->hd, static_cast<const double*>(V), op->m.P,
+                      static_cast<double*>(HV));
+  else
+    hvp_apply<float>(ex, op->m, op->N, B, op->p, op->hf, static_cast<const float*>(V), op->m.P,
+                     static_cast<float*>(HV));
+  return finish(ex, "hess_hvp_apply");
+}
+
+extern "C" hess_status hess_hvp_release(hess_hvp_op* op) {
+  delete op;
+  return HESS_OK;
+}

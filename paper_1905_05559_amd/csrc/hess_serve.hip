@@ -140,6 +140,10 @@ hess_status footprint(hess_ctx* ctx, const Req* q, int64_t nq_total, size_t* byt
       o.seed = r.seed;
       return hess_workspace_size(ctx, HESS_OP_TOPK, &q->model.view, &r.data, HESS_P_F32, r.K, &o, bytes);
     }
+    case HESS_REQ_CURVATURE: {
+      const int64_t K = r.K;
+      return hess_workspace_size(ctx, HESS_OP_CURVATURE, nullptr, nullptr, 0, r.nq, &K, bytes);
+    }
     case HESS_REQ_PREDVAR:
       if ((st = hess_workspace_size(ctx, HESS_OP_PREDVAR, &q->model.view, nullptr, 0, nq_total, nullptr, &a)))
         return st;
@@ -287,6 +291,15 @@ void worker(hess_server* s, int slot) {
     switch (grp[0]->r.kind) {
       case HESS_REQ_FULL: st = run_full(ctx, grp[0], ws, bytes); break;
       case HESS_REQ_TOPK: st = run_topk(ctx, grp[0], ws, bytes); break;
+      case HESS_REQ_CURVATURE: {
+        const hess_request& r = grp[0]->r;
+        hs::Model mm;
+        st = validate_mlp(nullptr, &grp[0]->model.view, mm, false);
+        if (st == HESS_OK)
+          st = hess_curvature(ctx, r.curv_mode, r.K, mm.P, r.lambda, r.Q, r.lam_tilde, r.nq,
+                              static_cast<const double*>(r.Xq), r.s, ws, bytes);
+        break;
+      }
       default: st = run_predvar_group(ctx, stream, grp, ws, bytes); break;
     }
     const auto t_end = clock_t_::now();
@@ -334,12 +347,18 @@ hess_status hess_server_create(hess_server** out, int device, int n_slots, void*
 
 hess_status hess_server_submit(hess_server* s, const hess_request* r, uint64_t* id) {
   if (!s || !r || !id) return HESS_E_ARG;
-  if (r->kind < HESS_REQ_FULL || r->kind > HESS_REQ_PREDVAR) return HESS_E_ARG;
+  if (r->kind < HESS_REQ_FULL || r->kind > HESS_REQ_CURVATURE) return HESS_E_ARG;
   Model m;
   hess_status st = validate_mlp(nullptr, &r->model, m, true);
   if (st != HESS_OK) return st;
   if (r->kind == HESS_REQ_PREDVAR && (r->nq < 1 || !r->Xq || !r->s || !r->lambda || !r->Q)) return HESS_E_ARG;
-  if (r->kind != HESS_REQ_PREDVAR && (st = validate_data(nullptr, &r->data, true)) != HESS_OK) return st;
+  if (r->kind == HESS_REQ_CURVATURE &&
+      (r->nq < 1 || r->K < 1 || r->K > m.P || !r->Xq || !r->s || !r->lambda || !r->Q || r->curv_mode < 0 ||
+       r->curv_mode > HESS_CURV_FULL_INV))
+    return HESS_E_ARG;
+  if (r->kind != HESS_REQ_PREDVAR && r->kind != HESS_REQ_CURVATURE &&
+      (st = validate_data(nullptr, &r->data, true)) != HESS_OK)
+    return st;
   Req* q = new Req();
   q->r = *r;
   q->model.from(r->model);

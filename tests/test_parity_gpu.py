@@ -278,6 +278,30 @@ def test_small_hvp(api, T, acts, N, seed, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_prepared_hvp_operator(api, prec):
+    # one preparation, several blocks of different sizes; against the oracle and hess_hvp
+    T, acts, N, seed = SMALL[4]
+    w = workloads.mlp_gaussian(T, acts, N, seed, dtype="float64" if prec == "f64" else "float32")
+    model, X, Y = to_dev(api, w, w.dtype)
+    om, Xo, Yo = oracle_of(w)
+    op = api.HvpOperator(model, X, Y, prec, max_B=64)
+    rng = np.random.default_rng(9)
+    for B in (1, 7, 64):
+        print("case prepared HVP T=%s B=%d prec=%s" % (T, B, prec), flush=True)
+        Vn = rng.standard_normal((B, model.P))
+        V = torch.from_numpy(Vn).to("cuda", X.dtype)
+        HV = op.apply(V).double().cpu().numpy()
+        ref = mlp.hvp(om, Xo, Yo, Vn.astype(np.float32).astype(np.float64) if prec == "f32" else Vn)
+        assert report("prepared HVP B=%d %s" % (B, prec), HV, ref) <= TOL[prec]
+        HV2 = api.hess_hvp(model, X, Y, V, prec).double().cpu().numpy()
+        assert report("prepared vs per-call HVP B=%d %s" % (B, prec), HV, HV2) <= TOL[prec]
+    with pytest.raises(api.HessError) as e:
+        op.apply(torch.zeros((65, model.P), dtype=X.dtype, device="cuda"))
+    assert e.value.name == "HESS_E_SHAPE"
+    op.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_sigmoid64_hvp(api, sig64, prec):
     w, om, Xo, Yo, _ = sig64
     td = torch.float64 if prec == "f64" else torch.float32

@@ -74,3 +74,42 @@ def test_predvar_f32_model_and_errors(api):
         api.hess_predvar(model, torch.from_numpy(lam).cuda(), torch.from_numpy(np.ascontiguousarray(Q)).cuda(),
                          delta, torch.from_numpy(Xq).cuda(), torch.full((16,), 99, dtype=torch.int32).cuda())
     assert e.value.name == "HESS_E_ARG"
+
+
+def test_curvature_operators_match_oracle(api):
+    # Sec. 5.5-5.6, App. A.2: every mode against the oracle's implicit forms (FP64, 1e-10)
+    from oracle import eig
+    rng = np.random.default_rng(21)
+    P, K, nx = 300, 12, 37
+    Qf, _ = np.linalg.qr(rng.standard_normal((P, K)))
+    Qn = np.ascontiguousarray(Qf.T)
+    lamn = np.sort(rng.uniform(0.2, 5.0, K))[::-1].copy()
+    Xn = rng.standard_normal((nx, P))
+    lam, Q, X = (torch.from_numpy(a).cuda() for a in (lamn, Qn, Xn))
+    for lt in (None, 0.05):
+        ltn = lamn[-1] if lt is None else lt
+        refs = {
+            "low_quad": np.array([eig.low_rank_quadratic(lamn, Qn, x) for x in Xn]),
+            "full_quad": np.array([eig.full_rank_quadratic(lamn, Qn, x, ltn) for x in Xn]),
+            "low_apply": np.stack([eig.low_rank_apply(lamn, Qn, x) for x in Xn]),
+            "full_apply": np.stack([eig.full_rank_apply(lamn, Qn, x, ltn) for x in Xn]),
+            "full_inverse": np.stack([eig.full_rank_inverse_apply(lamn, Qn, x, ltn) for x in Xn]),
+        }
+        for mode, ref in refs.items():
+            print("case curvature %s lam_tilde=%s" % (mode, lt), flush=True)
+            got = api.curvature(mode, lam, Q, X, lam_tilde=lt).cpu().numpy()
+            e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            print("  relF %.3e" % e, flush=True)
+            assert e <= 1e-10
+    # the full-rank inverse undoes the full-rank apply
+    Y = api.curvature("full_apply", lam, Q, X)
+    Z = api.curvature("full_inverse", lam, Q, Y)
+    assert float((Z - X).norm() / X.norm()) <= 1e-10
+    with pytest.raises(api.HessError) as e:
+        api.curvature("full_inverse", lam, Q, X, lam_tilde=0.0)
+    assert e.value.name == "HESS_E_NOTPD"
+    bad = lam.clone()
+    bad[-1] = -1.0
+    with pytest.raises(api.HessError) as e:
+        api.curvature("full_inverse", bad, Q, X, lam_tilde=0.1)
+    assert e.value.name == "HESS_E_NOTPD"

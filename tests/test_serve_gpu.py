@@ -47,6 +47,13 @@ def test_mix_equals_alone(api):
         oo = api.eig_opts(which="H", source="matrix_free", prec="f32", tol=1e-5, seed=7)
         l2, q2, _, _ = api.hess_topk_eig(m, x, y, 4, oo, raise_on_noconv=False)
         topk_alone.append((l2.clone(), q2.clone()))
+    # curvature-operator queries against the resident pairs (one per mode, two levels)
+    lam_pd = lam.abs() + 1e-2
+    curv = []
+    for k, mode in enumerate(sorted(api.CURV_MODES)):
+        V = torch.from_numpy(rng.standard_normal((int(rng.integers(1, 9)), model.P))).cuda()
+        lt = 0.03 * (k + 1)
+        curv.append((mode, V, lt, api.curvature(mode, lam_pd, Q, V, lam_tilde=lt).clone()))
     torch.cuda.synchronize()
 
     srv = api.Server(pool_bytes=2 << 30, n_slots=4, coalesce=True)
@@ -55,6 +62,12 @@ def test_mix_equals_alone(api):
         s = torch.empty(Xq.shape[0], dtype=torch.float64, device="cuda")
         outs.append(("predvar", i, s))
         ids.append(srv.submit("predvar", model, K=12, lam=lam, Q=Q, delta=delta, Xq=Xq, cls=cls, s=s))
+        if i % 12 == 5 and i // 12 < len(curv):
+            j = i // 12
+            mode, V, lt, ref = curv[j]
+            o = torch.empty_like(ref)
+            outs.append(("curvature", j, o))
+            ids.append(srv.submit("curvature", model, K=12, lam=lam_pd, Q=Q, Xq=V, s=o, curv_mode=mode, lam_tilde=lt))
         if i in (10, 40):
             for j, (m, x, y) in enumerate(odev):
                 H = torch.empty((m.P, m.P), dtype=torch.float32, device="cuda")
@@ -72,6 +85,8 @@ def test_mix_equals_alone(api):
         lats.append(lat)
         if kind == "predvar":
             assert torch.equal(out, alone[j]), j
+        elif kind == "curvature":
+            assert torch.equal(out, curv[j][3]), curv[j][0]
         elif kind == "full":
             assert torch.equal(out[0], full_alone[j][0]) and torch.equal(out[1], full_alone[j][1])
         else:
@@ -79,6 +94,7 @@ def test_mix_equals_alone(api):
     stats = srv.stats()
     print("served %d requests, stats %s, p50 %.2f ms" % (len(ids), stats, float(np.median(lats))), flush=True)
     assert stats["completed"] == len(ids) and stats["failed"] == 0
+    assert sum(1 for o in outs if o[0] == "curvature") == len(curv)
     srv.close()
 
 
@@ -90,4 +106,15 @@ def test_budget_rejection(api):
     with pytest.raises(api.HessError) as e:
         srv.submit("full", model, X=X, Y=Y, H=H)
     assert e.value.name == "HESS_E_BUDGET"
+    # curvature requests are checked at submission (mode, K and buffers)
+    lam = torch.ones(4, dtype=torch.float64, device="cuda")
+    Q = torch.zeros((4, model.P), dtype=torch.float64, device="cuda")
+    V = torch.zeros((2, model.P), dtype=torch.float64, device="cuda")
+    o = torch.empty(2, dtype=torch.float64, device="cuda")
+    for kw in ({"curv_mode": 7}, {"curv_mode": 0, "K": model.P + 1}):
+        args = dict(K=4, lam=lam, Q=Q, Xq=V, s=o, lam_tilde=0.5)
+        args.update(kw)
+        with pytest.raises(api.HessError) as e:
+            srv.submit("curvature", model, **args)
+        assert e.value.name == "HESS_E_ARG"
     srv.close()
