@@ -83,7 +83,7 @@ typedef struct {
 /* Operation codes for hess_workspace_size. */
 typedef enum {
   HESS_OP_EXACT = 0, HESS_OP_OPG = 1, HESS_OP_HVP = 2, HESS_OP_TOPK = 3, HESS_OP_PREDVAR = 4,
-  HESS_OP_BATCHED = 5, HESS_OP_EXACT_COLS = 6, HESS_OP_CURVATURE = 7
+  HESS_OP_BATCHED = 5, HESS_OP_EXACT_COLS = 6, HESS_OP_CURVATURE = 7, HESS_OP_SYEV = 8
 } hess_op;
 
 /* Create a context on `device`; `stream` is a hipStream_t (NULL = the null stream). */
@@ -143,7 +143,8 @@ hess_status hess_profile_reset(hess_ctx* ctx);
 hess_status hess_num_params(const hess_mlp* m, int64_t* P);
 
 /* Bytes of workspace `op` needs.  `arg` is B for HESS_OP_HVP, ncols for
- * HESS_OP_EXACT_COLS, nx for HESS_OP_CURVATURE (opts: const int64_t* K), K for HESS_OP_TOPK,
+ * HESS_OP_EXACT_COLS, nx for HESS_OP_CURVATURE (opts: const int64_t* K), n for HESS_OP_SYEV,
+ * K for HESS_OP_TOPK,
  * the number of queries for HESS_OP_PREDVAR, the number of networks M for
  * HESS_OP_BATCHED (then `m` and `d` point to arrays of M entries), unused otherwise.
  * For HESS_OP_TOPK `opts` is a const hess_eig_opts*, else NULL.  `data` may be NULL
@@ -195,6 +196,17 @@ typedef enum {
 hess_status hess_curvature(hess_ctx* ctx, int mode, int64_t K, int64_t P, const double* lambda, const double* Q,
                            double lam_tilde, int64_t nx, const double* X, double* out, void* ws, size_t ws_bytes);
 
+/* Eigen-decomposition of a dense symmetric n x n FP64 matrix on the device, the
+ * projected problem of the Lanczos eigensolver (paper, Sec. 5.3), 1 <= n <= 512.
+ * A: device, row-major with row stride lda >= n, used as (A + A^T) / 2, not modified.
+ * w: device, n eigenvalues, descending.  U: device, n x n row-major, row j = unit
+ * eigenvector of w[j], largest-magnitude component positive.  Householder
+ * tridiagonalisation, then implicit-shift QL; synchronises the call's stream.
+ * ws: hess_workspace_size(HESS_OP_SYEV, arg = n).  Errors: HESS_E_SHAPE (n, lda),
+ * HESS_E_NOCONV (more than 60 QL iterations for one eigenvalue, e.g. non-finite A). */
+hess_status hess_syev(hess_ctx* ctx, int64_t n, const double* A, int64_t lda, double* w, double* U, void* ws,
+                      size_t ws_bytes);
+
 /* Prepared HVP operator: the per-example passes of hess_hvp (forward and backward over
  * all N examples, paper Sec. 2-3) run once, then hess_hvp_apply forms H V for any number
  * of blocks of up to max_B directions without repeating them (paper, Sec. 5.1 and
@@ -228,18 +240,25 @@ typedef struct {
   int32_t max_iter;     /* cap on subspace iterations (default 200 if <= 0) */
   double tol;           /* stop when max_k ||M q_k - theta_k q_k|| <= tol * |theta_1| */
   uint64_t seed;        /* seed of the counter-based start block */
+  int32_t method;       /* 0 = filtered subspace iteration; 1 = thick-restart block Lanczos */
+  int32_t block;        /* method 1: Lanczos block size (default 32 if <= 0, at most 128) */
 } hess_eig_opts;
 
 typedef struct {
-  int32_t iters;             /* subspace iterations run */
-  int32_t applies;           /* operator applications (block products) */
+  int32_t iters;             /* subspace iterations run (method 1: restarts) */
+  int32_t applies;           /* operator applications (block products; method 1: blocks of `block`) */
   double max_rel_residual;   /* max_k ||M q_k - theta_k q_k|| / |theta_1| at exit */
   double shift_used;         /* spectral shift used for the algebraically-largest search */
 } hess_eig_info;
 
 /* K algebraically largest eigenpairs of H or the OPG (paper, Sec. 4.1, 5.3, 5.4:
- * which='LA', sorted descending), by randomized subspace iteration with FP64
- * Cholesky-QR re-orthogonalisation and FP64 Rayleigh-Ritz.
+ * which='LA', sorted descending).  method 0: randomized subspace iteration with a
+ * Chebyshev filter, FP64 Cholesky-QR re-orthogonalisation and FP64 Rayleigh-Ritz
+ * (K + oversample <= 128).  method 1: block Lanczos (the paper's solver, Sec. 5.3)
+ * with full FP64 re-orthogonalisation, thick restarts and locking of converged
+ * pairs; window min(512, 3K + 3b, P - b) basis vectors (must be >= K + 2b), a final
+ * Rayleigh-Ritz over the K locked vectors gives the reported pairs and residuals;
+ * max_iter caps the restarts.
  * lambda: device, K doubles, descending.  Q: device, K x P row-major doubles
  * (row k = eigenvector k, orthonormal, largest-|.| component positive).
  * Returns HESS_E_NOCONV (with the best iterate written) at max_iter. */

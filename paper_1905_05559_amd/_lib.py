@@ -16,7 +16,7 @@ STATUS_NAMES = {
 ACT = {"tanh": 0, "sigmoid": 1, "relu": 2}
 DTYPE = {"float64": 0, "float32": 1}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
-OP = {"exact": 0, "opg": 1, "hvp": 2, "topk": 3, "predvar": 4, "batched": 5, "exact_cols": 6, "curvature": 7}
+OP = {"exact": 0, "opg": 1, "hvp": 2, "topk": 3, "predvar": 4, "batched": 5, "exact_cols": 6, "curvature": 7, "syev": 8}
 OPT = {"check_inputs": 0, "hbm_budget": 1, "fault_after": 2, "profile": 3, "graphs": 4, "autotune": 5}
 
 # Every symbol include/hess.h declares.
@@ -26,6 +26,7 @@ EXPORTS = (
     "hess_topk_eig", "hess_predvar", "hess_profile_read", "hess_profile_reset", "hess_batched",
     "hess_server_create", "hess_server_submit", "hess_server_wait", "hess_server_stats", "hess_server_destroy",
     "hess_mfma_stream_rate", "hess_hvp_prepare", "hess_hvp_apply", "hess_hvp_release", "hess_curvature",
+    "hess_syev",
 )
 
 
@@ -41,7 +42,8 @@ class HessData(C.Structure):
 class HessEigOpts(C.Structure):
     _fields_ = [("which", C.c_int32), ("source", C.c_int32), ("M", C.c_void_p), ("M_dtype", C.c_int32),
                 ("prec", C.c_int32), ("P", C.c_int64), ("oversample", C.c_int64),
-                ("max_iter", C.c_int32), ("tol", C.c_double), ("seed", C.c_uint64)]
+                ("max_iter", C.c_int32), ("tol", C.c_double), ("seed", C.c_uint64), ("method", C.c_int32),
+                ("block", C.c_int32)]
 
 
 class HessEigInfo(C.Structure):
@@ -93,6 +95,7 @@ def load(path: str = LIB_PATH):
         "hess_hvp_apply": (st, [vp, vp, i64, vp, vp]),
         "hess_hvp_release": (st, [vp]),
         "hess_curvature": (st, [vp, C.c_int, i64, i64, vp, vp, C.c_double, i64, vp, vp, vp, C.c_size_t]),
+        "hess_syev": (st, [vp, i64, vp, i64, vp, vp, vp, C.c_size_t]),
         "hess_topk_eig": (st, [vp, pm, pd, i64, C.POINTER(HessEigOpts), vp, vp,
                                C.POINTER(HessEigInfo), vp, C.c_size_t]),
         "hess_predvar": (st, [vp, pm, i64, vp, vp, C.c_double, i64, vp, vp, vp, vp, C.c_size_t]),

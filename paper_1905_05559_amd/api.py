@@ -244,6 +244,24 @@ def curvature(mode: str, lam: torch.Tensor, Q: torch.Tensor, X: torch.Tensor, la
     return out
 
 
+def syev(A: torch.Tensor, ctx: Optional[Context] = None):
+    """Eigen-decomposition of a symmetric FP64 device matrix (n <= 512; rows may be
+    strided): returns (w descending (n,), U (n x n), row j = eigenvector j), see
+    hess_syev in include/hess.h."""
+    ctx = ctx or default_context()
+    if A.dtype != torch.float64 or A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1:
+        raise ValueError("syev takes a square FP64 matrix with unit column stride")
+    n = int(A.shape[0])
+    w = torch.empty(n, dtype=torch.float64, device=A.device)
+    U = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    nb = C.c_size_t()
+    ctx._check(ctx.lib.hess_workspace_size(ctx.h, L.OP["syev"], None, None, L.PREC["f64"], n, None, C.byref(nb)))
+    ws = ctx.workspace(nb.value)
+    ctx._check(ctx.lib.hess_syev(ctx.h, n, A.data_ptr(), int(A.stride(0)), w.data_ptr(), U.data_ptr(),
+                                 ws.data_ptr(), ws.numel()))
+    return w, U
+
+
 class HvpOperator:
     """Prepared HVP operator of (model, X, Y): the per-example passes run once, then
     apply(V) forms H V for blocks of up to max_B directions (hess_hvp_prepare /
@@ -299,7 +317,9 @@ def hess_exact_cols(model: MLP, X: torch.Tensor, Y: torch.Tensor, col0: int, nco
 
 def eig_opts(which: str = "H", source: str = "matrix_free", M: Optional[torch.Tensor] = None,
              prec: str = "f32", oversample: int = 10, max_iter: int = 200, tol: float = 1e-5,
-             seed: int = 0) -> L.HessEigOpts:
+             seed: int = 0, method: str = "subspace", block: int = 0) -> L.HessEigOpts:
+    """Options of hess_topk_eig; method "subspace" (filtered subspace iteration) or
+    "lanczos" (thick-restart block Lanczos with blocks of `block` vectors, 0 = 32)."""
     o = L.HessEigOpts()
     o.which = 0 if which == "H" else 1
     o.source = 0 if source == "matrix_free" else 1
@@ -311,6 +331,8 @@ def eig_opts(which: str = "H", source: str = "matrix_free", M: Optional[torch.Te
     o.max_iter = int(max_iter)
     o.tol = float(tol)
     o.seed = int(seed)
+    o.method = {"subspace": 0, "lanczos": 1}[method]
+    o.block = int(block)
     o._keep = M
     return o
 

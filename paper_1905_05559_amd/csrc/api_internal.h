@@ -94,6 +94,25 @@ void jv_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T
 // Workspace queries of the other translation units.
 hess_status exact_cols_workspace(hess_ctx* ctx, const Model& m, int64_t N, int prec, int64_t ncols, size_t* bytes);
 hess_status curvature_workspace(hess_ctx* ctx, int64_t K, int64_t nx, size_t* bytes);
+
+// Dense symmetric eigen-decomposition (n <= 512), hess_syev.hip: w descending, U rows
+// = eigenvectors (ldu), sign-normalised.  run_syev synchronises the stream once per
+// recorded rotation chunk and returns false on a device error or QL non-convergence.
+struct SyevBufs {
+  int n = 0;
+  double *A = nullptr, *Q = nullptr, *d = nullptr, *e = nullptr, *tau = nullptr, *rot = nullptr;
+  int *st = nullptr, *perm = nullptr;
+  int64_t cap = 0;
+};
+void plan_syev(Arena& ar, int n, SyevBufs& s);
+bool run_syev(Exec& ex, const double* A, int64_t lda, double* w, double* U, int64_t ldu, SyevBufs& s);
+hess_status syev_workspace(hess_ctx* ctx, int64_t n, size_t* bytes);
+
+// Y part = Q M for a thin FP32 block (k_skinny.hip): part[s][b][P] over ks slices of
+// kslice rows of M (P x P, row-major); the caller sums the slices in order.
+void skinny_slices(int64_t P, int64_t b, int64_t& ks, int64_t& kslice);
+void skinny_apply_f32(Exec& ex, const float* Q, int64_t b, int64_t P, const float* M, float* part, int64_t ks,
+                      int64_t kslice);
 hess_status hvp_workspace(hess_ctx* ctx, const Model& m, int64_t N, int prec, int64_t B, size_t* bytes);
 hess_status topk_workspace(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int64_t K,
                            const hess_eig_opts* o, size_t* bytes);

@@ -762,6 +762,8 @@ hess_status hess_workspace_size(hess_ctx* ctx, int op, const hess_mlp* mlp, cons
     case HESS_OP_CURVATURE:
       if (!opts) return fail(ctx, HESS_E_ARG, "HESS_OP_CURVATURE needs opts = const int64_t* K");
       return curvature_workspace(ctx, *static_cast<const int64_t*>(opts), arg, bytes);
+    case HESS_OP_SYEV:
+      return syev_workspace(ctx, arg, bytes);
     case HESS_OP_EXACT_COLS:
       if ((s = validate_mlp(ctx, mlp, m, false)) != HESS_OK) return s;
       if ((s = validate_data(ctx, d, false)) != HESS_OK) return s;

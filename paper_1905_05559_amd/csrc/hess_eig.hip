@@ -28,7 +28,7 @@ namespace {
 
 constexpr int TPB = 256;
 constexpr int BMAX = 128;     // largest block size (Jacobi and Cholesky run in LDS)
-constexpr int64_t KSPLIT = 4096;  // columns per split of the b x b Gram products
+constexpr int64_t KSPLIT = 1024;  // columns per split of the Gram products (block rows are padded to it)
 
 inline unsigned grid_for(int64_t n) {
   int64_t g = (n + TPB - 1) / TPB;
@@ -365,6 +365,7 @@ struct EigBufs {
   float *Qf, *Yf;
   float* Ypart = nullptr;      // dense FP32 operator: per-slice partial products
   int64_t ks = 1, kslice = 0;  // slices of the contraction over P
+  bool skinny = false;         // dense FP32 operator with b <= 64: thin-block kernel
   double *part, *W, *Linv, *T, *U, *theta, *res;
   int* info;
   Prep p;
@@ -412,7 +413,11 @@ static size_t plan_eig(Arena& ar, const Model* m, int64_t N, int64_t P, int64_t 
   e.Yf = ar.take<float>(b * P);
   e.part = ar.take<double>(e.S * b * b);
   if (source == 1 && mdtype == HESS_F32) {
-    dense_slices(P, b, e.ks, e.kslice);
+    e.skinny = b <= 64;
+    if (e.skinny)
+      skinny_slices(P, b, e.ks, e.kslice);
+    else
+      dense_slices(P, b, e.ks, e.kslice);
     e.Ypart = ar.take<float>(e.ks * b * P);
   }
   for (double** x : {&e.W, &e.Linv, &e.T, &e.U}) *x = ar.take<double>(b * b);
@@ -466,6 +471,12 @@ void op_apply(EigRun& r, const double* Q, double* Y) {
       // of M holds M[k][c] for all c); the contraction over k is split into slices whose
       // partial products are summed in slice order.
       if (!launch_ok(ex)) return;
+      if (e.skinny) {  // thin block: M streamed once per application
+        cast_2d<float>(ex, Q, b, P, ldp, e.Qf, P);
+        skinny_apply_f32(ex, e.Qf, b, P, static_cast<const float*>(r.M), e.Ypart, e.ks, e.kslice);
+        LAUNCH(k_sum_splits_f32, b * P, e.Ypart, e.ks, b, P, Y, ldp);
+        return;
+      }
       hipLaunchKernelGGL(k_cast_t, dim3((unsigned)((P + 31) / 32), (unsigned)((b + 31) / 32)), dim3(256), 0,
                          ex.stream, Q, b, P, ldp, e.Qf);
       KrgArgs<float, float> a;
@@ -596,19 +607,21 @@ void gram(EigRun& r, const double* A, const double* B, double* C) {
   LAUNCH(k_sum_splits, e.b * e.b, e.part, e.S, e.b * e.b, C);
 }
 
-// Q = orthonormal rows spanning Y: shifted Cholesky-QR, then two plain passes.  Y is overwritten.
-void orth(EigRun& r, double* Y, double* Q) {
+// Q = orthonormal rows spanning Y: shifted Cholesky-QR, then plain passes (three passes
+// in all by default; with first_plain the first pass is unshifted too).  Y is overwritten;
+// with an odd number of passes the result is in Q.
+void orth(EigRun& r, double* Y, double* Q, int passes = 3, bool first_plain = false) {
   Exec& ex = *r.ex;
   EigBufs& e = *r.e;
   const int b = (int)e.b;
   const size_t shm = (size_t)b * (b + 1) * sizeof(double);
-  for (int pass = 0; pass < 3; ++pass) {
+  for (int pass = 0; pass < passes; ++pass) {
     double* src = pass == 1 ? Q : Y;
     double* dst = pass == 1 ? Y : Q;
     gram(r, src, src, e.W);
     if (!launch_ok(ex)) return;
-    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), shm, ex.stream, e.W, b, e.P, pass == 0 ? 1 : 0, e.Linv,
-                       e.info);
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), shm, ex.stream, e.W, b, e.P,
+                       (pass == 0 && !first_plain) ? 1 : 0, e.Linv, e.info);
     gemm_rm<double>(ex, false, false, b, e.ldp, b, 1.0, e.Linv, b, src, e.ldp, 0.0, dst, e.ldp);
   }
 }
@@ -640,6 +653,282 @@ bool read_back(Exec& ex, EigBufs& e, std::vector<double>& theta, std::vector<dou
   return hipStreamSynchronize(ex.stream) == hipSuccess && !ex.ctx->fault_hit;
 }
 
+// ---------------------------------------------------------------------------
+// Thick-restart block Lanczos with locking (method 1).
+//
+// The window W holds n orthonormal rows (n <= win): kept Ritz vectors followed by
+// Lanczos blocks; T = W Op W^T is kept explicitly (n x n, row stride win).  Each step
+// applies Op to the open block (the last one), re-orthogonalises the product against
+// W and the locked vectors L with two classical Gram-Schmidt passes (their
+// coefficients give T's column block), and orthonormalises the remainder into the
+// next block; T's coupling block is V_new Z^T.  When the window is full, T is
+// diagonalised (Rayleigh-Ritz); residual norms of the Ritz pairs follow from the
+// remainder Z of the last block without another product.  The leading Ritz pairs with
+// residual below half the tolerance are locked; the next `keep` Ritz vectors plus the
+// orthonormalised remainder start the next window (T = diag(theta) with the coupling
+// row).  Once K pairs are locked, a Rayleigh-Ritz over L gives the reported pairs and
+// their true residuals.
+// ---------------------------------------------------------------------------
+
+// T[i][o + j] = T[o + j][i] = C[i][j] for i < n, j < b; the open block's diagonal
+// block is symmetrised.
+__global__ void k_put_cols(double* T, int64_t ldt, int64_t n, int64_t o, int64_t b, const double* C) {
+  GRID_STRIDE(e, n * b) {
+    const int64_t i = e / b, j = e % b;
+    double v = C[e];
+    if (i >= o && i < o + b) v = 0.5 * (v + C[(o + j) * b + (i - o)]);
+    T[i * ldt + o + j] = v;
+    T[(o + j) * ldt + i] = v;
+  }
+}
+
+// T[r0 + x][o + a] = T[o + a][r0 + x] = G[x][a]
+__global__ void k_put_coupling(double* T, int64_t ldt, int64_t r0, int64_t o, int64_t b, const double* G) {
+  GRID_STRIDE(e, b * b) {
+    const int64_t x = e / b, a = e % b;
+    T[(r0 + x) * ldt + o + a] = G[e];
+    T[(o + a) * ldt + r0 + x] = G[e];
+  }
+}
+
+// res[j] = sqrt(u_j^T Zg u_j), u_j = U[j][o .. o + b): residual norm of Ritz pair j
+__global__ void k_res_est(const double* U, int64_t ldu, int64_t n, int64_t o, int64_t b, const double* Zg,
+                          double* res) {
+  GRID_STRIDE(j, n) {
+    const double* u = U + j * ldu + o;
+    double acc = 0.0;
+    for (int64_t a = 0; a < b; ++a) {
+      double t = 0.0;
+      for (int64_t c = 0; c < b; ++c) t += Zg[a * b + c] * u[c];
+      acc += u[a] * t;
+    }
+    res[j] = sqrt(acc > 0.0 ? acc : 0.0);
+  }
+}
+
+// restarted T (zeroed before): T[j][j] = theta[j] (j < kk); coupling of the new block
+// T[kk + x][j] = T[j][kk + x] = sum_a G[x][a] U[j0 + j][o + a]
+__global__ void k_restart_t(double* T, int64_t ldt, int64_t kk, int64_t b, const double* theta, const double* U,
+                            int64_t ldu, int64_t j0, int64_t o, const double* G) {
+  GRID_STRIDE(e, (b + 1) * kk) {
+    const int64_t x = e / kk, j = e % kk;
+    if (x == b) {
+      T[j * ldt + j] = theta[j];
+    } else {
+      double acc = 0.0;
+      for (int64_t a = 0; a < b; ++a) acc += G[x * b + a] * U[(j0 + j) * ldu + o + a];
+      T[(kk + x) * ldt + j] = acc;
+      T[j * ldt + kk + x] = acc;
+    }
+  }
+}
+
+struct LzBufs {
+  int64_t b = 0, win = 0, keep = 0, K = 0;
+  double *W, *W2, *L, *C, *Cp, *part, *T, *U, *w, *res, *G, *Zg;
+  SyevBufs sy;
+};
+
+void plan_lanczos(Arena& ar, int64_t ldp, int64_t S, int64_t b, int64_t win, int64_t keep, int64_t K, LzBufs& z) {
+  z.b = b;
+  z.win = win;
+  z.keep = keep;
+  z.K = K;
+  z.W = ar.take<double>(win * ldp);
+  z.W2 = ar.take<double>(win * ldp);
+  z.L = ar.take<double>(K * ldp);
+  z.C = ar.take<double>(win * b);
+  z.Cp = ar.take<double>(std::max(win, K) * b);
+  z.part = ar.take<double>(S * std::max(win * b, K * K));
+  z.T = ar.take<double>(win * win);
+  z.U = ar.take<double>(win * win);
+  z.w = ar.take<double>(win);
+  z.res = ar.take<double>(win);
+  z.G = ar.take<double>(b * b);
+  z.Zg = ar.take<double>(b * b);
+  plan_syev(ar, (int)win, z.sy);
+}
+
+// C (M x N, row-major) = A B^T over the ldp columns of the row blocks A (M rows) and
+// B (N rows); split over KSPLIT columns, partials summed in split order.
+void gram_mn(EigRun& r, const double* A, int64_t M, const double* B, int64_t N, double* part, double* C) {
+  Exec& ex = *r.ex;
+  EigBufs& e = *r.e;
+  GemmArgs<double> g;
+  g.M = M; g.N = N; g.K = KSPLIT;
+  g.A = A; g.sam = e.ldp; g.sak = 1; g.sab = KSPLIT;
+  g.B = B; g.sbk = 1; g.sbn = e.ldp; g.sbb = KSPLIT;
+  g.C = part; g.scm = N; g.scn = 1; g.scb = M * N;
+  g.alpha = 1.0; g.beta = 0.0; g.batch = e.S;
+  gemm<double>(ex, g);
+  LAUNCH(k_sum_splits, M * N, part, e.S, M * N, C);
+}
+
+// Z -= C^T A: removes from the b rows of Z their components along the M rows of A
+void project_out(EigRun& r, const double* C, const double* A, int64_t M, double* Z) {
+  EigBufs& e = *r.e;
+  gemm_rm<double>(*r.ex, true, false, e.b, e.ldp, M, -1.0, C, e.b, A, e.ldp, 1.0, Z, e.ldp);
+}
+
+SyevBufs syev_view(const SyevBufs& s, int n) {
+  SyevBufs v = s;
+  v.n = n;
+  v.cap = 3 * (int64_t)n * n + 4 * (int64_t)n + 16;
+  return v;
+}
+
+// e.Q = orthonormal rows spanning e.Z's rows, orthogonal to the nw rows of Wb and the
+// nl rows of z.L; z.G = e.Q e.Z^T.  Two Cholesky-QR passes (the first shifted), one more
+// projection against Wb and L (which matters when Z is tiny, i.e. near an invariant
+// subspace), two plain Cholesky-QR passes.
+void lz_new_block(EigRun& r, LzBufs& z, const double* Wb, int64_t nw, int64_t nl) {
+  Exec& ex = *r.ex;
+  EigBufs& e = *r.e;
+  const int64_t nb = e.b * e.ldp;
+  hipMemcpyAsync(e.Y, e.Z, nb * sizeof(double), hipMemcpyDeviceToDevice, ex.stream);
+  orth(r, e.Y, e.Q, 2);  // result in e.Y
+  gram_mn(r, Wb, nw, e.Y, e.b, z.part, z.Cp);
+  project_out(r, z.Cp, Wb, nw, e.Y);
+  if (nl > 0) {
+    gram_mn(r, z.L, nl, e.Y, e.b, z.part, z.Cp);
+    project_out(r, z.Cp, z.L, nl, e.Y);
+  }
+  orth(r, e.Y, e.Q, 2, true);  // result in e.Y
+  hipMemcpyAsync(e.Q, e.Y, nb * sizeof(double), hipMemcpyDeviceToDevice, ex.stream);
+  gram_mn(r, e.Q, e.b, e.Z, e.b, z.part, z.G);
+}
+
+struct LzResult {
+  int restarts = 0, applies = 0;
+  double maxrel = 0.0;
+  bool converged = false, ok = true;
+};
+
+LzResult lanczos_topk(EigRun& r, LzBufs& z, int64_t K, double tol, int max_restarts, uint64_t seed, double* lambda,
+                      double* Qout) {
+  Exec& ex = *r.ex;
+  EigBufs& e = *r.e;
+  LzResult out;
+  const int64_t b = e.b, ldp = e.ldp, P = e.P, win = z.win, nb = b * ldp;
+  const double margin = 0.5;
+  for (double* x : {e.Q, e.Y, e.Z})
+    if (launch_ok(ex)) hipLaunchKernelGGL(k_fill, dim3(grid_for(nb)), dim3(TPB), 0, ex.stream, x, nb, 0.0);
+  if (launch_ok(ex))
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(win * win)), dim3(TPB), 0, ex.stream, z.T, win * win, 0.0);
+  if (launch_ok(ex))
+    hipLaunchKernelGGL(k_randn, dim3(grid_for(nb)), dim3(TPB), 0, ex.stream, seed, b, P, ldp, e.Y);
+  orth(r, e.Y, e.Q);
+  hipMemcpyAsync(z.W, e.Q, nb * sizeof(double), hipMemcpyDeviceToDevice, ex.stream);
+  int64_t n = b, o = 0, nl = 0;
+  double scale = 0.0;
+  std::vector<double> w, res;
+  for (;;) {
+    apply_op(r, r.gc, e.Q, e.Z);
+    ++out.applies;
+    for (int pass = 0; pass < 2; ++pass) {
+      double* c = pass == 0 ? z.C : z.Cp;
+      gram_mn(r, z.W, n, e.Z, b, z.part, c);
+      project_out(r, c, z.W, n, e.Z);
+      if (pass == 1 && launch_ok(ex))
+        hipLaunchKernelGGL(k_axpbypcz, dim3(grid_for(n * b)), dim3(TPB), 0, ex.stream, 1.0, z.C, 1.0, z.Cp, 0.0,
+                           nullptr, n * b, z.C);
+      if (nl > 0) {
+        gram_mn(r, z.L, nl, e.Z, b, z.part, z.Cp);
+        project_out(r, z.Cp, z.L, nl, e.Z);
+      }
+    }
+    if (launch_ok(ex))
+      hipLaunchKernelGGL(k_put_cols, dim3(grid_for(n * b)), dim3(TPB), 0, ex.stream, z.T, win, n, o, b, z.C);
+    if (n + b <= win) {
+      lz_new_block(r, z, z.W, n, nl);
+      if (launch_ok(ex))
+        hipLaunchKernelGGL(k_put_coupling, dim3(grid_for(b * b)), dim3(TPB), 0, ex.stream, z.T, win, n, o, b, z.G);
+      hipMemcpyAsync(z.W + n * ldp, e.Q, nb * sizeof(double), hipMemcpyDeviceToDevice, ex.stream);
+      o = n;
+      n += b;
+      continue;
+    }
+    // Rayleigh-Ritz on the full window
+    ++out.restarts;
+    SyevBufs sv = syev_view(z.sy, (int)n);
+    if (!run_syev(ex, z.T, win, z.w, z.U, n, sv)) {
+      out.ok = false;
+      return out;
+    }
+    gram_mn(r, e.Z, b, e.Z, b, z.part, z.Zg);
+    if (launch_ok(ex))
+      hipLaunchKernelGGL(k_res_est, dim3(grid_for(n)), dim3(TPB), 0, ex.stream, z.U, n, n, o, b, z.Zg, z.res);
+    w.assign(n, 0.0);
+    res.assign(n, 0.0);
+    hipMemcpyAsync(w.data(), z.w, n * sizeof(double), hipMemcpyDeviceToHost, ex.stream);
+    hipMemcpyAsync(res.data(), z.res, n * sizeof(double), hipMemcpyDeviceToHost, ex.stream);
+    if (hipStreamSynchronize(ex.stream) != hipSuccess || ex.ctx->fault_hit) {
+      out.ok = false;
+      return out;
+    }
+    scale = std::max(scale, std::fabs(w[0]));
+    const int64_t need = K - nl;
+    int64_t nc = 0;
+    while (nc < need && std::isfinite(res[nc]) && res[nc] <= margin * tol * scale) ++nc;
+    const bool last = nl + nc >= K || out.restarts >= max_restarts || !std::isfinite(w[0]);
+    // at the restart cap, the leading unconverged Ritz vectors fill the remaining slots
+    const int64_t take = last ? need : nc;
+    if (take > 0) gemm_rm<double>(ex, false, false, take, ldp, n, 1.0, z.U, n, z.W, ldp, 0.0, z.L + nl * ldp, ldp);
+    nl += take;
+    if (last) {
+      out.converged = nc >= need;
+      break;
+    }
+    const int64_t kk = std::min<int64_t>(z.keep, n - nc);
+    gemm_rm<double>(ex, false, false, kk, ldp, n, 1.0, z.U + nc * n, n, z.W, ldp, 0.0, z.W2, ldp);
+    std::swap(z.W, z.W2);
+    lz_new_block(r, z, z.W, kk, nl);
+    if (launch_ok(ex))
+      hipLaunchKernelGGL(k_fill, dim3(grid_for(win * win)), dim3(TPB), 0, ex.stream, z.T, win * win, 0.0);
+    if (launch_ok(ex))
+      hipLaunchKernelGGL(k_restart_t, dim3(grid_for((b + 1) * kk)), dim3(TPB), 0, ex.stream, z.T, win, kk, b,
+                         z.w + nc, z.U, n, nc, o, z.G);
+    hipMemcpyAsync(z.W + kk * ldp, e.Q, nb * sizeof(double), hipMemcpyDeviceToDevice, ex.stream);
+    o = kk;
+    n = kk + b;
+  }
+  // final Rayleigh-Ritz over the K locked vectors: M L into W2, in blocks of b rows
+  for (int64_t c0 = 0; c0 < K; c0 += b) {
+    const int64_t rows = std::min<int64_t>(b, K - c0);
+    if (rows < b && launch_ok(ex))
+      hipLaunchKernelGGL(k_fill, dim3(grid_for(nb)), dim3(TPB), 0, ex.stream, e.Q, nb, 0.0);
+    hipMemcpyAsync(e.Q, z.L + c0 * ldp, rows * ldp * sizeof(double), hipMemcpyDeviceToDevice, ex.stream);
+    apply_op(r, r.gc, e.Q, e.Z);
+    ++out.applies;
+    hipMemcpyAsync(z.W2 + c0 * ldp, e.Z, rows * ldp * sizeof(double), hipMemcpyDeviceToDevice, ex.stream);
+  }
+  gram_mn(r, z.L, K, z.W2, K, z.part, z.T);
+  SyevBufs sv = syev_view(z.sy, (int)K);
+  if (!run_syev(ex, z.T, K, z.w, z.U, K, sv)) {
+    out.ok = false;
+    return out;
+  }
+  gemm_rm<double>(ex, false, false, K, ldp, K, 1.0, z.U, K, z.L, ldp, 0.0, z.W, ldp);   // X
+  gemm_rm<double>(ex, false, false, K, ldp, K, 1.0, z.U, K, z.W2, ldp, 0.0, z.L, ldp);  // M X
+  if (launch_ok(ex))
+    hipLaunchKernelGGL(k_resid, dim3((unsigned)K), dim3(256), 0, ex.stream, z.L, z.W, z.w, P, ldp, z.res);
+  w.assign(K, 0.0);
+  res.assign(K, 0.0);
+  hipMemcpyAsync(w.data(), z.w, K * sizeof(double), hipMemcpyDeviceToHost, ex.stream);
+  hipMemcpyAsync(res.data(), z.res, K * sizeof(double), hipMemcpyDeviceToHost, ex.stream);
+  hipMemcpyAsync(lambda, z.w, K * sizeof(double), hipMemcpyDeviceToDevice, ex.stream);
+  if (launch_ok(ex))
+    hipLaunchKernelGGL(k_sign_copy, dim3((unsigned)K), dim3(256), 0, ex.stream, z.W, P, ldp, Qout);
+  if (hipStreamSynchronize(ex.stream) != hipSuccess || ex.ctx->fault_hit) {
+    out.ok = false;
+    return out;
+  }
+  const double sc = std::max(std::fabs(w[0]), 1e-300);
+  for (int64_t k = 0; k < K; ++k) out.maxrel = std::max(out.maxrel, res[k] / sc);
+  if (!std::isfinite(out.maxrel) || out.maxrel > tol) out.converged = false;
+  return out;
+}
+
 }  // namespace
 
 struct TopkPlan {
@@ -649,6 +938,8 @@ struct TopkPlan {
   int source = 0, which = 0, prec = 1, Mdtype = 0, max_iter = 200;
   double tol = 1e-5;
   int64_t oversample = 10;
+  int method = 0;
+  int64_t win = 0, keep = 0;  // method 1: window and kept Ritz vectors (b = block size)
 };
 
 static hess_status topk_validate(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, int64_t K,
@@ -679,6 +970,19 @@ static hess_status topk_validate(hess_ctx* ctx, const hess_mlp* mlp, const hess_
   t.max_iter = o->max_iter <= 0 ? 200 : o->max_iter;
   t.tol = o->tol > 0 ? o->tol : 1e-5;
   if (K < 1 || K > t.P) return fail(ctx, HESS_E_SHAPE, "K out of range");
+  t.method = o->method;
+  if (t.method != 0 && t.method != 1) return fail(ctx, HESS_E_ARG, "opts.method must be 0 or 1");
+  if (t.method == 1) {
+    // block b <= (P - K) / 3 so that a window of K + 2b rows leaves room for one more block
+    int64_t b = o->block > 0 ? o->block : 32;
+    b = std::min<int64_t>(std::min<int64_t>(b, BMAX), (t.P - K) / 3);
+    if (b < 1) return fail(ctx, HESS_E_SHAPE, "Lanczos: P must be at least K + 3");
+    t.b = b;
+    t.win = std::min<int64_t>(std::min<int64_t>(512, 3 * K + 3 * b), t.P - b);
+    if (t.win < K + 2 * b) return fail(ctx, HESS_E_SHAPE, "Lanczos: K + 2 block must fit in a 512-row window");
+    t.keep = std::min<int64_t>(2 * K + b, t.win - 2 * b);
+    return HESS_OK;
+  }
   t.b = std::min<int64_t>(rup(K + t.oversample, 16), t.P);
   if (t.b > BMAX) return fail(ctx, HESS_E_SHAPE, "K + oversample must not exceed 128");
   return HESS_OK;
@@ -692,6 +996,11 @@ hess_status topk_workspace(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* 
   Arena ar(nullptr);
   EigBufs e;
   *bytes = plan_eig(ar, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, t.Mdtype, e);
+  if (t.method == 1) {
+    LzBufs z;
+    plan_lanczos(ar, e.ldp, e.S, t.b, t.win, t.keep, K, z);
+    *bytes = ar.used;
+  }
   return HESS_OK;
 }
 
@@ -710,11 +1019,17 @@ extern "C" hess_status hess_topk_eig(hess_ctx* ctx, const hess_mlp* mlp, const h
   if (!lambda || !Qout) return fail(ctx, HESS_E_ARG, "lambda or Q is NULL");
   Arena probe(nullptr);
   EigBufs e0;
-  const size_t need = plan_eig(probe, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, t.Mdtype, e0);
+  size_t need = plan_eig(probe, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, t.Mdtype, e0);
+  LzBufs z;
+  if (t.method == 1) {
+    plan_lanczos(probe, e0.ldp, e0.S, t.b, t.win, t.keep, K, z);
+    need = probe.used;
+  }
   if ((s = check_ws(ctx, need, ws, ws_bytes, (size_t)K * (t.P + 1) * 8)) != HESS_OK) return s;
   Arena ar(ws);
   EigBufs e;
   plan_eig(ar, t.has_model ? &t.m : nullptr, t.N, t.P, t.b, t.source, t.prec, t.Mdtype, e);
+  if (t.method == 1) plan_lanczos(ar, e.ldp, e.S, t.b, t.win, t.keep, K, z);
   if (t.source == 0) {
     if ((s = check_inputs(ex, t.m, d, e.p)) != HESS_OK) return s;
     run_prep(ex, t.m, d, e.p, false);
@@ -728,6 +1043,22 @@ extern "C" hess_status hess_topk_eig(hess_ctx* ctx, const hess_mlp* mlp, const h
            t.source == 1 ? opts->M : nullptr};
   GraphCache graphs;  // destroyed after the call has synchronised (finish)
   if (ctx->graphs) r.gc = &graphs;
+  if (t.method == 1) {
+    const LzResult lr = lanczos_topk(r, z, K, t.tol, t.max_iter, (uint64_t)opts->seed, lambda, Qout);
+    if (info) {
+      info->iters = lr.restarts;
+      info->applies = lr.applies;
+      info->max_rel_residual = lr.maxrel;
+      info->shift_used = 0.0;
+    }
+    s = finish(ex, "hess_topk_eig");
+    if (s != HESS_OK) return s;
+    if (!lr.ok) return fail(ctx, HESS_E_NOCONV, "Lanczos: projected eigenproblem did not converge");
+    if (!lr.converged)
+      return fail(ctx, HESS_E_NOCONV,
+                  "no convergence within max_iter restarts (max rel residual " + std::to_string(lr.maxrel) + ")");
+    return HESS_OK;
+  }
   const int64_t nb = e.b * e.ldp;
   if (launch_ok(ex))
     hipLaunchKernelGGL(k_fill, dim3(grid_for(16)), dim3(TPB), 0, ex.stream, reinterpret_cast<double*>(e.info),
