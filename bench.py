@@ -8,7 +8,8 @@ step runs every row of the hot path on that workload, with inputs already
 resident in HBM:
   * the OPG  J^T J / N  (BF16 operands, FP32 accumulation), P x P FP32
   * the exact Hessian H (FP32 MFMA), P x P FP32
-  * the 100 algebraically largest eigenpairs of H (FP32 operator, FP64 Rayleigh-Ritz, tol 1e-5)
+  * the 100 algebraically largest eigenpairs of H by block Lanczos (blocks of 16, FP32
+    operator, FP64 re-orthogonalisation and Rayleigh-Ritz, tol 1e-5)
   * 512 dense Hessian-vector products (matrix-free R-operator, FP32)
   * the damped curvature query for 1024 inputs against those eigenpairs (FP64)
 value = 2 P^2 / step time  ("exact-H+OPG P^2-entries/s": P^2 entries of each matrix),
@@ -119,6 +120,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mnist", choices=["mnist", "sigmoid64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the measurements after the timed steps (HVP block sweep, other eigensolver "
+                         "configurations, MFMA stream rate), e.g. for a profile of the steps alone")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -164,7 +168,9 @@ def main():
     V = torch.from_numpy(workloads.gaussian_directions(B, P, 7)).to(dev)
     HV = torch.empty_like(V)
     Xq = torch.from_numpy(workloads.queries_like_mnist(NQ, 11, T1=w.T[0])).to(dev)
-    eopts = api.eig_opts(which="H", source="dense", M=H, tol=1e-5, seed=1, oversample=12, max_iter=200)
+    LZ_BLOCK = 16
+    eopts = api.eig_opts(which="H", source="dense", M=H, tol=1e-5, seed=1, max_iter=200, method="lanczos",
+                         block=LZ_BLOCK)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     phase_ms = {"opg": 0.0, "exact_H": 0.0, "topk": 0.0, "hvp": 0.0, "predvar": 0.0}
     eig_info = {}
@@ -242,13 +248,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "T": w.T, "N": w.N, "P": P,
                    "step": "OPG (BF16 MFMA, FP32 acc) + exact H (FP32 MFMA), P x P each; top-100 eigenpairs "
-                           "of H (FP32 operator, FP64 RR, tol 1e-5); 512 dense HVPs (FP32); damped query "
-                           "for 1024 inputs (FP64); inputs resident in HBM"},
+                           "of H (block Lanczos, block 16, FP32 operator, FP64 RR, tol 1e-5); 512 dense HVPs "
+                           "(FP32); damped query for 1024 inputs (FP64); inputs resident in HBM"},
         "phases_ms": {k: round(v, 3) for k, v in ph.items()},
         "hvps_per_s": {"dense_B512": B / (ph["hvp"] / 1e3), "basis_via_exact_H": P / (ph["exact_H"] / 1e3)},
         "opg_p2_entries_per_s": P * P / (ph["opg"] / 1e3),
         "exact_h_p2_entries_per_s": P * P / (ph["exact_H"] / 1e3),
-        "topk": {"K": K, "iters": eig_info.get("iters"), "applies": eig_info.get("applies"),
+        "topk": {"K": K, "method": "lanczos", "block": LZ_BLOCK, "restarts": eig_info.get("iters"),
+                 "block_applies": eig_info.get("applies"),
+                 "vectors_applied": (eig_info.get("applies") or 0) * LZ_BLOCK,
                  "max_rel_residual": eig_info.get("max_rel_residual")},
         "predvar_queries_per_s": NQ / (ph["predvar"] / 1e3),
         "roofline": roofline,
@@ -271,24 +279,45 @@ def main():
             times.append(a0.elapsed_time(a1))
         return sorted(times)[1] / 1e3
 
-    op = api.HvpOperator(model, X, Y, "f32", max_B=B, ctx=ctx)
-    rates = {}
-    for Bs in (1, 8, 64, 512):
-        Vb = V[:Bs].contiguous()
-        HVb = torch.empty_like(Vb)
-        rates["dense_B%d" % Bs] = Bs / timed(lambda: op.apply(Vb, out=HVb))
-        if Bs < B:
-            rates["dense_B%d_call" % Bs] = Bs / timed(lambda: api.hess_hvp(model, X, Y, Vb, "f32", out=HVb, ctx=ctx))
-    op.close()
-    rates["dense_B%d_call" % B] = out["hvps_per_s"].pop("dense_B%d" % B)
-    out["hvps_per_s"].update(rates)
-    # sustained rate of the dominant kernel's MFMA instruction in a register-only stream
-    stream_kind = {"f32": "f32_16x16x4", "bf16": "bf16_16x16x32", "f64": "f64_16x16x4"}[roofline["dtype"]]
-    srate = ctx.mfma_stream_rate(stream_kind)
-    out["roofline"]["mfma_stream_tflops"] = round(srate, 2)
-    out["roofline"]["frac_of_stream"] = round(roofline["achieved"] / srate, 4)
-    log("hvps/s %s; MFMA stream %s %.1f TFLOP/s" % (json.dumps({k: round(v, 1) for k, v in out["hvps_per_s"].items()}),
-                                                    stream_kind, srate))
+    if not args.no_side:
+        op = api.HvpOperator(model, X, Y, "f32", max_B=B, ctx=ctx)
+        rates = {}
+        for Bs in (1, 8, 64, 512):
+            Vb = V[:Bs].contiguous()
+            HVb = torch.empty_like(Vb)
+            rates["dense_B%d" % Bs] = Bs / timed(lambda: op.apply(Vb, out=HVb))
+            if Bs < B:
+                rates["dense_B%d_call" % Bs] = Bs / timed(lambda: api.hess_hvp(model, X, Y, Vb, "f32", out=HVb, ctx=ctx))
+        op.close()
+        # the same top-100 problem by the other eigensolver configurations (outside the timed steps)
+        for tag, oo in (("subspace_iteration", api.eig_opts(which="H", source="dense", M=H, tol=1e-5, seed=1,
+                                                             oversample=12, max_iter=200)),
+                        ("lanczos_block32", api.eig_opts(which="H", source="dense", M=H, tol=1e-5, seed=1,
+                                                          max_iter=200, method="lanczos", block=32))):
+            out["topk"]["ms_" + tag] = round(1e3 * timed(lambda: api.hess_topk_eig(None, None, None, K, oo, ctx=ctx)), 2)
+        # matrix-free operator (R-operator HVPs over all N examples, FP32), one call each
+        for tag, oo in (("matrix_free_lanczos_block16", api.eig_opts(which="H", source="matrix_free", prec="f32",
+                                                                      tol=1e-5, seed=1, max_iter=200,
+                                                                      method="lanczos", block=16)),
+                        ("matrix_free_subspace_iteration", api.eig_opts(which="H", source="matrix_free", prec="f32",
+                                                                         tol=1e-5, seed=1, oversample=12,
+                                                                         max_iter=200))):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, inf, st = api.hess_topk_eig(model, X, Y, K, oo, ctx=ctx, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            out["topk"]["ms_" + tag] = round(1e3 * (time.perf_counter() - t0), 2)
+            out["topk"]["info_" + tag] = {"status": st, **{k: inf[k] for k in ("iters", "applies", "max_rel_residual")}}
+            log("top-%d %s: %.1f ms %s %s" % (K, tag, out["topk"]["ms_" + tag], inf, st))
+        rates["dense_B%d_call" % B] = out["hvps_per_s"].pop("dense_B%d" % B)
+        out["hvps_per_s"].update(rates)
+        # sustained rate of the dominant kernel's MFMA instruction in a register-only stream
+        stream_kind = {"f32": "f32_16x16x4", "bf16": "bf16_16x16x32", "f64": "f64_16x16x4"}[roofline["dtype"]]
+        srate = ctx.mfma_stream_rate(stream_kind)
+        out["roofline"]["mfma_stream_tflops"] = round(srate, 2)
+        out["roofline"]["frac_of_stream"] = round(roofline["achieved"] / srate, 4)
+        log("hvps/s %s; MFMA stream %s %.1f TFLOP/s" % (json.dumps({k: round(v, 1) for k, v in out["hvps_per_s"].items()}),
+                                                        stream_kind, srate))
     del H, G, V, HV
     ctx.release_workspace()
     torch.cuda.empty_cache()

@@ -328,3 +328,52 @@ def test_hvp_basis_equals_exact_columns(api):
     err = (HV - H[:, cols].T).abs().max().item() / H.abs().max().item()
     print("basis HVP vs exact columns: rel max err %.3e" % err, flush=True)
     assert err < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Mini-batch and per-example modes (Sec. 3: H and the OPG of a mini-batch or of one
+# example are the same means over N' examples; the paper's listings average mini-batch
+# matrices over floor(N / bs) batches and drop the remainder)
+# ---------------------------------------------------------------------------
+
+def test_minibatch_mean_equals_full_n(api):
+    w = workloads.mlp_gaussian([12, 17, 9, 4], ["tanh", "sigmoid"], 300, 21, dtype="float64")
+    model, X, Y = to_dev(api, w, "float64")
+    om, Xo, Yo = oracle_of(w)
+    bs = 60
+    Hb = [api.hess_exact(model, X[i:i + bs].contiguous(), Y[i:i + bs].contiguous(), "f64").clone()
+          for i in range(0, 300, bs)]
+    Gb = [api.hess_opg(model, X[i:i + bs].contiguous(), Y[i:i + bs].contiguous(), "f64").clone()
+          for i in range(0, 300, bs)]
+    Hm = (sum(Hb) / len(Hb)).cpu().numpy()
+    Gm = (sum(Gb) / len(Gb)).cpu().numpy()
+    print("case mini-batch mean, bs=%d, %d batches" % (bs, len(Hb)), flush=True)
+    assert report("mean of mini-batch H vs oracle full-N H", Hm, mlp.hessian(om, Xo, Yo)) <= TOL["f64"]
+    assert report("mean of mini-batch OPG vs oracle full-N OPG", Gm, mlp.opg(om, Xo, Yo)) <= TOL["f64"]
+    # the listings' loop with a remainder: floor(N / bs) batches, the last N mod bs examples dropped
+    bs2 = 70
+    nb = 300 // bs2
+    Hd = sum(api.hess_exact(model, X[i * bs2:(i + 1) * bs2].contiguous(), Y[i * bs2:(i + 1) * bs2].contiguous(),
+                            "f64").clone() for i in range(nb)) / nb
+    Hk = api.hess_exact(model, X[:nb * bs2].contiguous(), Y[:nb * bs2].contiguous(), "f64")
+    assert report("dropped-remainder mean vs H of the kept examples", Hd.cpu().numpy(),
+                  Hk.cpu().numpy()) <= TOL["f64"]
+
+
+def test_per_example_hessians_batched(api):
+    # one hess_batched call with N' = 1 per network: the per-example H_n and OPG_n
+    w = workloads.mlp_gaussian([9, 14, 5], ["tanh"], 8, 22, dtype="float32")
+    model, X, Y = to_dev(api, w, "float32")
+    om, Xo, Yo = oracle_of(w)
+    n = X.shape[0]
+    Hs, Gs = api.hess_batched([model] * n, [X[i:i + 1].contiguous() for i in range(n)],
+                              [Y[i:i + 1].contiguous() for i in range(n)])
+    J = mlp.jacobian(om, Xo, Yo)
+    print("case per-example H and OPG of %d examples in one batched call" % n, flush=True)
+    for i in range(n):
+        Hr = mlp.hessian(om, Xo[i:i + 1], Yo[i:i + 1])
+        assert report("per-example H_%d" % i, Hs[i].cpu().numpy().astype(np.float64), Hr) <= TOL["f32"]
+        assert report("per-example OPG_%d = g g^T" % i, Gs[i].cpu().numpy().astype(np.float64),
+                      np.outer(J[i], J[i])) <= TOL["f32"]
+    Hmean = sum(h.double() for h in Hs).cpu().numpy() / n
+    assert report("mean of per-example H vs full H", Hmean, mlp.hessian(om, Xo, Yo)) <= TOL["f32"]
