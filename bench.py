@@ -7,7 +7,8 @@ uniform over 10 classes, Glorot-uniform weights, zero biases (P = 79510).  One
 step runs every row of the hot path on that workload, with inputs already
 resident in HBM:
   * the OPG  J^T J / N  (BF16 operands, FP32 accumulation), P x P FP32
-  * the exact Hessian H (FP32 MFMA), P x P FP32
+  * the exact Hessian H, P x P FP32: FP32 operands and accumulation, each product from BF16
+    MFMAs on compensated three-way splits of the operands (FP32-level error)
   * the 100 algebraically largest eigenpairs of H by block Lanczos (blocks of 16, FP32
     operator, FP64 re-orthogonalisation and Rayleigh-Ritz, tol 1e-5)
   * 512 dense Hessian-vector products (matrix-free R-operator, FP32)
@@ -33,7 +34,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAKS_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}   # MI355X dense MFMA peaks
+# MI355X dense MFMA peaks; "bf16x6": FP32 products from six BF16 MFMA products each
+# (compensated three-way split operands), so the BF16 peak divided by 6
+PEAKS_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "bf16x6": 2500.0 / 6}
 HBM_GBS = 8000.0
 
 
@@ -42,7 +45,7 @@ def log(*a):
 
 
 def kernel_dtype(name: str) -> str:
-    for k in ("bf16", "f64", "f32"):
+    for k in ("bf16x6", "bf16", "f64", "f32"):
         if "_" + k in name:
             return k
     return "f32"
@@ -180,7 +183,7 @@ def main():
         ev[0].record(s)
         api.hess_opg(model, X, Y, "bf16", out=G, ctx=ctx)
         ev[1].record(s)
-        api.hess_exact(model, X, Y, "f32", out=H, ctx=ctx)
+        api.hess_exact(model, X, Y, "f32_split", out=H, ctx=ctx)
         ev[2].record(s)
         lam, Q, info, st = api.hess_topk_eig(None, None, None, K, eopts, ctx=ctx)
         ev[3].record(s)
@@ -244,10 +247,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (H, HVP) + bf16->f32 (OPG) + f64 (QR, Rayleigh-Ritz, query)",
+        "dtype": "f32 operands via split-bf16 MFMA products, f32 accumulate (H) + f32 (HVP, eigensolver operator) "
+                 "+ bf16->f32 (OPG) + f64 (re-orthogonalisation, Rayleigh-Ritz, query)",
         "data": "synthetic",
         "config": {"workload": w.name, "T": w.T, "N": w.N, "P": P,
-                   "step": "OPG (BF16 MFMA, FP32 acc) + exact H (FP32 MFMA), P x P each; top-100 eigenpairs "
+                   "step": "OPG (BF16 MFMA, FP32 acc) + exact H (FP32, split-BF16 MFMA products), P x P each; top-100 eigenpairs "
                            "of H (block Lanczos, block 16, FP32 operator, FP64 RR, tol 1e-5); 512 dense HVPs "
                            "(FP32); damped query for 1024 inputs (FP64); inputs resident in HBM"},
         "phases_ms": {k: round(v, 3) for k, v in ph.items()},
@@ -311,9 +315,17 @@ def main():
             log("top-%d %s: %.1f ms %s %s" % (K, tag, out["topk"]["ms_" + tag], inf, st))
         rates["dense_B%d_call" % B] = out["hvps_per_s"].pop("dense_B%d" % B)
         out["hvps_per_s"].update(rates)
+        # the same H with plain FP32 MFMA products, one call
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.hess_exact(model, X, Y, "f32", out=H, ctx=ctx)
+        torch.cuda.synchronize()
+        out["exact_h_f32_mfma_ms"] = round(1e3 * (time.perf_counter() - t0), 1)
         # sustained rate of the dominant kernel's MFMA instruction in a register-only stream
-        stream_kind = {"f32": "f32_16x16x4", "bf16": "bf16_16x16x32", "f64": "f64_16x16x4"}[roofline["dtype"]]
-        srate = ctx.mfma_stream_rate(stream_kind)
+        # (per FP32 product for the split form: six BF16 products each)
+        stream_kind = {"f32": "f32_16x16x4", "bf16": "bf16_16x16x32", "bf16x6": "bf16_16x16x32",
+                       "f64": "f64_16x16x4"}[roofline["dtype"]]
+        srate = ctx.mfma_stream_rate(stream_kind) / (6.0 if roofline["dtype"] == "bf16x6" else 1.0)
         out["roofline"]["mfma_stream_tflops"] = round(srate, 2)
         out["roofline"]["frac_of_stream"] = round(roofline["achieved"] / srate, 4)
         log("hvps/s %s; MFMA stream %s %.1f TFLOP/s" % (json.dumps({k: round(v, 1) for k, v in out["hvps_per_s"].items()}),

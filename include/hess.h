@@ -61,8 +61,14 @@ typedef enum { HESS_F64 = 0, HESS_F32 = 1 } hess_dtype;
  *   HESS_P_F64   FP64 MFMA, FP64 output
  *   HESS_P_F32   FP32 MFMA with FP32 accumulation, FP32 output
  *   HESS_P_BF16  OPG only: per-example gradient tiles rounded to BF16 (round to
- *                nearest even), BF16 MFMA with FP32 accumulation, FP32 output */
-typedef enum { HESS_P_F64 = 0, HESS_P_F32 = 1, HESS_P_BF16 = 2 } hess_prec;
+ *                nearest even), BF16 MFMA with FP32 accumulation, FP32 output
+ *   HESS_P_F32_SPLIT  hess_exact and hess_opg: as HESS_P_F32 (FP32 operands, FP32
+ *                accumulation and output), but the FP32 contractions take each product
+ *                from BF16 MFMAs on compensated three-way splits of the FP32 operands
+ *                (x = h + m + l, each part the round-to-nearest-even BF16 of the remainder;
+ *                products h h, h m, m h, h l, l h, m m), which keeps FP32-level error.
+ *                Other entry points treat it as HESS_P_F32 where they accept HESS_P_F32. */
+typedef enum { HESS_P_F64 = 0, HESS_P_F32 = 1, HESS_P_BF16 = 2, HESS_P_F32_SPLIT = 3 } hess_prec;
 
 typedef struct {
   int32_t L;               /* number of layers including the input layer, L >= 2 */
@@ -107,8 +113,9 @@ const char* hess_last_error(const hess_ctx* ctx);
  * HESS_OPT_AUTOTUNE (default 0): the first FP32 contraction launch and the first BF16
  * Gram product of each shape class times every tile configuration of that kernel
  * (example chunk and LDS stage count) on a bounded sample of its tiles, synchronising
- * the stream, and caches the fastest for the context (contractions that accumulate into
- * their output keep the default); all configurations give bitwise identical results.
+ * the stream, and caches the choice for the context: the default configuration unless
+ * another is at least 3% faster on the sample (contractions that accumulate into their
+ * output keep the default); all configurations give bitwise identical results.
  * hess_autotune_report lists the decisions. */
 typedef enum {
   HESS_OPT_CHECK_INPUTS = 0, HESS_OPT_HBM_BUDGET = 1, HESS_OPT_FAULT_AFTER = 2, HESS_OPT_PROFILE = 3,

@@ -39,6 +39,7 @@ struct Arena {
 struct Exec {
   hipStream_t stream;
   hess_ctx* ctx;
+  bool split = false;  // FP32 contractions take their products from split-BF16 MFMAs
 };
 
 bool launch_ok(Exec& ex);   // fault-injection hook + hipGetLastError check

@@ -315,10 +315,12 @@ __device__ __forceinline__ void krg_tile(const KrgArgs<T, TOut>& a, int64_t t, i
 // ---------------------------------------------------------------------------
 constexpr int DLD = 132;
 
-// chunk of examples per stage and number of LDS stages (prefetch distance NST - 1)
-template <int KC_, int NST_>
+// chunk of examples per stage and number of LDS stages (prefetch distance NST - 1);
+// SPLIT: FP32 products from BF16 MFMAs on three-way split operands (chunks of 32)
+template <int KC_, int NST_, bool SPLIT_ = false>
 struct DmaCfg {
   static constexpr int KC = KC_, NST = NST_;
+  static constexpr bool SPLIT = SPLIT_;
 };
 using DmaDefault = DmaCfg<16, 2>;  // measured: (16, 2) 131, (16, 3) 129, (32, 2) 126 TFLOP/s
 
@@ -339,6 +341,34 @@ struct DmaSmem {
 };
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// x = h + m + l with h, m, l BF16: h = RNE(x), m = RNE(x - h), l = RNE(x - h - m); both
+// differences are exact in FP32, so |x - h - m - l| <= 2^-24 |x| (up to underflow).
+// Two values at a time: one packed conversion per part.
+typedef float f2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split3x2(f2_t x, bf2_t& h, bf2_t& m, bf2_t& l) {
+  h = __builtin_convertvector(x, bf2_t);
+  const f2_t r = x - __builtin_convertvector(h, f2_t);
+  m = __builtin_convertvector(r, bf2_t);
+  l = __builtin_convertvector(r - __builtin_convertvector(m, f2_t), bf2_t);
+}
+// operand parts of the six products, in order m m, l h, h l, m h, h m, h h (smallest first)
+__device__ __forceinline__ const bf8_t& pr_x(int pr, const bf8_t& h, const bf8_t& m, const bf8_t& l) {
+  return pr == 0 ? m : pr == 1 ? l : pr == 2 ? h : pr == 3 ? m : h;
+}
+__device__ __forceinline__ const bf8_t& pr_y(int pr, const bf8_t& h, const bf8_t& m, const bf8_t& l) {
+  return pr == 0 ? m : pr == 1 ? h : pr == 2 ? l : pr == 3 ? h : pr == 4 ? m : h;
+}
+// the three BF16 parts of 8 values v[0..7] as MFMA operands
+__device__ __forceinline__ void split3x8(const float (&v)[8], bf8_t& h, bf8_t& m, bf8_t& l) {
+  bf2_t hh[4], mm[4], ll[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) split3x2(f2_t{v[2 * p], v[2 * p + 1]}, hh[p], mm[p], ll[p]);
+  h = bf8_t{hh[0][0], hh[0][1], hh[1][0], hh[1][1], hh[2][0], hh[2][1], hh[3][0], hh[3][1]};
+  m = bf8_t{mm[0][0], mm[0][1], mm[1][0], mm[1][1], mm[2][0], mm[2][1], mm[3][0], mm[3][1]};
+  l = bf8_t{ll[0][0], ll[0][1], ll[1][0], ll[1][1], ll[2][0], ll[2][1], ll[3][0], ll[3][1]};
+}
 
 __device__ __forceinline__ int64_t mn64(int64_t x, int64_t y) { return x < y ? x : y; }
 
@@ -513,6 +543,42 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
       const float* Bs = As + SM::AB;
       const float* W = As + 2 * SM::AB;
       const int kv = (int)mn64(DKC, a.N - kc * DKC);
+      if constexpr (ONE && C::SPLIT) {
+        // the chunk's 32 examples at once: this lane supplies k = 8 q + s (s = 0..7) of
+        // its four rows (A, weighted) and four columns (B); each value is split in three
+        // BF16 parts and the products h h, h m, m h, h l, l h, m m of A and B parts are
+        // accumulated in FP32 by v_mfma_f32_16x16x32_bf16 (same output layout as the
+        // FP32 instruction).  The dropped m l, l m, l l terms are below 2^-32 relative.
+        static_assert(DKC == 32, "split products take chunks of 32 examples");
+        const f4_t wlo = wt4(W, ur_lane, uc_lane, 4 * q, kv), whi = wt4(W, ur_lane, uc_lane, 4 * q + 4, kv);
+        float av[4][8], bv[4][8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int k = 8 * q + s;
+          const float ws = s < 4 ? wlo[s] : whi[s - 4];
+          const f4_t a4 = *(const f4_t*)&As[k * DLD + wr * 64 + 4 * row16] * ws;
+          const f4_t b4 = *(const f4_t*)&Bs[k * DLD + wc * 64 + 4 * row16];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            av[i][s] = a4[i];
+            bv[i][s] = b4[i];
+          }
+        }
+        bf8_t bh[4], bm[4], bl[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) split3x8(bv[j], bh[j], bm[j], bl[j]);
+        // row block by row block; consecutive MFMAs on one accumulator are 4 apart
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          bf8_t ah, am, al;
+          split3x8(av[i], ah, am, al);
+#pragma unroll
+          for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mma_bf16(pr_x(pr, ah, am, al), pr_y(pr, bh[j], bm[j], bl[j]), acc[i][j]);
+        }
+        continue;
+      }
 #pragma unroll
       for (int k0 = 0; k0 < DKC; k0 += 16) {
         if (ONE) {
@@ -753,12 +819,14 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
         };
         if (cfg == 1) run(DmaCfg<16, 3>());
         else if (cfg == 2) run(DmaCfg<32, 2>());
+        else if (cfg == 3) run(DmaCfg<32, 2, true>());
         else run(DmaDefault());
       };
-      int cfg = variant == 5 ? 2 : (variant == 6 ? 1 : 0);
+      int cfg = variant == 5 ? 2 : (variant == 6 ? 1 : (variant == 7 || ex.split ? 3 : 0));
+      if (cfg == 3 && label.compare(0, 7, "krg_f32") == 0) label = "krg_bf16x6" + label.substr(7);
       // Probes write into the output, which the full launch then overwrites; a launch that
       // accumulates into its output keeps the default configuration.
-      if (variant == 0 && ex.ctx->autotune && !a.accumulate && launch_ok(ex)) {
+      if (variant == 0 && !ex.split && ex.ctx->autotune && !a.accumulate && launch_ok(ex)) {
         // probe on the first two device rounds of tiles (all of them if fewer)
         static const int64_t slots = [] {
           int dev = 0, cus = 256;

@@ -15,7 +15,7 @@ from paper_1905_05559_amd import workloads
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 2e-2}
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 2e-2, "f32_split": 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -61,7 +61,7 @@ SMALL = [
 
 
 @pytest.mark.parametrize("T,acts,N,seed", SMALL)
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
 def test_small_exact_and_opg(api, T, acts, N, seed, prec):
     print("case T=%s acts=%s N=%d seed=%d prec=%s" % (T, acts, N, seed, prec), flush=True)
     w = workloads.mlp_gaussian(T, acts, N, seed, dtype="float64" if prec == "f64" else "float32")
@@ -96,7 +96,7 @@ def sig64():
 SIG64_BLOCKS = [(0, 64), (4032, 4096), (4096, 4170), (4746, 4810)]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32_split"])
 def test_sigmoid64_opg_full(api, sig64, prec):
     w, om, Xo, Yo, Gref = sig64
     model, X, Y = to_dev(api, w, "float64" if prec == "f64" else "float32")
@@ -108,7 +108,7 @@ def test_sigmoid64_opg_full(api, sig64, prec):
     assert report("sigmoid64 OPG %s" % prec, G, Gref) <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
 def test_sigmoid64_exact_sampled_blocks(api, sig64, prec):
     w, om, Xo, Yo, _ = sig64
     td = torch.float64 if prec == "f64" else torch.float32
@@ -137,7 +137,7 @@ def test_sigmoid64_reduced_n_exact_full(api):
         assert report("sigmoid64 N=600 H %s" % prec, H, Href) <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
 def test_wide_units_exact_and_opg(api, prec):
     # 301 inputs per hidden unit: tiles touch at most two units per side; N = 300 leaves a
     # ragged last chunk of examples
@@ -168,19 +168,20 @@ def test_mnist_shaped_full_size_sampled_columns(api):
     model = api.MLP.from_workload(w, dtype=torch.float32)
     X = torch.from_numpy(w.X).to("cuda")
     Y = torch.from_numpy(w.Y).to("cuda")
-    H = api.hess_exact(model, X, Y, "f32")
-    rowsH = {b: H[b[0]:b[1], :].double().cpu().numpy() for b in MNIST_BLOCKS}
-    colsH = {b: H[:, b[0]:b[1]].double().cpu().numpy() for b in MNIST_BLOCKS[:2]}
-    del H
-    torch.cuda.empty_cache()
-    for b in MNIST_BLOCKS[:2]:
-        assert np.array_equal(rowsH[b], colsH[b].T)
-    for b in MNIST_BLOCKS[:3]:
-        ref = mlp.hessian_cols(om, Xo, Yo, b[0], b[1])
-        assert report("mnist H[:, %d:%d] f32" % b, rowsH[b].T, ref) <= TOL["f32"]
+    refs = {b: mlp.hessian_cols(om, Xo, Yo, b[0], b[1]) for b in MNIST_BLOCKS[:3]}
+    for prec in ("f32", "f32_split"):
+        H = api.hess_exact(model, X, Y, prec)
+        rowsH = {b: H[b[0]:b[1], :].double().cpu().numpy() for b in MNIST_BLOCKS}
+        colsH = {b: H[:, b[0]:b[1]].double().cpu().numpy() for b in MNIST_BLOCKS[:2]}
+        del H
+        torch.cuda.empty_cache()
+        for b in MNIST_BLOCKS[:2]:
+            assert np.array_equal(rowsH[b], colsH[b].T)
+        for b in MNIST_BLOCKS[:3]:
+            assert report("mnist H[:, %d:%d] %s" % (b + (prec,)), rowsH[b].T, refs[b]) <= TOL[prec]
     cols = [c for b in MNIST_BLOCKS for c in range(b[0], b[1])]
     Gref = mlp.opg_cols(om, Xo, Yo, cols)
-    for prec in ("f32", "bf16"):
+    for prec in ("f32", "bf16", "f32_split"):
         G = api.hess_opg(model, X, Y, prec)
         Gc = G[:, cols].double().cpu().numpy()
         del G
