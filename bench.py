@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mnist", choices=["mnist", "sigmoid64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--h-prec", default="f32_split", choices=["f32_split", "f32"],
+                    help="products of the exact-H contractions: split-BF16 MFMA (default) or FP32 MFMA")
     ap.add_argument("--no-side", action="store_true",
                     help="skip the measurements after the timed steps (HVP block sweep, other eigensolver "
                          "configurations, MFMA stream rate), e.g. for a profile of the steps alone")
@@ -183,7 +185,7 @@ def main():
         ev[0].record(s)
         api.hess_opg(model, X, Y, "bf16", out=G, ctx=ctx)
         ev[1].record(s)
-        api.hess_exact(model, X, Y, "f32_split", out=H, ctx=ctx)
+        api.hess_exact(model, X, Y, args.h_prec, out=H, ctx=ctx)
         ev[2].record(s)
         lam, Q, info, st = api.hess_topk_eig(None, None, None, K, eopts, ctx=ctx)
         ev[3].record(s)
