@@ -2,7 +2,7 @@
 // b x P) and a dense symmetric FP32 matrix M (P x P), the products of the block
 // Lanczos eigensolver on a formed H or OPG (paper, Sec. 5.3).  With b this small the
 // product reads M once (4 P^2 bytes) for 2 b P^2 flops, so it is bound by HBM for
-// b <~ 32: the tile is SR (= 32 or 64) rows x 256 columns of M, streamed through LDS in
+// b <~ 32: the tile is SR (= 16, 32 or 64) rows x 256 columns of M, streamed through LDS in
 // chunks of 16 rows of M, double-buffered, one barrier per chunk.  The contraction over
 // P is split into slices (one workgroup per column block and slice); partial products
 // go to part[slice][b][P] and are summed in slice order by the caller.
@@ -30,7 +30,7 @@ struct SkinnyLds {
 };
 
 template <int SR>
-__global__ __launch_bounds__(256, SR == 32 ? 4 : 2) void k_skinny_f32(const float* __restrict__ Q, int64_t ldq, int64_t b,
+__global__ __launch_bounds__(256, SR <= 32 ? 4 : 2) void k_skinny_f32(const float* __restrict__ Q, int64_t ldq, int64_t b,
                                                        int64_t P, const float* __restrict__ M, int64_t ldm,
                                                        float* __restrict__ part, int64_t kslice, int64_t ncb,
                                                        int64_t ntiles) {
@@ -185,7 +185,10 @@ void skinny_apply_f32(Exec& ex, const float* Q, int64_t b, int64_t P, const floa
   const int64_t ncb = (P + SC - 1) / SC, ntiles = ncb * ks;
   const int tok = prof_begin(ex, "dense_apply_skinny_f32", 2.0 * b * (double)P * P,
                              4.0 * (double)P * P + 4.0 * b * P * (1 + ks));
-  if (b <= 32) {
+  if (b <= 16) {
+    hipLaunchKernelGGL(k_skinny_f32<16>, dim3((unsigned)xcd_grid(ntiles), 1), dim3(256), 0, ex.stream, Q, P, b, P, M,
+                       P, part, kslice, ncb, ntiles);
+  } else if (b <= 32) {
     hipLaunchKernelGGL(k_skinny_f32<32>, dim3((unsigned)xcd_grid(ntiles), 1), dim3(256), 0, ex.stream, Q, P, b, P, M,
                        P, part, kslice, ncb, ntiles);
   } else {
