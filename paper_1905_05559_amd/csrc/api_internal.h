@@ -74,6 +74,7 @@ struct HvpBufs {
   std::vector<T*> abar, delta, D1, CE, W, Vbar, HVbar, RZ, RA, RD;
   T* Yhat = nullptr;
   T* S = nullptr;
+  T* Tacc = nullptr;  // T_l x (B T_{l-1}) partial of the delta^T R{A} accumulation
   int64_t Nc = 0, Bmax = 0;
 };
 template <typename T>

@@ -51,6 +51,15 @@ __global__ void k_unpack_hv(const T* HVbar, int64_t B, int64_t P, int64_t offW, 
   }
 }
 
+// HVbar_b[i][j] += Tacc[i][b T_in + j] for the weight columns j < T_in of every direction b
+template <typename T>
+__global__ void k_add_wcols(const T* Tacc, int64_t B, int64_t Tl, int64_t Tin, T* HVbar) {
+  GRID_STRIDE(e, Tl * B * Tin) {
+    const int64_t i = e / (B * Tin), r = e % (B * Tin), b = r / Tin, j = r % Tin;
+    HVbar[(b * Tl + i) * (Tin + 1) + j] += Tacc[e];
+  }
+}
+
 // RA[n][b][t] = D1[n][t] * RZ[n][b][t]
 template <typename T>
 __global__ void k_ra(const T* RZ, const T* D1, int64_t Nc, int64_t B, int64_t Tl, T* RA) {
@@ -168,6 +177,9 @@ size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBuf
     if (l < L) h.RA[l] = ar.take<T>(h.Nc * B * m.T[l - 1]);
   }
   h.S = ar.take<T>(h.Nc * B);
+  int64_t tacc = 0;
+  for (int l = 3; l <= L; ++l) tacc = std::max<int64_t>(tacc, m.T[l - 1] * B * m.T[l - 2]);
+  h.Tacc = tacc > 0 ? ar.take<T>(tacc) : nullptr;
   h.Bmax = B;
   return ar.used;
 }
@@ -260,14 +272,13 @@ void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<
       gemm_rm<T>(ex, true, false, B * Tl, Tin + 1, Nc, invN, h.RD[l], B * Tl, h.abar[l - 1] + n0 * p.lda[l - 1],
                  p.lda[l - 1], beta_acc, h.HVbar[l], Tin + 1);
       if (l >= 3) {
-        // + delta^(l)^T R{A^(l-1)}_b, batched over b, into the weight columns
-        GemmArgs<T> g;
-        g.M = Tl; g.N = Tin; g.K = Nc;
-        g.A = h.delta[l] + n0 * Tl; g.sam = 1; g.sak = Tl; g.sab = 0;
-        g.B = h.RA[l - 1]; g.sbk = B * Tin; g.sbn = 1; g.sbb = Tin;
-        g.C = h.HVbar[l]; g.scm = Tin + 1; g.scn = 1; g.scb = Tl * (Tin + 1);
-        g.alpha = invN; g.beta = T(1); g.batch = B;
-        gemm<T>(ex, g);
+        // + delta^(l)^T R{A^(l-1)}_b for all directions at once: R{A} of the chunk is
+        // N_c x (B T_in), so this is one T_l x (B T_in) product (rather than B products of
+        // T_l x T_in, each a mostly empty tile); the result is added into the weight
+        // columns of each direction's block
+        gemm_rm<T>(ex, true, false, Tl, B * Tin, Nc, invN, h.delta[l] + n0 * Tl, Tl, h.RA[l - 1], B * Tin, T(0),
+                   h.Tacc, B * Tin);
+        LAUNCH(k_add_wcols<T>, Tl * B * Tin, h.Tacc, B, Tl, Tin, h.HVbar[l]);
       }
     }
   }

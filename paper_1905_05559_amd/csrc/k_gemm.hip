@@ -4,7 +4,8 @@
 //
 // Tiling: 256 threads = 4 wavefronts in a 2 x 2 grid; each wavefront owns a
 // (BM/2) x (BN/2) sub-tile made of 16 x 16 MFMA blocks.  The K dimension is staged
-// through LDS in chunks of 16, stored k-contiguous per row so that each lane picks
+// through two LDS stages in chunks of 16 (one barrier per chunk), stored k-contiguous
+// per row so that each lane picks
 // up its four k values of a chunk with one vector read; the sum over k inside a
 // chunk is permuted (lane group q takes k = 4q..4q+3 over the four MFMA steps),
 // which is legal because A and B use the same permutation.
@@ -17,12 +18,29 @@ namespace {
 constexpr int KC = 16;
 constexpr int KP = KC + 4;  // padded row length in LDS (bank spread)
 
-template <typename T, int BM, int BN>
+// Raw buffer load of one element; an offset at or past num_records reads 0.
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+// BUF: operands read through buffer resources (the host checks that every element of A
+// and B lies within 2^31 bytes of its batch base), so an element outside M x K (N x K)
+// gets an out-of-range offset and reads 0 with no branch; a guarded plain load compiles
+// to a branch and a full wait per element.
+template <typename T, int BM, int BN, bool BUF>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g, int64_t tiles_n, int64_t ntiles) {
   using Op = MfmaOp<T>;
   using acc_t = typename Op::acc_t;
-  __shared__ __attribute__((aligned(16))) T As[BM * KP];
-  __shared__ __attribute__((aligned(16))) T Bs[BN * KP];
+  // two LDS stages: chunk c + 1 is stored into the other stage while chunk c is multiplied
+  __shared__ __attribute__((aligned(16))) T As[2][BM * KP];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BN * KP];
 
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x, ntiles);
   if (tile < 0) return;
@@ -47,34 +65,51 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g, int64_t tiles_
   auto idx_b = [&](int e, int& n, int& k) {
     if (b_kfast) { n = e / KC; k = e % KC; } else { k = e / BN; n = e % BN; }
   };
+  __amdgpu_buffer_rsrc_t rsa, rsb;
+  if constexpr (BUF) {
+    rsa = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(A), (short)0, 0x7fffffff, 0x00020000);
+    rsb = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(B), (short)0, 0x7fffffff, 0x00020000);
+  }
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < AE; ++i) {
       int m, k;
       idx_a(tid + i * 256, m, k);
       const int64_t gm = m0 + m, gk = k0 + k;
-      ra[i] = (gm < g.M && gk < g.K) ? A[gm * g.sam + gk * g.sak] : T(0);
+      if constexpr (BUF) {
+        const uint32_t off = (gm < g.M && gk < g.K) ? (uint32_t)((gm * g.sam + gk * g.sak) * (int64_t)sizeof(T))
+                                                    : 0xfffffff0u;
+        ra[i] = buf_load<T>(rsa, off);
+      } else {
+        ra[i] = (gm < g.M && gk < g.K) ? A[gm * g.sam + gk * g.sak] : T(0);
+      }
     }
 #pragma unroll
     for (int i = 0; i < BE; ++i) {
       int n, k;
       idx_b(tid + i * 256, n, k);
       const int64_t gn = n0 + n, gk = k0 + k;
-      rb[i] = (gn < g.N && gk < g.K) ? B[gk * g.sbk + gn * g.sbn] : T(0);
+      if constexpr (BUF) {
+        const uint32_t off = (gn < g.N && gk < g.K) ? (uint32_t)((gk * g.sbk + gn * g.sbn) * (int64_t)sizeof(T))
+                                                    : 0xfffffff0u;
+        rb[i] = buf_load<T>(rsb, off);
+      } else {
+        rb[i] = (gn < g.N && gk < g.K) ? B[gk * g.sbk + gn * g.sbn] : T(0);
+      }
     }
   };
-  auto store = [&]() {
+  auto store = [&](int st) {
 #pragma unroll
     for (int i = 0; i < AE; ++i) {
       int m, k;
       idx_a(tid + i * 256, m, k);
-      As[m * KP + k] = ra[i];
+      As[st][m * KP + k] = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < BE; ++i) {
       int n, k;
       idx_b(tid + i * 256, n, k);
-      Bs[n * KP + k] = rb[i];
+      Bs[st][n * KP + k] = rb[i];
     }
   };
 
@@ -87,30 +122,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g, int64_t tiles_
   const int row = lane & 15, q = lane >> 4;
   const int64_t nk = (g.K + KC - 1) / KC;
   load(0);
-  store();
+  store(0);
   __syncthreads();
   for (int64_t kc = 0; kc < nk; ++kc) {
+    const int st = (int)(kc & 1);
     if (kc + 1 < nk) load((kc + 1) * KC);
     T a[RB][4], b[CB][4];
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) a[i][s] = As[(wr * WM + i * 16 + row) * KP + 4 * q + s];
+      for (int s = 0; s < 4; ++s) a[i][s] = As[st][(wr * WM + i * 16 + row) * KP + 4 * q + s];
 #pragma unroll
     for (int j = 0; j < CB; ++j)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) b[j][s] = Bs[(wc * WN + j * 16 + row) * KP + 4 * q + s];
+      for (int s = 0; s < 4; ++s) b[j][s] = Bs[st][(wc * WN + j * 16 + row) * KP + 4 * q + s];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int j = 0; j < CB; ++j) acc[i][j] = Op::mma(a[i][s], b[j][s], acc[i][j]);
+    // the other stage was last read in the previous chunk, before the barrier below
+    if (kc + 1 < nk) store(st ^ 1);
     __syncthreads();
-    if (kc + 1 < nk) {
-      store();
-      __syncthreads();
-    }
   }
 
 #pragma unroll
@@ -129,6 +163,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g, int64_t tiles_
       }
 }
 
+// Byte extent of a strided operand (rows x k) from its batch base; strides are >= 0.
+inline int64_t extent_bytes(int64_t rows, int64_t k, int64_t s_row, int64_t s_k, size_t elem) {
+  return ((rows - 1) * s_row + (k - 1) * s_k + 1) * (int64_t)elem;
+}
+
 template <typename T, int BM, int BN>
 void launch(Exec& ex, const GemmArgs<T>& g) {
   const int64_t tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
@@ -138,7 +177,14 @@ void launch(Exec& ex, const GemmArgs<T>& g) {
   const double b = (double)g.batch;
   const int tok = prof_begin(ex, sizeof(T) == 8 ? "gemm_f64" : "gemm_f32", 2.0 * g.M * g.N * g.K * b,
                              (double)(g.M * g.K + g.K * g.N + g.M * g.N) * sizeof(T) * b);
-  hipLaunchKernelGGL((gemm_kernel<T, BM, BN>), grid, dim3(256), 0, ex.stream, g, tn, nt);
+  const int64_t lim = 0x7fffff00;
+  const bool buf = g.sam >= 0 && g.sak >= 0 && g.sbk >= 0 && g.sbn >= 0 &&
+                   extent_bytes(g.M, g.K, g.sam, g.sak, sizeof(T)) < lim &&
+                   extent_bytes(g.N, g.K, g.sbn, g.sbk, sizeof(T)) < lim;
+  if (buf)
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, true>), grid, dim3(256), 0, ex.stream, g, tn, nt);
+  else
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, false>), grid, dim3(256), 0, ex.stream, g, tn, nt);
   prof_end(ex, tok);
 }
 
