@@ -11,7 +11,7 @@ resident in HBM:
     MFMAs on compensated three-way splits of the operands (FP32-level error)
   * the 100 algebraically largest eigenpairs of H by block Lanczos (blocks of 16, FP32
     operator, FP64 re-orthogonalisation and Rayleigh-Ritz, tol 1e-5)
-  * 512 dense Hessian-vector products (matrix-free R-operator, FP32)
+  * 512 dense Hessian-vector products (matrix-free R-operator, FP32 with split-BF16 GEMM products)
   * the damped curvature query for 1024 inputs against those eigenpairs (FP64)
 value = 2 P^2 / step time  ("exact-H+OPG P^2-entries/s": P^2 entries of each matrix),
 with the per-phase times, HVPs/s and query rates reported beside it.
@@ -124,7 +124,7 @@ def main():
     ap.add_argument("--workload", default="mnist", choices=["mnist", "sigmoid64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--h-prec", default="f32_split", choices=["f32_split", "f32"],
-                    help="products of the exact-H contractions: split-BF16 MFMA (default) or FP32 MFMA")
+                    help="products of the exact-H contractions and the HVP GEMMs: split-BF16 MFMA (default) or FP32 MFMA")
     ap.add_argument("--no-side", action="store_true",
                     help="skip the measurements after the timed steps (HVP block sweep, other eigensolver "
                          "configurations, MFMA stream rate), e.g. for a profile of the steps alone")
@@ -189,7 +189,7 @@ def main():
         ev[2].record(s)
         lam, Q, info, st = api.hess_topk_eig(None, None, None, K, eopts, ctx=ctx)
         ev[3].record(s)
-        api.hess_hvp(model, X, Y, V, "f32", out=HV, ctx=ctx)
+        api.hess_hvp(model, X, Y, V, args.h_prec, out=HV, ctx=ctx)
         ev[4].record(s)
         delta = max(1e-3, 1e-3 - float(lam.min()))  # keeps lambda_k + delta > 0
         api.hess_predvar(model, lam, Q, delta, Xq, ctx=ctx)
@@ -249,13 +249,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 operands via split-bf16 MFMA products, f32 accumulate (H) + f32 (HVP, eigensolver operator) "
+        "dtype": "f32 operands via split-bf16 MFMA products, f32 accumulate (H, HVP) + f32 (eigensolver operator) "
                  "+ bf16->f32 (OPG) + f64 (re-orthogonalisation, Rayleigh-Ritz, query)",
         "data": "synthetic",
         "config": {"workload": w.name, "T": w.T, "N": w.N, "P": P,
                    "step": "OPG (BF16 MFMA, FP32 acc) + exact H (FP32, split-BF16 MFMA products), P x P each; top-100 eigenpairs "
                            "of H (block Lanczos, block 16, FP32 operator, FP64 RR, tol 1e-5); 512 dense HVPs "
-                           "(FP32); damped query for 1024 inputs (FP64); inputs resident in HBM"},
+                           "(FP32, split-BF16 GEMM products); damped query for 1024 inputs (FP64); inputs resident in HBM"},
         "phases_ms": {k: round(v, 3) for k, v in ph.items()},
         "hvps_per_s": {"dense_B512": B / (ph["hvp"] / 1e3), "basis_via_exact_H": P / (ph["exact_H"] / 1e3)},
         "opg_p2_entries_per_s": P * P / (ph["opg"] / 1e3),
@@ -286,14 +286,15 @@ def main():
         return sorted(times)[1] / 1e3
 
     if not args.no_side:
-        op = api.HvpOperator(model, X, Y, "f32", max_B=B, ctx=ctx)
+        op = api.HvpOperator(model, X, Y, args.h_prec, max_B=B, ctx=ctx)
         rates = {}
         for Bs in (1, 8, 64, 512):
             Vb = V[:Bs].contiguous()
             HVb = torch.empty_like(Vb)
             rates["dense_B%d" % Bs] = Bs / timed(lambda: op.apply(Vb, out=HVb))
             if Bs < B:
-                rates["dense_B%d_call" % Bs] = Bs / timed(lambda: api.hess_hvp(model, X, Y, Vb, "f32", out=HVb, ctx=ctx))
+                rates["dense_B%d_call" % Bs] = Bs / timed(lambda: api.hess_hvp(model, X, Y, Vb, args.h_prec, out=HVb,
+                                                                               ctx=ctx))
         op.close()
         # the same top-100 problem by the other eigensolver configurations (outside the timed steps)
         for tag, oo in (("subspace_iteration", api.eig_opts(which="H", source="dense", M=H, tol=1e-5, seed=1,

@@ -959,7 +959,7 @@ static hess_status topk_validate(hess_ctx* ctx, const hess_mlp* mlp, const hess_
   } else {
     if ((s = validate_mlp(ctx, mlp, t.m, need_ptrs)) != HESS_OK) return s;
     if ((s = validate_data(ctx, d, need_ptrs)) != HESS_OK) return s;
-    if (o->prec != HESS_P_F64 && o->prec != HESS_P_F32)
+    if (o->prec != HESS_P_F64 && o->prec != HESS_P_F32 && o->prec != HESS_P_F32_SPLIT)
       return fail(ctx, HESS_E_UNSUPPORTED, "matrix-free operator: F64 or F32");
     t.has_model = true;
     t.N = d->N;
@@ -1039,6 +1039,8 @@ extern "C" hess_status hess_topk_eig(hess_ctx* ctx, const hess_mlp* mlp, const h
       hvp_setup<float>(ex, t.m, t.N, e.p, e.hf);
   }
   set_lds_limits();
+  // matrix-free FP32 operator with split-BF16 products in its GEMMs
+  ex.split = t.source == 0 && t.prec == HESS_P_F32_SPLIT;
   EigRun r{&ex, &e, t.has_model ? &t.m : nullptr, t.N, t.source, t.which, t.prec, t.Mdtype,
            t.source == 1 ? opts->M : nullptr};
   GraphCache graphs;  // destroyed after the call has synchronised (finish)

@@ -441,14 +441,16 @@ size_t ws_hvp(const Model& m, int64_t N, int prec, int64_t B) {
 }  // namespace
 
 hess_status exact_cols_workspace(hess_ctx* ctx, const Model& m, int64_t N, int prec, int64_t ncols, size_t* bytes) {
-  if (prec != HESS_P_F64 && prec != HESS_P_F32) return fail(ctx, HESS_E_UNSUPPORTED, "H columns: F64 or F32 only");
+  if (prec != HESS_P_F64 && prec != HESS_P_F32 && prec != HESS_P_F32_SPLIT)
+    return fail(ctx, HESS_E_UNSUPPORTED, "H columns: F64, F32 or F32_SPLIT only");
   if (ncols < 1) return fail(ctx, HESS_E_SHAPE, "ncols must be positive");
   *bytes = ws_exact_cols(m, N, prec, ncols);
   return HESS_OK;
 }
 
 hess_status hvp_workspace(hess_ctx* ctx, const Model& m, int64_t N, int prec, int64_t B, size_t* bytes) {
-  if (prec != HESS_P_F64 && prec != HESS_P_F32) return fail(ctx, HESS_E_UNSUPPORTED, "HVP: F64 or F32 only");
+  if (prec != HESS_P_F64 && prec != HESS_P_F32 && prec != HESS_P_F32_SPLIT)
+    return fail(ctx, HESS_E_UNSUPPORTED, "HVP: F64, F32 or F32_SPLIT only");
   if (B < 1 || B > 65535) return fail(ctx, HESS_E_SHAPE, "B out of range (1..65535)");
   *bytes = ws_hvp(m, N, prec, B);
   return HESS_OK;
@@ -466,9 +468,11 @@ extern "C" hess_status hess_hvp(hess_ctx* ctx, const hess_mlp* mlp, const hess_d
   Model m;
   if ((s = validate_mlp(ctx, mlp, m, true)) != HESS_OK) return s;
   if ((s = validate_data(ctx, d, true)) != HESS_OK) return s;
-  if (prec != HESS_P_F64 && prec != HESS_P_F32) return fail(ctx, HESS_E_UNSUPPORTED, "HVP: F64 or F32 only");
+  if (prec != HESS_P_F64 && prec != HESS_P_F32 && prec != HESS_P_F32_SPLIT)
+    return fail(ctx, HESS_E_UNSUPPORTED, "HVP: F64, F32 or F32_SPLIT only");
   if (B < 1 || B > 65535) return fail(ctx, HESS_E_SHAPE, "B out of range (1..65535)");
   if (!V || !HV) return fail(ctx, HESS_E_ARG, "V or HV is NULL");
+  ex.split = prec == HESS_P_F32_SPLIT;
   const size_t need = ws_hvp(m, d->N, prec, B);
   if ((s = check_ws(ctx, need, ws, ws_bytes, (size_t)B * m.P * (prec == HESS_P_F64 ? 16 : 8))) != HESS_OK)
     return s;
@@ -500,9 +504,11 @@ extern "C" hess_status hess_exact_cols(hess_ctx* ctx, const hess_mlp* mlp, const
   Model m;
   if ((s = validate_mlp(ctx, mlp, m, true)) != HESS_OK) return s;
   if ((s = validate_data(ctx, d, true)) != HESS_OK) return s;
-  if (prec != HESS_P_F64 && prec != HESS_P_F32) return fail(ctx, HESS_E_UNSUPPORTED, "H columns: F64 or F32 only");
+  if (prec != HESS_P_F64 && prec != HESS_P_F32 && prec != HESS_P_F32_SPLIT)
+    return fail(ctx, HESS_E_UNSUPPORTED, "H columns: F64, F32 or F32_SPLIT only");
   if (ncols < 1 || col0 < 0 || col0 > m.P - ncols) return fail(ctx, HESS_E_SHAPE, "column range outside [0, P)");
   if (!Hcols) return fail(ctx, HESS_E_ARG, "Hcols is NULL");
+  ex.split = prec == HESS_P_F32_SPLIT;
   const size_t need = ws_exact_cols(m, d->N, prec, ncols);
   if ((s = check_ws(ctx, need, ws, ws_bytes, (size_t)ncols * m.P * (prec == HESS_P_F64 ? 8 : 4))) != HESS_OK)
     return s;
@@ -545,8 +551,10 @@ extern "C" hess_status hess_hvp_prepare(hess_ctx* ctx, const hess_mlp* mlp, cons
   Model m;
   if ((s = validate_mlp(ctx, mlp, m, true)) != HESS_OK) return s;
   if ((s = validate_data(ctx, d, true)) != HESS_OK) return s;
-  if (prec != HESS_P_F64 && prec != HESS_P_F32) return fail(ctx, HESS_E_UNSUPPORTED, "HVP: F64 or F32 only");
+  if (prec != HESS_P_F64 && prec != HESS_P_F32 && prec != HESS_P_F32_SPLIT)
+    return fail(ctx, HESS_E_UNSUPPORTED, "HVP: F64, F32 or F32_SPLIT only");
   if (max_B < 1 || max_B > 65535) return fail(ctx, HESS_E_SHAPE, "max_B out of range (1..65535)");
+  ex.split = prec == HESS_P_F32_SPLIT;
   const size_t need = ws_hvp(m, d->N, prec, max_B);
   if ((s = check_ws(ctx, need, ws, ws_bytes, 0)) != HESS_OK) return s;
   hess_hvp_op* o = new hess_hvp_op();
@@ -585,6 +593,7 @@ extern "C" hess_status hess_hvp_apply(hess_ctx* ctx, hess_hvp_op* op, int64_t B,
   if (!op) return fail(ctx, HESS_E_ARG, "op is NULL");
   if (B < 1 || B > op->maxB) return fail(ctx, HESS_E_SHAPE, "B outside 1..max_B");
   if (!V || !HV) return fail(ctx, HESS_E_ARG, "V or HV is NULL");
+  ex.split = op->prec == HESS_P_F32_SPLIT;
   if (op->prec == HESS_P_F64)
     hvp_apply<double>(ex, op->m, op->N, B, op->p, op->hd, static_cast<const double*>(V), op->m.P,
                       static_cast<double*>(HV));

@@ -168,6 +168,143 @@ inline int64_t extent_bytes(int64_t rows, int64_t k, int64_t s_row, int64_t s_k,
   return ((rows - 1) * s_row + (k - 1) * s_k + 1) * (int64_t)elem;
 }
 
+// FP32 GEMM with each product taken from BF16 MFMAs on three-way split operands
+// (x = h + m + l by round-to-nearest-even of the remainder; products h h, h m, m h, h l,
+// l h, m m accumulated in FP32 by v_mfma_f32_16x16x32_bf16): chunks of 32 k staged in two
+// LDS stages, k-contiguous per row, so a lane's 8 consecutive k of a row are two 16-byte
+// reads; the same tiling and output layout as the FP32 kernel.
+constexpr int SKC = 32, SKP = SKC + 4;
+
+template <int BM, int BN, bool BUF>
+__global__ __launch_bounds__(256, 2) void gemm_split_kernel(GemmArgs<float> g, int64_t tiles_n, int64_t ntiles) {
+  __shared__ __attribute__((aligned(16))) float As[2][BM * SKP];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BN * SKP];
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x, ntiles);
+  if (tile < 0) return;
+  const int64_t bz = blockIdx.y;
+  const float* A = g.A + bz * g.sab;
+  const float* B = g.B + bz * g.sbb;
+  float* C = g.C + bz * g.scb;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  constexpr int WM = BM / 2, WN = BN / 2, RB = WM / 16, CB = WN / 16;
+  const int64_t m0 = (tile / tiles_n) * BM, n0 = (tile % tiles_n) * BN;
+  constexpr int AE = BM * SKC / 256, BE = BN * SKC / 256;
+  const bool a_kfast = (g.sak == 1), b_kfast = (g.sbk == 1);
+  float ra[AE], rb[BE];
+  __amdgpu_buffer_rsrc_t rsa, rsb;
+  if constexpr (BUF) {
+    rsa = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(A), (short)0, 0x7fffffff, 0x00020000);
+    rsb = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(B), (short)0, 0x7fffffff, 0x00020000);
+  }
+  auto idx_a = [&](int e, int& m, int& k) {
+    if (a_kfast) { m = e / SKC; k = e % SKC; } else { k = e / BM; m = e % BM; }
+  };
+  auto idx_b = [&](int e, int& n, int& k) {
+    if (b_kfast) { n = e / SKC; k = e % SKC; } else { k = e / BN; n = e % BN; }
+  };
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < AE; ++i) {
+      int m, k;
+      idx_a(tid + i * 256, m, k);
+      const int64_t gm = m0 + m, gk = k0 + k;
+      if constexpr (BUF) {
+        const uint32_t off = (gm < g.M && gk < g.K) ? (uint32_t)((gm * g.sam + gk * g.sak) * 4) : 0xfffffff0u;
+        ra[i] = buf_load<float>(rsa, off);
+      } else {
+        ra[i] = (gm < g.M && gk < g.K) ? A[gm * g.sam + gk * g.sak] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BE; ++i) {
+      int n, k;
+      idx_b(tid + i * 256, n, k);
+      const int64_t gn = n0 + n, gk = k0 + k;
+      if constexpr (BUF) {
+        const uint32_t off = (gn < g.N && gk < g.K) ? (uint32_t)((gk * g.sbk + gn * g.sbn) * 4) : 0xfffffff0u;
+        rb[i] = buf_load<float>(rsb, off);
+      } else {
+        rb[i] = (gn < g.N && gk < g.K) ? B[gk * g.sbk + gn * g.sbn] : 0.f;
+      }
+    }
+  };
+  auto store = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < AE; ++i) {
+      int m, k;
+      idx_a(tid + i * 256, m, k);
+      As[st][m * SKP + k] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < BE; ++i) {
+      int n, k;
+      idx_b(tid + i * 256, n, k);
+      Bs[st][n * SKP + k] = rb[i];
+    }
+  };
+  f4_t acc[RB][CB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+  const int row = lane & 15, q = lane >> 4;
+  const int64_t nk = (g.K + SKC - 1) / SKC;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int64_t kc = 0; kc < nk; ++kc) {
+    const int st = (int)(kc & 1);
+    if (kc + 1 < nk) load((kc + 1) * SKC);
+    bf8_t bh[CB], bm[CB], bl[CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      float v[8];
+      const f4_t* p = (const f4_t*)&Bs[st][(wc * WN + j * 16 + row) * SKP + 8 * q];
+      const f4_t v0 = p[0], v1 = p[1];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        v[s] = v0[s];
+        v[4 + s] = v1[s];
+      }
+      split3x8(v, bh[j], bm[j], bl[j]);
+    }
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      float v[8];
+      const f4_t* p = (const f4_t*)&As[st][(wr * WM + i * 16 + row) * SKP + 8 * q];
+      const f4_t v0 = p[0], v1 = p[1];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        v[s] = v0[s];
+        v[4 + s] = v1[s];
+      }
+      bf8_t ah, am, al;
+      split3x8(v, ah, am, al);
+#pragma unroll
+      for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) acc[i][j] = mma_bf16(pr_x(pr, ah, am, al), pr_y(pr, bh[j], bm[j], bl[j]), acc[i][j]);
+    }
+    if (kc + 1 < nk) store(st ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = m0 + wr * WM + i * 16 + 4 * q + v;
+        const int64_t n = n0 + wc * WN + j * 16 + row;
+        if (m < g.M && n < g.N) {
+          float* c = C + m * g.scm + n * g.scn;
+          const float val = g.alpha * acc[i][j][v];
+          *c = (g.beta != 0.f) ? val + g.beta * (*c) : val;
+        }
+      }
+}
+
 template <typename T, int BM, int BN>
 void launch(Exec& ex, const GemmArgs<T>& g) {
   const int64_t tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
@@ -175,12 +312,26 @@ void launch(Exec& ex, const GemmArgs<T>& g) {
   dim3 grid((unsigned)xcd_grid(nt), (unsigned)g.batch);
   if (!launch_ok(ex)) return;
   const double b = (double)g.batch;
-  const int tok = prof_begin(ex, sizeof(T) == 8 ? "gemm_f64" : "gemm_f32", 2.0 * g.M * g.N * g.K * b,
+  const int tok = prof_begin(ex, sizeof(T) == 8 ? "gemm_f64" : (ex.split ? "gemm_bf16x6" : "gemm_f32"),
+                             2.0 * g.M * g.N * g.K * b,
                              (double)(g.M * g.K + g.K * g.N + g.M * g.N) * sizeof(T) * b);
   const int64_t lim = 0x7fffff00;
   const bool buf = g.sam >= 0 && g.sak >= 0 && g.sbk >= 0 && g.sbn >= 0 &&
                    extent_bytes(g.M, g.K, g.sam, g.sak, sizeof(T)) < lim &&
                    extent_bytes(g.N, g.K, g.sbn, g.sbk, sizeof(T)) < lim;
+  if constexpr (sizeof(T) == 4) {
+    if (ex.split) {  // FP32 products from split-BF16 MFMAs: tiles of BM x BN/2 (register budget)
+      constexpr int SBN = BN / 2;
+      const int64_t stn = (g.N + SBN - 1) / SBN, snt = tm * stn;
+      const dim3 sgrid((unsigned)xcd_grid(snt), (unsigned)g.batch);
+      if (buf)
+        hipLaunchKernelGGL((gemm_split_kernel<BM, SBN, true>), sgrid, dim3(256), 0, ex.stream, g, stn, snt);
+      else
+        hipLaunchKernelGGL((gemm_split_kernel<BM, SBN, false>), sgrid, dim3(256), 0, ex.stream, g, stn, snt);
+      prof_end(ex, tok);
+      return;
+    }
+  }
   if (buf)
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, true>), grid, dim3(256), 0, ex.stream, g, tn, nt);
   else

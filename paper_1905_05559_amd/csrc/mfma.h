@@ -38,6 +38,34 @@ __device__ __forceinline__ f4_t mma_bf16(bf8_t a, bf8_t b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// x = h + m + l with h, m, l BF16: h = RNE(x), m = RNE(x - h), l = RNE(x - h - m); both
+// differences are exact in FP32, so |x - h - m - l| <= 2^-24 |x| (up to underflow).
+// Two values at a time: one packed conversion per part.
+typedef float f2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split3x2(f2_t x, bf2_t& h, bf2_t& m, bf2_t& l) {
+  h = __builtin_convertvector(x, bf2_t);
+  const f2_t r = x - __builtin_convertvector(h, f2_t);
+  m = __builtin_convertvector(r, bf2_t);
+  l = __builtin_convertvector(r - __builtin_convertvector(m, f2_t), bf2_t);
+}
+// operand parts of the six products, in order m m, l h, h l, m h, h m, h h (smallest first)
+__device__ __forceinline__ const bf8_t& pr_x(int pr, const bf8_t& h, const bf8_t& m, const bf8_t& l) {
+  return pr == 0 ? m : pr == 1 ? l : pr == 2 ? h : pr == 3 ? m : h;
+}
+__device__ __forceinline__ const bf8_t& pr_y(int pr, const bf8_t& h, const bf8_t& m, const bf8_t& l) {
+  return pr == 0 ? m : pr == 1 ? h : pr == 2 ? l : pr == 3 ? h : pr == 4 ? m : h;
+}
+// the three BF16 parts of 8 values v[0..7] as MFMA operands
+__device__ __forceinline__ void split3x8(const float (&v)[8], bf8_t& h, bf8_t& m, bf8_t& l) {
+  bf2_t hh[4], mm[4], ll[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) split3x2(f2_t{v[2 * p], v[2 * p + 1]}, hh[p], mm[p], ll[p]);
+  h = bf8_t{hh[0][0], hh[0][1], hh[1][0], hh[1][1], hh[2][0], hh[2][1], hh[3][0], hh[3][1]};
+  m = bf8_t{mm[0][0], mm[0][1], mm[1][0], mm[1][1], mm[2][0], mm[2][1], mm[3][0], mm[3][1]};
+  l = bf8_t{ll[0][0], ll[0][1], ll[1][0], ll[1][1], ll[2][0], ll[2][1], ll[3][0], ll[3][1]};
+}
+
 // Map a dispatch-order workgroup id to a logical tile id so that each of the 8
 // XCDs (which receive workgroups round-robin) works on one contiguous range of
 // logical tiles; neighbouring tiles then share operand panels in that XCD's L2.

@@ -287,3 +287,16 @@ def test_lanczos_repeatable_graphs_noconv_and_shapes(api):
         api.hess_topk_eig(model, X, Y, 460, api.eig_opts(which="H", source="matrix_free", prec="f32",
                                                            method="lanczos"))
     assert e.value.name == "HESS_E_SHAPE"
+
+
+def test_lanczos_matrix_free_split_products(api, sig600):
+    # the matrix-free H operator with split-BF16 products in its FP32 GEMMs: same eigenpairs to the
+    # FP32 tolerance
+    w, Href = sig600
+    model = api.MLP.from_workload(w, dtype=torch.float32)
+    X = torch.from_numpy(w.X).cuda()
+    Y = torch.from_numpy(w.Y).cuda()
+    o = api.eig_opts(which="H", source="matrix_free", prec="f32_split", tol=1e-5, seed=4, method="lanczos")
+    lam, Q, info, st = api.hess_topk_eig(model, X, Y, 32, o)
+    print("info", info, st)
+    _check("sigmoid64 N=600 matrix-free H split products top-32 lanczos", lam, Q, Href, 32, 1e-5, 3e-5)

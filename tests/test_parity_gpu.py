@@ -189,7 +189,7 @@ def test_mnist_shaped_full_size_sampled_columns(api):
         assert report("mnist OPG[:, blocks] %s" % prec, Gc, Gref) <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
 def test_exact_cols_match_oracle(api, prec):
     for T, acts, N, seed in (SMALL[2], SMALL[4]):
         print("case exact_cols T=%s N=%d prec=%s" % (T, N, prec), flush=True)
@@ -264,7 +264,7 @@ def test_run_twice_bitwise(api):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("T,acts,N,seed", SMALL)
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
 def test_small_hvp(api, T, acts, N, seed, prec):
     print("hvp case T=%s N=%d prec=%s" % (T, N, prec), flush=True)
     w = workloads.mlp_gaussian(T, acts, N, seed, dtype="float64" if prec == "f64" else "float32")
@@ -278,7 +278,7 @@ def test_small_hvp(api, T, acts, N, seed, prec):
         assert report("HV %s B=%d %s" % (T, B, prec), HV, ref) <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
 def test_prepared_hvp_operator(api, prec):
     # one preparation, several blocks of different sizes; against the oracle and hess_hvp
     T, acts, N, seed = SMALL[4]
@@ -292,7 +292,7 @@ def test_prepared_hvp_operator(api, prec):
         Vn = rng.standard_normal((B, model.P))
         V = torch.from_numpy(Vn).to("cuda", X.dtype)
         HV = op.apply(V).double().cpu().numpy()
-        ref = mlp.hvp(om, Xo, Yo, Vn.astype(np.float32).astype(np.float64) if prec == "f32" else Vn)
+        ref = mlp.hvp(om, Xo, Yo, Vn if prec == "f64" else Vn.astype(np.float32).astype(np.float64))
         assert report("prepared HVP B=%d %s" % (B, prec), HV, ref) <= TOL[prec]
         HV2 = api.hess_hvp(model, X, Y, V, prec).double().cpu().numpy()
         assert report("prepared vs per-call HVP B=%d %s" % (B, prec), HV, HV2) <= TOL[prec]
@@ -302,7 +302,7 @@ def test_prepared_hvp_operator(api, prec):
     op.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
 def test_sigmoid64_hvp(api, sig64, prec):
     w, om, Xo, Yo, _ = sig64
     td = torch.float64 if prec == "f64" else torch.float32
