@@ -250,6 +250,7 @@ __global__ __launch_bounds__(256, 2) void gemm_split_kernel(GemmArgs<float> g, i
     for (int j = 0; j < CB; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
   const int row = lane & 15, q = lane >> 4;
   const int64_t nk = (g.K + SKC - 1) / SKC;
+  const SplitC sc = split_consts();
   load(0);
   store(0);
   __syncthreads();
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(256, 2) void gemm_split_kernel(GemmArgs<float> g, i
         v[s] = v0[s];
         v[4 + s] = v1[s];
       }
-      split3x8(v, bh[j], bm[j], bl[j]);
+      split3x8(v, bh[j], bm[j], bl[j], sc);
     }
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(256, 2) void gemm_split_kernel(GemmArgs<float> g, i
         v[4 + s] = v1[s];
       }
       bf8_t ah, am, al;
-      split3x8(v, ah, am, al);
+      split3x8(v, ah, am, al, sc);
 #pragma unroll
       for (int pr = 0; pr < 6; ++pr)
 #pragma unroll

@@ -523,6 +523,7 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
         // accumulated in FP32 by v_mfma_f32_16x16x32_bf16 (same output layout as the
         // FP32 instruction).  The dropped m l, l m, l l terms are below 2^-32 relative.
         static_assert(DKC == 32, "split products take chunks of 32 examples");
+        const SplitC sc = split_consts();
         const f4_t wlo = wt4(W, ur_lane, uc_lane, 4 * q, kv), whi = wt4(W, ur_lane, uc_lane, 4 * q + 4, kv);
         float av[4][8], bv[4][8];
 #pragma unroll
@@ -539,12 +540,12 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
         }
         bf8_t bh[4], bm[4], bl[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) split3x8(bv[j], bh[j], bm[j], bl[j]);
+        for (int j = 0; j < 4; ++j) split3x8(bv[j], bh[j], bm[j], bl[j], sc);
         // row block by row block; consecutive MFMAs on one accumulator are 4 apart
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           bf8_t ah, am, al;
-          split3x8(av[i], ah, am, al);
+          split3x8(av[i], ah, am, al, sc);
 #pragma unroll
           for (int pr = 0; pr < 6; ++pr)
 #pragma unroll

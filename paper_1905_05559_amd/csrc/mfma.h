@@ -43,11 +43,28 @@ __device__ __forceinline__ f4_t mma_bf16(bf8_t a, bf8_t b, f4_t c) {
 // Two values at a time: one packed conversion per part.
 typedef float f2_t __attribute__((ext_vector_type(2)));
 typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void split3x2(f2_t x, bf2_t& h, bf2_t& m, bf2_t& l) {
+// The residuals x - h are formed by v_dot2c_f32_bf16 as x + h.lo * (-1) + h.hi * 0 (and
+// the mirror for the high half): one instruction per value instead of a widening and a
+// subtraction; the result is exact (x - h is representable).  The two packed multipliers
+// are produced by s_mov in SGPRs (SplitC): folded as an inline constant, the compiler's
+// encoding of the pair (-1, 0) did not multiply by -1.
+struct SplitC {
+  bf2_t nlo, nhi;  // (-1, 0) and (0, -1)
+};
+__device__ __forceinline__ SplitC split_consts() {
+  unsigned lo, hi;
+  asm volatile("s_mov_b32 %0, 0x0000bf80" : "=s"(lo));
+  asm volatile("s_mov_b32 %0, 0xbf800000" : "=s"(hi));
+  return SplitC{__builtin_bit_cast(bf2_t, lo), __builtin_bit_cast(bf2_t, hi)};
+}
+__device__ __forceinline__ void split3x2(f2_t x, bf2_t& h, bf2_t& m, bf2_t& l, const SplitC& c) {
   h = __builtin_convertvector(x, bf2_t);
-  const f2_t r = x - __builtin_convertvector(h, f2_t);
-  m = __builtin_convertvector(r, bf2_t);
-  l = __builtin_convertvector(r - __builtin_convertvector(m, f2_t), bf2_t);
+  const float r0 = __builtin_amdgcn_fdot2_f32_bf16(h, c.nlo, x[0], false);
+  const float r1 = __builtin_amdgcn_fdot2_f32_bf16(h, c.nhi, x[1], false);
+  m = __builtin_convertvector(f2_t{r0, r1}, bf2_t);
+  const float s0 = __builtin_amdgcn_fdot2_f32_bf16(m, c.nlo, r0, false);
+  const float s1 = __builtin_amdgcn_fdot2_f32_bf16(m, c.nhi, r1, false);
+  l = __builtin_convertvector(f2_t{s0, s1}, bf2_t);
 }
 // operand parts of the six products, in order m m, l h, h l, m h, h m, h h (smallest first)
 __device__ __forceinline__ const bf8_t& pr_x(int pr, const bf8_t& h, const bf8_t& m, const bf8_t& l) {
@@ -57,10 +74,10 @@ __device__ __forceinline__ const bf8_t& pr_y(int pr, const bf8_t& h, const bf8_t
   return pr == 0 ? m : pr == 1 ? h : pr == 2 ? l : pr == 3 ? h : pr == 4 ? m : h;
 }
 // the three BF16 parts of 8 values v[0..7] as MFMA operands
-__device__ __forceinline__ void split3x8(const float (&v)[8], bf8_t& h, bf8_t& m, bf8_t& l) {
+__device__ __forceinline__ void split3x8(const float (&v)[8], bf8_t& h, bf8_t& m, bf8_t& l, const SplitC& c) {
   bf2_t hh[4], mm[4], ll[4];
 #pragma unroll
-  for (int p = 0; p < 4; ++p) split3x2(f2_t{v[2 * p], v[2 * p + 1]}, hh[p], mm[p], ll[p]);
+  for (int p = 0; p < 4; ++p) split3x2(f2_t{v[2 * p], v[2 * p + 1]}, hh[p], mm[p], ll[p], c);
   h = bf8_t{hh[0][0], hh[0][1], hh[1][0], hh[1][1], hh[2][0], hh[2][1], hh[3][0], hh[3][1]};
   m = bf8_t{mm[0][0], mm[0][1], mm[1][0], mm[1][1], mm[2][0], mm[2][1], mm[3][0], mm[3][1]};
   l = bf8_t{ll[0][0], ll[0][1], ll[1][0], ll[1][1], ll[2][0], ll[2][1], ll[3][0], ll[3][1]};
