@@ -115,7 +115,19 @@ struct KrgArgs {
   int32_t ksplit = 1;
   int64_t kslice = 0, out_split = 0;
   const char* label = nullptr;  // profile name (default: by weight mode and precision)
+  // Column source already split into three BF16 parts (bsplit layout, blocks of 32
+  // slots; bp_nblk = c.pad / 32), read by the split-product tile instead of splitting
+  // the FP32 columns in every wavefront; nullptr: split in the tile.
+  const uint32_t* bparts = nullptr;
+  int32_t bp_nblk = 0;
 };
+// Three-way BF16 split of an N x len column source (row stride ld) into the chunked
+// fragment layout read by the split-product tile: per chunk of 32 examples, per part
+// (h, m, l), per block of 32 slots, 512 dwords ordered [slot / 16 % 2][example / 8 % 4]
+// [slot % 16][example pair % 4], each dword two BF16 values of consecutive examples.
+// Slots >= len and examples >= N are zero.  Size: bsplit_dwords(N, pad) dwords.
+int64_t bsplit_dwords(int64_t N, int32_t pad);
+void bsplit(Exec& ex, const float* src, int64_t ld, int32_t len, int32_t pad, int64_t N, uint32_t* out);
 template <typename T, typename TOut>
 void krg(Exec& ex, const KrgArgs<T, TOut>& a);
 // Several contractions (FP32) through one persistent launch; jobs_dev is a device array.

@@ -464,11 +464,19 @@ struct HOps {
   OpgBufs<T> base;                // abar and delta in operand precision
   std::vector<T*> G, K;           // weights in operand precision
   T* D1T = nullptr;               // sigma'^(m) transposed, operand precision
+  uint32_t* bparts = nullptr;     // split products: column source of layer m split in BF16 parts
 };
+
+// Column layers whose source the split-product tile reads pre-split: slots padded to a
+// multiple of 32 and at least 128 per unit (two units per 128-column tile).
+static bool presplit_layer(const Model& m, int mm) {
+  const int64_t pad = rup(m.T[mm - 2] + 1, 16);
+  return pad % 32 == 0 && pad >= 128;
+}
 
 template <typename T>
 size_t plan_exact(const Model& m, int64_t N, void* ws, Prep& p, HOps<T>& ops, std::vector<HFactors>& fac,
-                  bool same_type) {
+                  bool same_type, bool split = false) {
   Arena ar(ws);
   const int L = m.L;
   plan_prep(ar, m, N, p, true);
@@ -497,6 +505,12 @@ size_t plan_exact(const Model& m, int64_t N, void* ws, Prep& p, HOps<T>& ops, st
     peak = std::max(peak, a2.used);
   }
   ar.used = peak;
+  if (split && !same_type) {  // one region for the pre-split column source, reused per layer
+    int64_t dw = 0;
+    for (int mm = 2; mm <= L; ++mm)
+      if (presplit_layer(m, mm)) dw = std::max(dw, bsplit_dwords(N, (int32_t)rup(m.T[mm - 2] + 1, 16)));
+    if (dw > 0) ops.bparts = ar.take<uint32_t>((size_t)dw);
+  }
   return ar.used;
 }
 
@@ -569,11 +583,22 @@ void run_exact(Exec& ex, const Model& m, int64_t N, Prep& p, HOps<T>& ops, std::
         D1w = d1;
       }
     }
+    // split products: the column source abar^(m-1) split once for all blocks of this m
+    uint32_t* bp = nullptr;
+    if constexpr (sizeof(T) == 4) {
+      if (ex.split && ops.bparts && presplit_layer(m, mm)) {
+        const KrgSide<T> cs = side_layer<T>(m, mm, abar[mm - 1], p.lda[mm - 1], nullptr, 0);
+        bsplit(ex, abar[mm - 1], p.lda[mm - 1], cs.len, cs.pad, N, ops.bparts);
+        bp = ops.bparts;
+      }
+    }
     // term 1: weighted Gram of abar^(l-1) and abar^(m-1)
     for (int l = mm; l <= L; ++l) {
       KrgArgs<T, TOut> a;
       a.r = side_layer<T>(m, l, abar[l - 1], p.lda[l - 1], nullptr, 0);
       a.c = side_layer<T>(m, mm, abar[mm - 1], p.lda[mm - 1], nullptr, 0);
+      a.bparts = bp;
+      a.bp_nblk = a.c.pad / 32;
       a.wmode = KRG_PAIR_FULL;
       a.wts = Gw[l];
       a.ldw = N;
@@ -742,7 +767,7 @@ static size_t ws_exact(const Model& m, int64_t N, int prec) {
     return plan_exact<double>(m, N, nullptr, p, o, fac, true);
   }
   HOps<float> o;
-  return plan_exact<float>(m, N, nullptr, p, o, fac, false);
+  return plan_exact<float>(m, N, nullptr, p, o, fac, false, prec == HESS_P_F32_SPLIT);
 }
 
 hess_status hess_workspace_size(hess_ctx* ctx, int op, const hess_mlp* mlp, const hess_data* d, int prec,
@@ -850,7 +875,7 @@ hess_status hess_exact(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, i
     plan_prep(ar, m, d->N, p0, true);
     plan_opg_ops<float>(ar, m, d->N, p0, o.base);
     const size_t base_used = ar.used;
-    plan_exact<float>(m, d->N, ws, p, o, fac, false);
+    plan_exact<float>(m, d->N, ws, p, o, fac, false, ex.split);
     if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
     run_prep(ex, m, d, p, true);
     run_exact<float, float>(ex, m, d->N, p, o, fac, ws, base_used, static_cast<float*>(H), false);

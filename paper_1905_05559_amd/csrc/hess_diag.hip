@@ -10,47 +10,79 @@ namespace {
 
 typedef float f16v_t __attribute__((ext_vector_type(16)));
 
-template <int KIND>
-__global__ __launch_bounds__(256) void k_mfma_stream(float* sink, int64_t iters) {
+// One kernel per instruction, each holding only its own accumulators (a shared body
+// made the compiler shuttle every accumulator through other registers each iteration).
+__global__ __launch_bounds__(256, 2) void k_stream_f32(float* sink, int64_t iters) {
   const int l = threadIdx.x & 63;
   f4_t acc[16];
-  d4_t dacc[16];
-  f16v_t acc32[4];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    acc[i] = f4_t{0.f, 0.f, 0.f, 0.f};
-    dacc[i] = d4_t{0.0, 0.0, 0.0, 0.0};
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) acc32[i] = f16v_t{};
+  for (int i = 0; i < 16; ++i) acc[i] = f4_t{0.f, 0.f, 0.f, 0.f};
   const float a = 1e-3f * (float)l, b = 2e-3f;
-  bf8_t av, bv;
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[i], 0, 0, 0);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s += acc[i][0];
+  if (s == -1.0e30f) sink[0] = s;  // never true: keeps the accumulators live
+}
+
+__device__ __forceinline__ void stream_operands(bf8_t& av, bf8_t& bv) {
+  const int l = threadIdx.x & 63;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     av[i] = (__bf16)(1e-3f * (float)(l + i));
     bv[i] = (__bf16)(1e-3f * (float)i);
   }
+}
+
+__global__ __launch_bounds__(256, 2) void k_stream_bf16_16(float* sink, int64_t iters) {
+  f4_t acc[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = f4_t{0.f, 0.f, 0.f, 0.f};
+  bf8_t av, bv;
+  stream_operands(av, bv);
   for (int64_t it = 0; it < iters; ++it) {
-    if (KIND == 0) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[i], 0, 0, 0);
-    } else if (KIND == 1) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
-    } else if (KIND == 2) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) acc32[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc32[i], 0, 0, 0);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) dacc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a, (double)b, dacc[i], 0, 0, 0);
-    }
+    for (int i = 0; i < 16; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
   }
   float s = 0.f;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) s += acc[i][0] + (float)dacc[i][0];
+  for (int i = 0; i < 16; ++i) s += acc[i][0];
+  if (s == -1.0e30f) sink[0] = s;
+}
+
+__global__ __launch_bounds__(256, 2) void k_stream_bf16_32(float* sink, int64_t iters) {
+  f16v_t acc[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) s += acc32[i][0];
-  if (s == -1.0e30f) sink[0] = s;  // never true: keeps the accumulators live
+  for (int i = 0; i < 4; ++i) acc[i] = f16v_t{};
+  bf8_t av, bv;
+  stream_operands(av, bv);
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[i], 0, 0, 0);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) s += acc[i][0];
+  if (s == -1.0e30f) sink[0] = s;
+}
+
+__global__ __launch_bounds__(256, 2) void k_stream_f64(float* sink, int64_t iters) {
+  const int l = threadIdx.x & 63;
+  d4_t acc[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = d4_t{0.0, 0.0, 0.0, 0.0};
+  const double a = 1e-3 * (double)l, b = 2e-3;
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s += acc[i][0];
+  if (s == -1.0e30) sink[0] = (float)s;
 }
 
 }  // namespace
@@ -78,10 +110,10 @@ extern "C" hess_status hess_mfma_stream_rate(hess_ctx* ctx, int kind, int64_t it
   for (int rep = 0; rep < 2; ++rep) {
     (void)hipEventRecord(e0, ex.stream);
     switch (kind) {
-      case 0: hipLaunchKernelGGL(k_mfma_stream<0>, dim3(blocks), dim3(256), 0, ex.stream, sink, iters); break;
-      case 1: hipLaunchKernelGGL(k_mfma_stream<1>, dim3(blocks), dim3(256), 0, ex.stream, sink, iters); break;
-      case 2: hipLaunchKernelGGL(k_mfma_stream<2>, dim3(blocks), dim3(256), 0, ex.stream, sink, iters); break;
-      default: hipLaunchKernelGGL(k_mfma_stream<3>, dim3(blocks), dim3(256), 0, ex.stream, sink, iters); break;
+      case 0: hipLaunchKernelGGL(k_stream_f32, dim3(blocks), dim3(256), 0, ex.stream, sink, iters); break;
+      case 1: hipLaunchKernelGGL(k_stream_bf16_16, dim3(blocks), dim3(256), 0, ex.stream, sink, iters); break;
+      case 2: hipLaunchKernelGGL(k_stream_bf16_32, dim3(blocks), dim3(256), 0, ex.stream, sink, iters); break;
+      default: hipLaunchKernelGGL(k_stream_f64, dim3(blocks), dim3(256), 0, ex.stream, sink, iters); break;
     }
     (void)hipEventRecord(e1, ex.stream);
     (void)hipEventSynchronize(e1);

@@ -316,27 +316,37 @@ __device__ __forceinline__ void krg_tile(const KrgArgs<T, TOut>& a, int64_t t, i
 constexpr int DLD = 132;
 
 // chunk of examples per stage and number of LDS stages (prefetch distance NST - 1);
-// SPLIT: FP32 products from BF16 MFMAs on three-way split operands (chunks of 32)
-template <int KC_, int NST_, bool SPLIT_ = false>
+// SPLIT: FP32 products from BF16 MFMAs on three-way split operands (chunks of 32);
+// BPS: the column operand arrives already split (bsplit layout) and is copied into LDS
+// as BF16 parts in MFMA operand order; A rows are unpadded (128-bit reads of 16 lanes
+// cover 256 contiguous bytes) and the pair weights go to registers, so that two
+// workgroups (2 x 80 KB) share a CU
+template <int KC_, int NST_, bool SPLIT_ = false, bool BPS_ = false>
 struct DmaCfg {
   static constexpr int KC = KC_, NST = NST_;
-  static constexpr bool SPLIT = SPLIT_;
+  static constexpr bool SPLIT = SPLIT_, BPS = BPS_;
+  static_assert(!BPS || (SPLIT && KC == 32), "pre-split columns need split products on chunks of 32");
 };
 using DmaDefault = DmaCfg<16, 2>;  // measured: (16, 2) 131, (16, 3) 129, (32, 2) 126 TFLOP/s
 
 template <int WMODE, int MAXU, class C = DmaDefault>
 struct DmaSmem {
   static constexpr int DKC = C::KC;
-  static constexpr int AB = DKC * DLD;
+  static constexpr int ALD = C::BPS ? 128 : DLD;  // A row stride (floats)
+  static constexpr int AB = DKC * ALD;
   static constexpr int WN1 = WMODE == KRG_PAIR_FULL ? MAXU * MAXU * DKC : MAXU * DKC;  // floats per weight array
   static constexpr int NW = WMODE == KRG_RANK1 ? 2 : 1;                              // weight arrays
   static constexpr int WI1 = (WN1 + 63) / 64;                                         // copies per array
   static constexpr int WI = NW * WI1;
-  static constexpr int STAGE = 2 * AB + NW * WN1;
+  // B: FP32 like A, or (BPS) the three BF16 parts of the tile's 128 columns as 24
+  // fragments of 64 lanes x 16 bytes, fragment ((wc * 4 + j) * 3 + part)
+  static constexpr int BSZ = C::BPS ? 24 * 256 : AB;
+  static constexpr int WOFF = AB + BSZ;  // weights after A and B (none for BPS)
+  static constexpr int STAGE = AB + BSZ + (C::BPS ? 0 : NW * WN1);
   static constexpr int SIZE = C::NST * STAGE;
-  // copies every wavefront issues per chunk: KC / 2 for A, KC / 2 for B, and its share
-  // of the weight copies (a lower bound when RANK1 scale factors may be absent)
-  static constexpr int VMC = DKC + (WMODE == KRG_RANK1 ? 0 : WI / 4);
+  // copies every wavefront issues per chunk: KC / 2 for A, KC / 2 for B (24 for BPS),
+  // and its share of the weight copies (a lower bound when RANK1 scale factors may be absent)
+  static constexpr int VMC = DKC / 2 + (C::BPS ? 24 : DKC / 2) + (C::BPS || WMODE == KRG_RANK1 ? 0 : WI / 4);
   static constexpr int WPW = (WI + 3) / 4;  // weight copies one wavefront may issue
 };
 
@@ -355,6 +365,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* base, int6
 
 __device__ __forceinline__ void copy_lds(__amdgpu_buffer_rsrc_t r, float* dst, int voff) {
   __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr_t)dst, 4, voff, 0, 0, 0);
+}
+// the same with a wavefront-uniform byte offset added by the scalar offset operand
+__device__ __forceinline__ void copy_lds_s(__amdgpu_buffer_rsrc_t r, float* dst, int voff, int soff) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr_t)dst, 4, voff, soff, 0, 0);
 }
 
 // s_waitcnt vmcnt(N) with expcnt and lgkmcnt left free (gfx9 encoding: vmcnt bits 3:0 and 15:14)
@@ -392,6 +406,20 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
     const int sr = (int)mn64(r % a.r.pad, a.r.len - 1), sc = (int)mn64(c % a.c.pad, a.c.len - 1);
     voffA[m] = (int)((k * a.r.ld + sr) * 4);
     voffB[m] = (int)((k * a.c.ld + sc) * 4);
+  }
+  // BPS: byte offsets of the tile's four 32-column groups (column half h, group g) in a
+  // pre-split chunk.  With BPS, block j of a wavefront holds its columns 16 j .. 16 j + 15,
+  // so blocks 0, 1 lie in group 0 and blocks 2, 3 in group 1; a group never crosses a
+  // unit (pad is a multiple of 32).
+  int bpo[4] = {0, 0, 0, 0};
+  if constexpr (C::BPS) {
+    const int64_t vcols = (int64_t)a.c.n_units * a.c.pad;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      int64_t cb = c0 + 32 * x;
+      if (cb >= vcols) cb = 0;  // beyond the last unit: any group (outputs discarded)
+      bpo[x] = (int)((cb % a.c.pad) / 32 * 512 * 4);
+    }
   }
   int voffW[SM::WPW];
   bool wlive[SM::WPW];
@@ -434,13 +462,36 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
     float* S = smem + st * SM::STAGE;
     const __amdgpu_buffer_rsrc_t ra = rsrc_of(a.r.src + n0 * a.r.ld, (int64_t)kv * a.r.ld);
     const __amdgpu_buffer_rsrc_t rb = rsrc_of(a.c.src + n0 * a.c.ld, (int64_t)kv * a.c.ld);
+    if constexpr (C::BPS) {
+      // voffA[m] = voffA[m & 1] + (m / 2) rows of the source: the row part is uniform
 #pragma unroll
-    for (int m = 0; m < KH; ++m) copy_lds(ra, S + ((DKC / 4) * wave + (m >> 1)) * DLD + (m & 1) * 64, voffA[m]);
+      for (int m = 0; m < KH; ++m)
+        copy_lds_s(ra, S + ((DKC / 4) * wave + (m >> 1)) * SM::ALD + (m & 1) * 64, voffA[m & 1],
+                   (int)((m >> 1) * a.r.ld * 4));
+    } else {
 #pragma unroll
-    for (int m = 0; m < KH; ++m)
-      copy_lds(rb, S + SM::AB + ((DKC / 4) * wave + (m >> 1)) * DLD + (m & 1) * 64, voffB[m]);
-    float* W = S + 2 * SM::AB;
-    if (WMODE == KRG_PAIR_FULL || WMODE == KRG_PAIR_DIAG) {
+      for (int m = 0; m < KH; ++m) copy_lds(ra, S + ((DKC / 4) * wave + (m >> 1)) * SM::ALD + (m & 1) * 64, voffA[m]);
+    }
+    if constexpr (C::BPS) {
+      // 96 fragment row blocks of 256 bytes (2 halves x 4 j x 3 parts x 4 row blocks), 24 per
+      // wavefront, each 256 contiguous bytes of chunk n0 / 32 of the pre-split source
+      const int64_t cs = (int64_t)3 * a.bp_nblk * 512;  // dwords per chunk
+      const __amdgpu_buffer_rsrc_t rp = rsrc_of(a.bparts + (n0 / DKC) * cs, cs);
+#pragma unroll
+      for (int x = 0; x < 24; ++x) {  // (half, j, part) fixed per x; wavefront w copies row block w
+        const int part = x % 3, j = (x / 3) & 3, h = x / 12, mb = wave;
+        copy_lds(rp, S + SM::AB + ((h * 4 + j) * 3 + part) * 256 + mb * 64,
+                 bpo[2 * h + (j >> 1)] + 4 * (part * a.bp_nblk * 512 + (j & 1) * 256 + mb * 64 + lane));
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < KH; ++m)
+        copy_lds(rb, S + SM::AB + ((DKC / 4) * wave + (m >> 1)) * DLD + (m & 1) * 64, voffB[m]);
+    }
+    float* W = S + SM::WOFF;
+    if (C::BPS) {
+      // pair weights are loaded into registers by the tile (wload)
+    } else if (WMODE == KRG_PAIR_FULL || WMODE == KRG_PAIR_DIAG) {
       const int64_t base = (WMODE == KRG_PAIR_FULL ? ((int64_t)ur_lo * a.c.n_units + uc_lo) : (int64_t)ur_lo) * a.ldw + n0;
       const __amdgpu_buffer_rsrc_t rw = rsrc_of(a.wts + base, wtot - base);
 #pragma unroll
@@ -499,8 +550,34 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
   for (int i = 0; i < 4; ++i) ur_blk[i] = (int)((r0 + wr * 64 + 16 * i) / a.r.pad) - ur_lo;
 
   const int64_t nk = (a.N + DKC - 1) / DKC;
+  // BPS: this lane's pair weights of examples n0 + 8 q .. n0 + 8 q + 7 for its row unit and
+  // column unit u (relative), read straight into registers through one wavefront-uniform
+  // buffer that starts at the tile's first unit pair (the lane's pair is in the offset, as
+  // for the weight copies); examples past N read as zero
+  const int64_t wb0 = ((int64_t)ur_lo * a.c.n_units + uc_lo) * a.ldw;
+  auto wload = [&](int64_t n0, int u, float (&w)[8]) {
+    const int ur = min(ur_lo + ur_lane, a.r.n_units - 1), uc = min(uc_lo + u, a.c.n_units - 1);
+    const int vo = (int)((((int64_t)(ur - ur_lo) * a.c.n_units + (uc - uc_lo)) * a.ldw + 8 * q) * 4);
+    const __amdgpu_buffer_rsrc_t rw = rsrc_of(a.wts + wb0 + n0, wtot - wb0 - n0);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) w[s] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rw, vo + 4 * s, 0, 0));
+    if (n0 + DKC > a.N) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        if (n0 + 8 * q + s >= a.N) w[s] = 0.f;
+    }
+  };
   auto kloop = [&](auto oc) {
     constexpr bool ONE = decltype(oc)::value;
+    // BPS: the rows are weighted for one column unit, or for two when the wavefront's
+    // columns lie in two units (units ubase and ubase + 1, split at its 32nd column)
+    constexpr int NPB = ONE ? 1 : 2;
+    const int ubase = ONE ? uc_lane : (int)((c0 + wc * 64) / a.c.pad) - uc_lo;
+    float wcur[NPB][8], wnxt[NPB][8];
+    if constexpr (C::BPS) {
+#pragma unroll
+      for (int ps = 0; ps < NPB; ++ps) wload(0, ubase + ps, wnxt[ps]);
+    }
 #pragma unroll
     for (int c = 0; c < DST - 1; ++c)
       if (c < nk) issue(c, (int64_t)c * DKC);
@@ -511,11 +588,63 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
       // about to be refilled are complete
       asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
       if (kc + DST - 1 < nk) issue((int)((kc + DST - 1) % DST), (kc + DST - 1) * DKC);
+      if constexpr (C::BPS) {  // this chunk's weights landed with its copies; fetch the next
+#pragma unroll
+        for (int ps = 0; ps < NPB; ++ps)
+#pragma unroll
+          for (int s = 0; s < 8; ++s) wcur[ps][s] = wnxt[ps][s];
+        if (kc + 1 < nk) {
+#pragma unroll
+          for (int ps = 0; ps < NPB; ++ps) wload((kc + 1) * DKC, ubase + ps, wnxt[ps]);
+        }
+      }
       const int st = (int)(kc % DST);
       const float* As = smem + st * SM::STAGE;
       const float* Bs = As + SM::AB;
-      const float* W = As + 2 * SM::AB;
+      const float* W = As + SM::WOFF;
       const int kv = (int)mn64(DKC, a.N - kc * DKC);
+      if constexpr (C::BPS) {
+        // The columns arrive split: 12 fragment reads (lane = 16 q + row16 holds examples
+        // 8 q .. 8 q + 7 of column 16 j + row16).  The rows are weighted and split here,
+        // once per column unit: blocks 0, 1 take the weights of group 0's unit and blocks
+        // 2, 3 those of group 1's unit (the same unit unless the wavefront straddles two).
+        const SplitC sc = split_consts();
+        const bf8_t* Bq = reinterpret_cast<const bf8_t*>(Bs);
+        bf8_t bh[4], bm[4], bl[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          bh[j] = Bq[((wc * 4 + j) * 3 + 0) * 64 + lane];
+          bm[j] = Bq[((wc * 4 + j) * 3 + 1) * 64 + lane];
+          bl[j] = Bq[((wc * 4 + j) * 3 + 2) * 64 + lane];
+        }
+        float ax[4][8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const f4_t a4 = *(const f4_t*)&As[(8 * q + s) * SM::ALD + wr * 64 + 4 * row16];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) ax[i][s] = a4[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+          for (int ps = 0; ps < NPB; ++ps) {
+            float av[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) av[s] = ax[i][s] * wcur[ps][s];
+            bf8_t ah, am, al;
+            split3x8(av, ah, am, al, sc);
+            constexpr int J0 = 0, JN = 4 / NPB;
+#pragma unroll
+            for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+              for (int jj = J0; jj < JN; ++jj) {
+                const int j = ps * JN + jj;
+                acc[i][j] = mma_bf16(pr_x(pr, ah, am, al), pr_y(pr, bh[j], bm[j], bl[j]), acc[i][j]);
+              }
+          }
+        }
+        continue;
+      }
       if constexpr (ONE && C::SPLIT) {
         // the chunk's 32 examples at once: this lane supplies k = 8 q + s (s = 0..7) of
         // its four rows (A, weighted) and four columns (B); each value is split in three
@@ -598,7 +727,7 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
   int64_t ccomp[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int64_t c = c0 + wc * 64 + 4 * row16 + j;
+    const int64_t c = c0 + wc * 64 + (C::BPS ? 16 * j + row16 : 4 * row16 + j);
     const int64_t uc = c / a.c.pad, sc = c % a.c.pad;
     ccomp[j] = c;
     cok[j] = uc < a.c.n_units && sc < a.c.len;
@@ -608,7 +737,7 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t r = r0 + wr * 64 + (one_cunit ? 16 * q + 4 * v + i : 16 * i + 4 * q + v);
+      const int64_t r = r0 + wr * 64 + ((C::BPS || one_cunit) ? 16 * q + 4 * v + i : 16 * i + 4 * q + v);
       const int64_t ur = r / a.r.pad, sr = r % a.r.pad;
       if (!(ur < a.r.n_units && sr < a.r.len)) continue;
       const int64_t fr = flat_index(a.r.perm, a.r.off, a.r.Tin, a.r.Tout, ur, sr);
@@ -637,6 +766,7 @@ __global__ __launch_bounds__(256, 2) void krg_kernel_dma(KrgArgs<float, float> a
     if (a.r.scale) a.r.scale += k0 * a.r.ld_scale;
     if (a.c.scale) a.c.scale += k0 * a.c.ld_scale;
     if (a.wts) a.wts += k0;
+    if (a.bparts) a.bparts += (k0 / 32) * (int64_t)3 * a.bp_nblk * 512;  // kslice is a multiple of 32
     a.N = mn64(a.kslice, a.N - k0);
     a.out += sp * a.out_split;
   }
@@ -733,6 +863,33 @@ __global__ __launch_bounds__(256, 2) void krg_persistent(const KrgJob* jobs, int
 
 __global__ void k_zero_counter(unsigned long long* c) { *c = 0ull; }
 
+// One thread per dword of the pre-split layout (see bsplit in common.h): two consecutive
+// examples of one slot, split by the same arithmetic as the tile's split3x2.
+__global__ __launch_bounds__(256) void k_bsplit(const float* __restrict__ src, int64_t ld, int32_t len, int32_t nblk,
+                                                int64_t N, int64_t total, uint32_t* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= total) return;
+  const int e = (int)(t & 511);
+  const int64_t cb = t >> 9;  // chunk * nblk + block
+  const int64_t chunk = cb / nblk;
+  const int bi = (int)(cb - chunk * nblk);
+  const int jj = e >> 8, q = (e >> 6) & 3, s16 = (e >> 2) & 15, w = e & 3;
+  const int sc = bi * 32 + 16 * jj + s16;
+  const int64_t k = chunk * 32 + 8 * q + 2 * w;
+  float x0 = 0.f, x1 = 0.f;
+  if (sc < len) {
+    if (k < N) x0 = src[k * ld + sc];
+    if (k + 1 < N) x1 = src[(k + 1) * ld + sc];
+  }
+  bf2_t h, m, l;
+  split3x2(f2_t{x0, x1}, h, m, l, split_consts());
+  const int64_t ps = (int64_t)nblk * 512;
+  const int64_t o = (chunk * 3 * nblk + bi) * 512 + e;
+  out[o] = __builtin_bit_cast(uint32_t, h);
+  out[o + ps] = __builtin_bit_cast(uint32_t, m);
+  out[o + 2 * ps] = __builtin_bit_cast(uint32_t, l);
+}
+
 template <typename T, typename TOut, int KC, int STAGES>
 void launch_cfg(Exec& ex, const KrgArgs<T, TOut>& a, dim3 grid, int64_t tc, int64_t nt) {
 #define KRG_LAUNCH(MODE, SYMV) \
@@ -750,7 +907,8 @@ void launch_cfg(Exec& ex, const KrgArgs<T, TOut>& a, dim3 grid, int64_t tc, int6
 }  // namespace
 
 // variant: 0 = default for the precision; register-staged tile 1 = (KC 16, 1 stage), 2 = (16, 2),
-// 3 = (32, 1), 4 = (32, 2); FP32 LDS-staged tile 5 = (32 examples, 2 stages), 6 = (16, 3)
+// 3 = (32, 1), 4 = (32, 2); FP32 LDS-staged tile 5 = (32 examples, 2 stages), 6 = (16, 3);
+// split products 7 = columns split in the tile, 8 = pre-split columns (needs a.bparts)
 template <typename T, typename TOut>
 void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
   const int64_t rows = (int64_t)a.r.n_units * a.r.pad, cols = (int64_t)a.c.n_units * a.c.pad;
@@ -787,17 +945,27 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
       auto go = [&](int cfg, dim3 g, int64_t ntl) {
         auto run = [&](auto c) {
           using C = decltype(c);
-          if (maxu == 2) launch_dma<2, C>(ex, a, g, tc, ntl);
-          else if (maxu == 5) launch_dma<5, C>(ex, a, g, tc, ntl);
-          else launch_dma<9, C>(ex, a, g, tc, ntl);
+          if constexpr (C::BPS) {  // only the pair-weighted form with two units per tile side
+            if (a.symmetric) launch_dma_one<KRG_PAIR_FULL, true, 2, C>(ex, a, g, tc, ntl);
+            else launch_dma_one<KRG_PAIR_FULL, false, 2, C>(ex, a, g, tc, ntl);
+          } else {
+            if (maxu == 2) launch_dma<2, C>(ex, a, g, tc, ntl);
+            else if (maxu == 5) launch_dma<5, C>(ex, a, g, tc, ntl);
+            else launch_dma<9, C>(ex, a, g, tc, ntl);
+          }
         };
         if (cfg == 1) run(DmaCfg<16, 3>());
         else if (cfg == 2) run(DmaCfg<32, 2>());
         else if (cfg == 3) run(DmaCfg<32, 2, true>());
+        else if (cfg == 4) run(DmaCfg<32, 2, true, true>());
         else run(DmaDefault());
       };
-      int cfg = variant == 5 ? 2 : (variant == 6 ? 1 : (variant == 7 || ex.split ? 3 : 0));
-      if (cfg == 3 && label.compare(0, 7, "krg_f32") == 0) label = "krg_bf16x6" + label.substr(7);
+      int cfg = variant == 5 ? 2 : (variant == 6 ? 1 : (variant >= 7 || ex.split ? 3 : 0));
+      // split products on pre-split columns (variant 8 asks for it explicitly)
+      const bool bps = a.bparts && a.wmode == KRG_PAIR_FULL && maxu == 2 && a.c.pad % 32 == 0 &&
+                       a.bp_nblk == a.c.pad / 32 && (ks == 1 || a.kslice % 32 == 0);
+      if (cfg == 3 && bps && variant != 7) cfg = 4;
+      if (cfg >= 3 && label.compare(0, 7, "krg_f32") == 0) label = "krg_bf16x6" + label.substr(7);
       // Probes write into the output, which the full launch then overwrites; a launch that
       // accumulates into its output keeps the default configuration.
       if (variant == 0 && !ex.split && ex.ctx->autotune && !a.accumulate && launch_ok(ex)) {
@@ -861,6 +1029,18 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
 }
 
 bool krg_persistent_fits(const KrgArgs<float, float>& a) { return dma_fits(a, 9); }
+
+int64_t bsplit_dwords(int64_t N, int32_t pad) { return (N + 31) / 32 * 3 * (int64_t)(pad / 32) * 512; }
+
+void bsplit(Exec& ex, const float* src, int64_t ld, int32_t len, int32_t pad, int64_t N, uint32_t* out) {
+  const int64_t nblk = pad / 32, total = (N + 31) / 32 * nblk * 512;
+  if (total <= 0 || pad % 32 != 0 || len > pad) return;
+  if (!launch_ok(ex)) return;
+  const int tok = prof_begin(ex, "bsplit", 0.0, (double)N * len * 4 + (double)total * 12);
+  hipLaunchKernelGGL(k_bsplit, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, ex.stream, src, ld, len,
+                     (int32_t)nblk, N, total, out);
+  prof_end(ex, tok);
+}
 
 int64_t krg_tiles(const KrgArgs<float, float>& a, int64_t* tiles_c) {
   const int64_t rows = (int64_t)a.r.n_units * a.r.pad, cols = (int64_t)a.c.n_units * a.c.pad;

@@ -154,6 +154,23 @@ def test_wide_units_exact_and_opg(api, prec):
     assert report("OPG wide %s" % prec, G, Gref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("T,acts,N,seed", [
+    ([127, 24, 10], ["relu"], 300, 11),   # 128 slots per unit: wavefronts never straddle units
+    ([223, 12, 5], ["tanh"], 97, 12),     # 224 slots: every other unit boundary splits a wavefront
+])
+def test_presplit_columns_exact(api, T, acts, N, seed):
+    # split products read the first layer's column source pre-split (unit slots padded to a
+    # multiple of 32, at least 128); ragged last chunk of examples in both cases
+    print("case presplit columns T=%s acts=%s N=%d seed=%d" % (T, acts, N, seed), flush=True)
+    w = workloads.mlp_gaussian(T, acts, N, seed, dtype="float32")
+    model, X, Y = to_dev(api, w, w.dtype)
+    om, Xo, Yo = oracle_of(w)
+    Href = mlp.hessian(om, Xo, Yo, block=256)
+    H = api.hess_exact(model, X, Y, "f32_split").double().cpu().numpy()
+    assert np.array_equal(H, H.T)
+    assert report("H   %s f32_split (pre-split columns)" % T, H, Href) <= TOL["f32_split"]
+
+
 # Column blocks of the MNIST-shaped network (P = 79510): the first inputs of unit 0, the
 # boundary between hidden units 37 and 38, the last hidden biases and first output
 # weights, and the output layer's tail with its biases.
