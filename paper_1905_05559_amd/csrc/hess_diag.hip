@@ -12,7 +12,7 @@ typedef float f16v_t __attribute__((ext_vector_type(16)));
 
 // One kernel per instruction, each holding only its own accumulators (a shared body
 // made the compiler shuttle every accumulator through other registers each iteration).
-__global__ __launch_bounds__(256, 2) void k_stream_f32(float* sink, int64_t iters) {
+__global__ __launch_bounds__(256) void k_stream_f32(float* sink, int64_t iters) {
   const int l = threadIdx.x & 63;
   f4_t acc[16];
 #pragma unroll
