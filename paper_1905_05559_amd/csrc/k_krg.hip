@@ -945,9 +945,10 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
       auto go = [&](int cfg, dim3 g, int64_t ntl) {
         auto run = [&](auto c) {
           using C = decltype(c);
-          if constexpr (C::BPS) {  // only the pair-weighted form with two units per tile side
+          if constexpr (C::BPS) {  // only the pair-weighted form, two column units per tile
             if (a.symmetric) launch_dma_one<KRG_PAIR_FULL, true, 2, C>(ex, a, g, tc, ntl);
-            else launch_dma_one<KRG_PAIR_FULL, false, 2, C>(ex, a, g, tc, ntl);
+            else if (maxu == 2) launch_dma_one<KRG_PAIR_FULL, false, 2, C>(ex, a, g, tc, ntl);
+            else launch_dma_one<KRG_PAIR_FULL, false, 5, C>(ex, a, g, tc, ntl);
           } else {
             if (maxu == 2) launch_dma<2, C>(ex, a, g, tc, ntl);
             else if (maxu == 5) launch_dma<5, C>(ex, a, g, tc, ntl);
@@ -962,8 +963,10 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
       };
       int cfg = variant == 5 ? 2 : (variant == 6 ? 1 : (variant >= 7 || ex.split ? 3 : 0));
       // split products on pre-split columns (variant 8 asks for it explicitly)
-      const bool bps = a.bparts && a.wmode == KRG_PAIR_FULL && maxu == 2 && a.c.pad % 32 == 0 &&
-                       a.bp_nblk == a.c.pad / 32 && (ks == 1 || a.kslice % 32 == 0);
+      // (the rows may span up to 5 units of a tile: each lane's rows lie in one unit)
+      const bool bps = a.bparts && a.wmode == KRG_PAIR_FULL && a.c.pad >= 128 && a.c.pad % 32 == 0 &&
+                       (maxu == 2 || (maxu == 5 && !a.symmetric)) && a.bp_nblk == a.c.pad / 32 &&
+                       (ks == 1 || a.kslice % 32 == 0);
       if (cfg == 3 && bps && variant != 7) cfg = 4;
       if (cfg >= 3 && label.compare(0, 7, "krg_f32") == 0) label = "krg_bf16x6" + label.substr(7);
       // Probes write into the output, which the full launch then overwrites; a launch that
