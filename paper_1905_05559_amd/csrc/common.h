@@ -143,7 +143,8 @@ void krg_persistent_launch(Exec& ex, const KrgJob* jobs_dev, int njobs, int64_t 
                            double flops, double bytes);
 // Tile-configuration variants (tuning and tests): register-staged tile 1..4 = (K chunk,
 // LDS stages) in {(16,1), (16,2), (32,1), (32,2)}; FP32 LDS-staged tile 5 = (32, 2),
-// 6 = (16, 3); 0 = the default for the precision (FP32: LDS-staged (16, 2)).
+// 6 = (16, 3); split products 7 = columns split in the tile, 8 = pre-split columns
+// (a.bparts); 0 = the default for the precision (FP32: LDS-staged (16, 2)).
 template <typename T, typename TOut>
 void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant);
 // BF16 OPG: materialise Jt (P x ldk, BF16, p-major) then one symmetric Gram product.
@@ -158,7 +159,8 @@ void jt_bf16(Exec& ex, const JtArgs& a);
 int64_t jt_ld(int64_t N);
 void gram_bf16(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64_t N, float scale, float* C, int64_t ldc);
 // variant 1: register-staged Gram kernel; 2: LDS-staged with 32-example chunks in 4 stages;
-// otherwise LDS-staged with 64-example chunks in 2 stages (default)
+// 3: LDS-staged (64, 2) with each chunk's copies issued together after the barrier;
+// otherwise LDS-staged (64, 2) with the copies spread over the MFMA rows (default)
 void gram_bf16_variant(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64_t N, float scale, float* C,
                        int64_t ldc, int variant);
 
