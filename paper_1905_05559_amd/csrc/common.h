@@ -121,6 +121,14 @@ struct KrgArgs {
   const uint32_t* bparts = nullptr;
   int32_t bp_nblk = 0;
 };
+// Pair-diagonal contraction (KRG_PAIR_DIAG, FP32) as one product instead of tiles:
+// out[row(u, s)][col(u, b)] (+)= scale * sum_n w[u][n] r.src[n][s] c.src[n][b] for units
+// u < min(r.n_units, c.n_units), through Y[n][u len_r + s] = w[u][n] r.src[n][s] (N x U len_r),
+// PD_SLICES partial products Y^T c.src over slices of the examples, and a scatter that sums
+// them (mirrored if a.mirror).  Workspace: pairdiag_floats(a) floats.
+constexpr int PD_SLICES = 8;
+int64_t pairdiag_floats(int64_t N, int64_t U, int64_t len_r, int64_t len_c);
+void krg_pairdiag_gemm(Exec& ex, const KrgArgs<float, float>& a, float* ws);
 // Three-way BF16 split of an N x len column source (row stride ld) into the chunked
 // fragment layout read by the split-product tile: per chunk of 32 examples, per part
 // (h, m, l), per block of 32 slots, 512 dwords ordered [slot / 16 % 2][example / 8 % 4]

@@ -465,7 +465,15 @@ struct HOps {
   std::vector<T*> G, K;           // weights in operand precision
   T* D1T = nullptr;               // sigma'^(m) transposed, operand precision
   uint32_t* bparts = nullptr;     // split products: column source of layer m split in BF16 parts
+  float* pdws = nullptr;          // pair-diagonal blocks as one product (FP32 operands)
 };
+
+// Pair-diagonal block of column layer mm (the K term with l = mm + 1): units T_m, row slots
+// T_{m+1}, column slots T_{m-1} + 1; done as one product when its workspace stays below 2 GB.
+static int64_t pairdiag_block_floats(const Model& m, int64_t N, int mm) {
+  return pairdiag_floats(N, m.T[mm - 1], m.T[mm], m.T[mm - 2] + 1);
+}
+constexpr int64_t kPairdiagMaxBytes = int64_t(2) << 30;
 
 // Column layers whose source the split-product tile reads pre-split: slots padded to a
 // multiple of 32 and at least 128 per unit (two units per 128-column tile).
@@ -510,6 +518,14 @@ size_t plan_exact(const Model& m, int64_t N, void* ws, Prep& p, HOps<T>& ops, st
     for (int mm = 2; mm <= L; ++mm)
       if (presplit_layer(m, mm)) dw = std::max(dw, bsplit_dwords(N, (int32_t)rup(m.T[mm - 2] + 1, 16)));
     if (dw > 0) ops.bparts = ar.take<uint32_t>((size_t)dw);
+  }
+  if (!same_type) {
+    int64_t pf = 0;
+    for (int mm = 2; mm <= L - 1; ++mm) {
+      const int64_t f = pairdiag_block_floats(m, N, mm);
+      if (f * 4 <= kPairdiagMaxBytes) pf = std::max(pf, f);
+    }
+    if (pf > 0) ops.pdws = ar.take<float>((size_t)pf);
   }
   return ar.used;
 }
@@ -643,6 +659,12 @@ void run_exact(Exec& ex, const Model& m, int64_t N, Prep& p, HOps<T>& ops, std::
       a.mirror = 1;
       a.scale = 1.0 / (double)N;
       a.N = N;
+      if constexpr (sizeof(T) == 4 && sizeof(TOut) == 4) {
+        if (l - 1 == mm && ops.pdws && pairdiag_block_floats(m, N, mm) * 4 <= kPairdiagMaxBytes) {
+          krg_pairdiag_gemm(ex, a, ops.pdws);
+          continue;
+        }
+      }
       krg<T, TOut>(ex, a);
     }
   }

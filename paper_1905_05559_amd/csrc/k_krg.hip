@@ -863,6 +863,11 @@ __global__ __launch_bounds__(256, 2) void krg_persistent(const KrgJob* jobs, int
 
 __global__ void k_zero_counter(unsigned long long* c) { *c = 0ull; }
 
+__global__ __launch_bounds__(256) void k_fill_zero(float* __restrict__ p, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) p[t] = 0.f;
+}
+
 // One thread per dword of the pre-split layout (see bsplit in common.h): two consecutive
 // examples of one slot, split by the same arithmetic as the tile's split3x2.
 __global__ __launch_bounds__(256) void k_bsplit(const float* __restrict__ src, int64_t ld, int32_t len, int32_t nblk,
@@ -1032,6 +1037,73 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
 }
 
 bool krg_persistent_fits(const KrgArgs<float, float>& a) { return dma_fits(a, 9); }
+
+// ---- pair-diagonal contraction as one product ----
+namespace {
+__global__ __launch_bounds__(256) void k_pd_form(const float* __restrict__ rsrc, int64_t rld, int32_t lr,
+                                                 const float* __restrict__ w, int64_t ldw, int32_t U, int64_t N,
+                                                 float* __restrict__ Y) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x, row = (int64_t)U * lr;
+  if (t >= N * row) return;
+  const int64_t n = t / row;
+  const int e = (int)(t - n * row), u = e / lr, sl = e - u * lr;
+  Y[t] = w[u * ldw + n] * rsrc[n * rld + sl];
+}
+
+__global__ __launch_bounds__(256) void k_pd_scatter(const float* __restrict__ Cp, int64_t part, int32_t lr,
+                                                    int32_t lc, int32_t U, KrgArgs<float, float> a) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)U * lr * lc) return;
+  const int b = (int)(t % lc);
+  const int64_t m = t / lc;
+  const int u = (int)(m / lr), sl = (int)(m % lr);
+  float acc = 0.f;
+#pragma unroll
+  for (int sp = 0; sp < PD_SLICES; ++sp) acc += Cp[sp * part + t];
+  const int64_t fr = flat_index(a.r.perm, a.r.off, a.r.Tin, a.r.Tout, u, sl);
+  const int64_t fc = flat_index(a.c.perm, a.c.off, a.c.Tin, a.c.Tout, u, b);
+  const double v = a.scale * (double)acc;
+  store_out<float>(a.out, fr * a.ldo + fc, v, a.accumulate);
+  if (a.mirror) store_out<float>(a.out, fc * a.ldo + fr, v, a.accumulate);
+}
+}  // namespace
+
+int64_t pairdiag_floats(int64_t N, int64_t U, int64_t len_r, int64_t len_c) {
+  return N * U * len_r + (int64_t)PD_SLICES * U * len_r * len_c;
+}
+
+void krg_pairdiag_gemm(Exec& ex, const KrgArgs<float, float>& a, float* ws) {
+  const int32_t U = std::min(a.r.n_units, a.c.n_units), lr = a.r.len, lc = a.c.len;
+  const int64_t N = a.N, M = (int64_t)U * lr, part = M * lc;
+  if (U <= 0 || N <= 0 || !launch_ok(ex)) return;
+  float* Y = ws;
+  float* Cp = ws + N * M;
+  const int tok = prof_begin(ex, "krg_pairdiag_gemm", 2.0 * N * (double)M * lc,
+                             (double)N * (a.r.ld + a.c.ld + U) * 4 + (double)N * M * 8 + (double)part * 4 * 3);
+  hipLaunchKernelGGL(k_pd_form, dim3((unsigned)((N * M + 255) / 256)), dim3(256), 0, ex.stream, a.r.src, a.r.ld, lr,
+                     a.wts, a.ldw, U, N, Y);
+  // partial products over PD_SLICES slices of the examples: PD_SLICES - 1 equal slices in
+  // one batched call, the rest in a second call
+  const int64_t ks = N / PD_SLICES, klast = N - (PD_SLICES - 1) * ks;
+  if (ks > 0) {
+    GemmArgs<float> g;
+    g.M = M; g.N = lc; g.K = ks;
+    g.A = Y; g.sam = 1; g.sak = M; g.sab = ks * M;
+    g.B = a.c.src; g.sbk = a.c.ld; g.sbn = 1; g.sbb = ks * a.c.ld;
+    g.C = Cp; g.scm = lc; g.scn = 1; g.scb = part;
+    g.alpha = 1.f; g.beta = 0.f; g.batch = PD_SLICES - 1;
+    gemm<float>(ex, g);
+  } else {
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((part * (PD_SLICES - 1) + 255) / 256)), dim3(256), 0, ex.stream,
+                       Cp, part * (PD_SLICES - 1));
+  }
+  const int64_t k0 = (PD_SLICES - 1) * ks;
+  gemm_rm<float>(ex, true, false, M, lc, klast, 1.f, Y + k0 * M, M, a.c.src + k0 * a.c.ld, a.c.ld, 0.f,
+                 Cp + (PD_SLICES - 1) * part, lc);
+  hipLaunchKernelGGL(k_pd_scatter, dim3((unsigned)((part + 255) / 256)), dim3(256), 0, ex.stream, Cp, part, lr, lc, U,
+                     a);
+  prof_end(ex, tok);
+}
 
 int64_t bsplit_dwords(int64_t N, int32_t pad) { return (N + 31) / 32 * 3 * (int64_t)(pad / 32) * 512; }
 
