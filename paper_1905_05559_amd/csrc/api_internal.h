@@ -61,6 +61,12 @@ void cast_ops(Exec& ex, const Model& m, const Prep& p, OpgBufs<T>& b);
 // Row/column side of the contraction for layer l (params W^(l-1), b^(l)).
 template <typename T>
 KrgSide<T> side_layer(const Model& m, int l, const T* abar, int64_t lda, const T* scale, int64_t ld_scale);
+// Pair-diagonal block of column layer mm (the K term with l = mm + 1; units T_m, row slots
+// T_{m+1}, column slots T_{m-1} + 1): FP32 workspace of its one-product form, which is used
+// when that stays within kPairdiagMaxBytes (single and batched Hessians alike, so that the
+// two agree bitwise).
+int64_t pairdiag_block_floats(const Model& m, int64_t N, int mm);
+constexpr int64_t kPairdiagMaxBytes = int64_t(2) << 30;
 
 // Unit-direction R-operator factors of one column layer; see hess_api.hip.
 struct HFactors {

@@ -468,12 +468,9 @@ struct HOps {
   float* pdws = nullptr;          // pair-diagonal blocks as one product (FP32 operands)
 };
 
-// Pair-diagonal block of column layer mm (the K term with l = mm + 1): units T_m, row slots
-// T_{m+1}, column slots T_{m-1} + 1; done as one product when its workspace stays below 2 GB.
-static int64_t pairdiag_block_floats(const Model& m, int64_t N, int mm) {
+int64_t pairdiag_block_floats(const Model& m, int64_t N, int mm) {
   return pairdiag_floats(N, m.T[mm - 1], m.T[mm], m.T[mm - 2] + 1);
 }
-constexpr int64_t kPairdiagMaxBytes = int64_t(2) << 30;
 
 // Column layers whose source the split-product tile reads pre-split: slots padded to a
 // multiple of 32 and at least 128 per unit (two units per 128-column tile).

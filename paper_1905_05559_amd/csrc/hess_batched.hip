@@ -30,6 +30,7 @@ struct BPlan {
   unsigned long long* counter = nullptr;
   int* flags = nullptr;
   int64_t njobs_max = 0;
+  float* pdws = nullptr;  // pair-diagonal blocks as one product (one network at a time)
 };
 
 // FP64 scratch needed by one network: per-example caches plus the factors of one column layer.
@@ -75,6 +76,13 @@ size_t plan_batched(Arena& ar, int64_t M, const hess_mlp* models, const hess_dat
   bp.counter = ar.take<unsigned long long>(1);
   bp.njobs_max = nj;
   bp.jobs = ar.take<KrgJob>(nj);
+  int64_t pf = 0;
+  for (int64_t i = 0; i < M; ++i)
+    for (int mm = 2; mm <= bp.nets[i].m.L - 1; ++mm) {
+      const int64_t f = pairdiag_block_floats(bp.nets[i].m, bp.nets[i].N, mm);
+      if (f * 4 <= kPairdiagMaxBytes) pf = std::max(pf, f);
+    }
+  if (pf > 0) bp.pdws = ar.take<float>((size_t)pf);
   for (int64_t i = 0; i < M; ++i) {
     BNet& b = bp.nets[i];
     const Model& m = b.m;
@@ -161,6 +169,7 @@ extern "C" hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* mo
   std::vector<KrgJob> jobsA, jobsB;
   double flopsA = 0, flopsB = 0;
   std::vector<KrgArgs<float, float>> missA, missB;  // contractions too large for the persistent launch
+  std::vector<KrgArgs<float, float>> pdiag;         // pair-diagonal blocks done as one product
   auto add = [&](std::vector<KrgJob>& v, const KrgArgs<float, float>& a, double& flops) {
     if (!krg_persistent_fits(a)) {
       (&v == &jobsA ? missA : missB).push_back(a);
@@ -259,6 +268,10 @@ extern "C" hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* mo
             if (l - 1 == mm) {
               t2.wmode = KRG_PAIR_DIAG;
               t2.wts = b.D1[mm];
+              if (bp.pdws && pairdiag_block_floats(m, N, mm) * 4 <= kPairdiagMaxBytes) {
+                pdiag.push_back(t2);  // as hess_exact does it
+                continue;
+              }
             } else {
               t2.wmode = KRG_PAIR_FULL;
               t2.wts = b.K[mm][l - 1];
@@ -278,6 +291,8 @@ extern "C" hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* mo
     krg_persistent_launch(ex, bp.jobs, (int)nA, totA, bp.counter, flopsA, 0.0);
   }
   for (const auto& a : missA) krg<float, float>(ex, a);
+  // they accumulate onto phase A's blocks only, so their place among phase B does not matter
+  for (const auto& a : pdiag) krg_pairdiag_gemm(ex, a, bp.pdws);
   if (nB) {
     hipMemcpyAsync(bp.jobs + nA, jobsB.data(), nB * sizeof(KrgJob), hipMemcpyHostToDevice, ex.stream);
     krg_persistent_launch(ex, bp.jobs + nA, (int)nB, totB, bp.counter, flopsB, 0.0);
