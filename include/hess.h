@@ -169,9 +169,10 @@ hess_status hess_workspace_size(hess_ctx* ctx, int op, const hess_mlp* m, const 
  * prec: HESS_P_F64, HESS_P_F32 or HESS_P_F32_SPLIT (HESS_P_BF16 -> HESS_E_UNSUPPORTED).
  * With FP32 operands the workspace also holds the block between a layer's weights and
  * the previous layer's weights as one product (N T_m T_{m+1} + 8 T_m T_{m+1} (T_{m-1} + 1)
- * floats, where that stays within 2 GiB).  With HESS_P_F32_SPLIT it also holds the first
- * qualifying layer inputs split into BF16 parts (about 6 N (T_{m-1} + 1) bytes, for
- * layers whose inputs plus bias pad to a multiple of 32 and at least 128). */
+ * floats, where that stays within 2 GiB).  With HESS_P_F32_SPLIT it also holds one
+ * layer's inputs at a time split into BF16 parts, sized for the largest layer that
+ * qualifies (inputs plus bias padded to a multiple of 32 and at least 128): about
+ * 6 N (T_{m-1} + 1) bytes. */
 hess_status hess_exact(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int prec,
                        void* H, void* ws, size_t ws_bytes);
 
