@@ -47,16 +47,23 @@ __global__ __launch_bounds__(256) void jt_bf16_kernel(JtArgs a) {
       }
     }
   }
-#pragma unroll 4
-  for (int t = 0; t < 16; ++t) {
-    const int64_t n = n0 + nb + t;
-    float v = 0.f;
-    if (lay >= 0 && n < a.N) {
-      const float d = a.delta[lay][n * a.ld_delta[lay] + i];
-      const float x = a.abar[lay][n * a.ld_abar[lay] + j];
-      v = d * x;
+  // all 16 examples' loads issued before any product (full unroll: 32 loads in flight)
+  float dv[16], xv[16];
+  if (lay >= 0) {
+    const float* dl = a.delta[lay] + i;
+    const float* xl = a.abar[lay] + j;
+    const int64_t ldd = a.ld_delta[lay], ldx = a.ld_abar[lay];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int64_t n = min(n0 + nb + t, a.N - 1);  // clamped in-range read; zeroed below
+      dv[t] = dl[n * ldd];
+      xv[t] = xl[n * ldx];
     }
-    tile[pp][nb + t] = (__bf16)v;
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const bool ok = lay >= 0 && n0 + nb + t < a.N;
+    tile[pp][nb + t] = (__bf16)(ok ? dv[t] * xv[t] : 0.f);
   }
   __syncthreads();
   // phase 2: write 64 rows x 128 bytes, 16 bytes per thread
