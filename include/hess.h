@@ -68,7 +68,8 @@ typedef enum { HESS_F64 = 0, HESS_F32 = 1 } hess_dtype;
  *                (x = h + m + l, each part the round-to-nearest-even BF16 of the remainder;
  *                products h h, h m, m h, h l, l h, m m), which keeps FP32-level error.
  *                hess_hvp, hess_hvp_prepare, hess_exact_cols and the matrix-free operator
- *                of hess_topk_eig accept it too (their FP32 GEMMs take split products);
+ *                of hess_topk_eig accept it too (their FP32 GEMMs take split products,
+ *                except contractions of at most 128 terms, which use FP32 MFMAs);
  *                hess_batched does not. */
 typedef enum { HESS_P_F64 = 0, HESS_P_F32 = 1, HESS_P_BF16 = 2, HESS_P_F32_SPLIT = 3 } hess_prec;
 

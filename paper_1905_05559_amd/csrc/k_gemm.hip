@@ -313,7 +313,11 @@ void launch(Exec& ex, const GemmArgs<T>& g) {
   dim3 grid((unsigned)xcd_grid(nt), (unsigned)g.batch);
   if (!launch_ok(ex)) return;
   const double b = (double)g.batch;
-  const int tok = prof_begin(ex, sizeof(T) == 8 ? "gemm_f64" : (ex.split ? "gemm_bf16x6" : "gemm_f32"),
+  // split products for FP32 under ex.split, except short contractions (K <= 128), which
+  // keep the FP32 MFMA tile: the split form pads K to chunks of 32 and its six products
+  // and splits cost more than they save there
+  const bool split = sizeof(T) == 4 && ex.split && g.K > 128;
+  const int tok = prof_begin(ex, sizeof(T) == 8 ? "gemm_f64" : (split ? "gemm_bf16x6" : "gemm_f32"),
                              2.0 * g.M * g.N * g.K * b,
                              (double)(g.M * g.K + g.K * g.N + g.M * g.N) * sizeof(T) * b);
   const int64_t lim = 0x7fffff00;
@@ -321,7 +325,7 @@ void launch(Exec& ex, const GemmArgs<T>& g) {
                    extent_bytes(g.M, g.K, g.sam, g.sak, sizeof(T)) < lim &&
                    extent_bytes(g.N, g.K, g.sbn, g.sbk, sizeof(T)) < lim;
   if constexpr (sizeof(T) == 4) {
-    if (ex.split) {  // FP32 products from split-BF16 MFMAs: tiles of BM x BN/2 (register budget)
+    if (split) {  // FP32 products from split-BF16 MFMAs: tiles of BM x BN/2 (register budget)
       constexpr int SBN = BN / 2;
       const int64_t stn = (g.N + SBN - 1) / SBN, snt = tm * stn;
       const dim3 sgrid((unsigned)xcd_grid(snt), (unsigned)g.batch);
