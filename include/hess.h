@@ -188,7 +188,8 @@ hess_status hess_opg(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int p
 
 /* Hessian-vector products for B directions (paper, Sec. 5.1 and Appendix A.1):
  * HV[b,:] = H V[b,:].  V, HV: device, B x P row-major (direction-contiguous), FP64
- * for HESS_P_F64 else FP32.  prec: HESS_P_F64 or HESS_P_F32. */
+ * for HESS_P_F64 else FP32.  prec: HESS_P_F64, HESS_P_F32 or HESS_P_F32_SPLIT
+ * (HESS_P_BF16 -> HESS_E_UNSUPPORTED). */
 hess_status hess_hvp(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int prec,
                      int64_t B, const void* V, void* HV, void* ws, size_t ws_bytes);
 
@@ -240,8 +241,9 @@ hess_status hess_hvp_release(hess_hvp_op* op);
 /* Columns col0 .. col0 + ncols - 1 of the exact H (paper, Sec. 5.1: the Hessian-vector
  * product with the j-th unit vector is column j of H), computed as HVPs with basis
  * directions in blocks of up to 512 columns.  Hcols: device, P x ncols row-major, FP64
- * for HESS_P_F64 else FP32.  prec: HESS_P_F64 or HESS_P_F32.  Errors: HESS_E_SHAPE if
- * the column range is empty or leaves [0, P); otherwise as hess_hvp. */
+ * for HESS_P_F64 else FP32.  prec: HESS_P_F64, HESS_P_F32 or HESS_P_F32_SPLIT.
+ * Errors: HESS_E_SHAPE if the column range is empty or leaves [0, P); otherwise as
+ * hess_hvp. */
 hess_status hess_exact_cols(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int prec,
                             int64_t col0, int64_t ncols, void* Hcols, void* ws, size_t ws_bytes);
 
@@ -250,7 +252,8 @@ typedef struct {
   int32_t source;       /* 0 = matrix-free operator from (m, d); 1 = dense symmetric M */
   const void* M;        /* source == 1: device, P x P row-major symmetric */
   int32_t M_dtype;      /* source == 1: hess_dtype of M */
-  int32_t prec;         /* source == 0: hess_prec of the operator (HESS_P_F64 / HESS_P_F32) */
+  int32_t prec;         /* source == 0: hess_prec of the operator (HESS_P_F64, HESS_P_F32 or
+                           HESS_P_F32_SPLIT) */
   int64_t P;            /* source == 1: order of M (m may be NULL) */
   int64_t oversample;   /* block size b = roundup(K + oversample, 16); default 10 if < 0 */
   int32_t max_iter;     /* cap on subspace iterations (default 200 if <= 0) */
@@ -338,6 +341,10 @@ typedef struct {
   double* s;             /* PREDVAR: nq outputs; CURVATURE: nq or nq x P outputs; device FP64 */
   int32_t curv_mode;     /* CURVATURE: hess_curv_mode (the model gives P) */
   double lam_tilde;      /* CURVATURE: full-rank level */
+  int32_t fault_launch;  /* test hook, 0 = off: n > 0 makes this request's n-th kernel launch
+                            report HESS_E_DEVICE without launching (HESS_OPT_FAULT_AFTER on the
+                            slot's context for this request only); such a request is never
+                            coalesced with others */
 } hess_request;
 
 hess_status hess_server_create(hess_server** srv, int device, int n_slots, void* pool, size_t pool_bytes,

@@ -55,7 +55,7 @@ class HessRequest(C.Structure):
     _fields_ = [("kind", C.c_int32), ("model", HessMlp), ("data", HessData), ("H", C.c_void_p), ("G", C.c_void_p),
                 ("K", C.c_int64), ("lam", C.c_void_p), ("Q", C.c_void_p), ("tol", C.c_double), ("seed", C.c_uint64),
                 ("delta", C.c_double), ("nq", C.c_int64), ("Xq", C.c_void_p), ("cls", C.c_void_p), ("s", C.c_void_p),
-                ("curv_mode", C.c_int32), ("lam_tilde", C.c_double)]
+                ("curv_mode", C.c_int32), ("lam_tilde", C.c_double), ("fault_launch", C.c_int32)]
 
 
 class HessProfEntry(C.Structure):

@@ -432,10 +432,12 @@ class Server:
         self._keep = {}
 
     def submit(self, kind: str, model: MLP, X=None, Y=None, H=None, G=None, K=0, lam=None, Q=None, tol=1e-5,
-               seed=0, delta=0.0, Xq=None, cls=None, s=None, curv_mode=None, lam_tilde=0.0) -> int:
+               seed=0, delta=0.0, Xq=None, cls=None, s=None, curv_mode=None, lam_tilde=0.0,
+               fault_launch: int = 0) -> int:
         """Queue one request.  kind "curvature": lam, Q (K pairs), Xq = nq x P FP64 vectors,
         s = outputs (nq for the quadratic forms, nq x P for the products), curv_mode one of
-        CURV_MODES, lam_tilde the full-rank level."""
+        CURV_MODES, lam_tilde the full-rank level.  fault_launch > 0 (test hook) makes the
+        request's n-th kernel launch report HESS_E_DEVICE without launching it."""
         r = L.HessRequest()
         r.kind = self.REQ[kind]
         m = model.struct()
@@ -463,6 +465,7 @@ class Server:
                 raise ValueError("curvature requests take contiguous FP64 vectors Xq (nq x P)")
             r.curv_mode = CURV_MODES[curv_mode] if isinstance(curv_mode, str) else int(curv_mode)
             r.lam_tilde = float(lam_tilde)
+        r.fault_launch = int(fault_launch)
         keep += [H, G, lam, Q, Xq, cls, s, X, Y]
         rid = C.c_uint64()
         st = self.lib.hess_server_submit(self.h, C.byref(r), C.byref(rid))

@@ -158,6 +158,7 @@ hess_status footprint(hess_ctx* ctx, const Req* q, int64_t nq_total, size_t* byt
 bool same_query_target(const Req* a, const Req* b) {
   const hess_request &x = a->r, &y = b->r;
   if (x.kind != HESS_REQ_PREDVAR || y.kind != HESS_REQ_PREDVAR) return false;
+  if (x.fault_launch > 0 || y.fault_launch > 0) return false;
   if (x.K != y.K || x.lambda != y.lambda || x.Q != y.Q || x.delta != y.delta) return false;
   const hess_mlp &m = a->model.view, &n = b->model.view;
   if (m.L != n.L || m.dtype != n.dtype) return false;
@@ -288,6 +289,8 @@ void worker(hess_server* s, int slot) {
     }
     hess_status st;
     char* ws = s->pool + off;
+    const int32_t fault = grp[0]->r.fault_launch;
+    if (fault > 0) hess_set_option(ctx, HESS_OPT_FAULT_AFTER, fault - 1);
     switch (grp[0]->r.kind) {
       case HESS_REQ_FULL: st = run_full(ctx, grp[0], ws, bytes); break;
       case HESS_REQ_TOPK: st = run_topk(ctx, grp[0], ws, bytes); break;
@@ -302,6 +305,7 @@ void worker(hess_server* s, int slot) {
       }
       default: st = run_predvar_group(ctx, stream, grp, ws, bytes); break;
     }
+    if (fault > 0) hess_set_option(ctx, HESS_OPT_FAULT_AFTER, -1);
     const auto t_end = clock_t_::now();
     {
       std::lock_guard<std::mutex> lk(s->mu);

@@ -1,8 +1,14 @@
-"""GPU tests of the serving core: every result is the same alone and in the mix."""
+"""GPU tests of the serving core: every result is the same alone and in the mix, and
+every served result agrees with the FP64 oracle at its path's tolerance (FP64 damped
+queries and curvature operators 1e-10; FP32 H and OPG 1e-5; FP32 top-k eigenpairs within
+the solver tolerance plus the FP32 operator error, Sec. 4.1 / 5.3)."""
 import numpy as np
 import pytest
 import torch
 
+from oracle import eig as oeig
+from oracle import mlp
+from oracle import predvar as opv
 from paper_1905_05559_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -96,6 +102,58 @@ def test_mix_equals_alone(api):
     assert stats["completed"] == len(ids) and stats["failed"] == 0
     assert sum(1 for o in outs if o[0] == "curvature") == len(curv)
     srv.close()
+
+    # ---- every served result against the FP64 oracle ----
+    om = mlp.model_from(wr.T, wr.acts, wr.W, wr.b)
+    lam_h, Q_h = lam.cpu().numpy(), Q.cpu().numpy()
+    lpd_h = lam_pd.cpu().numpy()
+    worst = {}
+    for kind, j, out in outs:
+        if kind == "predvar":
+            Xq, cls = preds[j]
+            Xn = Xq.cpu().numpy().astype(np.float64)
+            c = cls.cpu().numpy() if cls is not None else opv.default_classes(om, Xn)
+            ref = opv.predvar_dense(lam_h, Q_h, delta, opv.logit_grad(om, Xn, c))
+            e = relf(out.cpu().numpy(), ref)
+            tol = 1e-10
+        elif kind == "curvature":
+            mode, V, lt, _ = curv[j]
+            Vn = V.cpu().numpy()
+            f = {"low_quad": lambda x: oeig.low_rank_quadratic(lpd_h, Q_h, x),
+                 "full_quad": lambda x: oeig.full_rank_quadratic(lpd_h, Q_h, x, lt),
+                 "low_apply": lambda x: oeig.low_rank_apply(lpd_h, Q_h, x),
+                 "full_apply": lambda x: oeig.full_rank_apply(lpd_h, Q_h, x, lt),
+                 "full_inverse": lambda x: oeig.full_rank_inverse_apply(lpd_h, Q_h, x, lt)}[mode]
+            ref = np.array([f(x) for x in Vn])
+            e = relf(out.cpu().numpy(), ref)
+            tol = 1e-10
+            kind = "curvature_" + mode
+        elif kind == "full":
+            w = others[j]
+            o2 = mlp.model_from(w.T, w.acts, w.W, w.b)
+            Xo, Yo = w.X.astype(np.float64), w.Y.astype(np.float64)
+            eH = relf(out[0].double().cpu().numpy(), mlp.hessian(o2, Xo, Yo))
+            eG = relf(out[1].double().cpu().numpy(), mlp.opg(o2, Xo, Yo))
+            e, tol = max(eH, eG), 1e-5
+        else:
+            w = others[j]
+            o2 = mlp.model_from(w.T, w.acts, w.W, w.b)
+            Href = mlp.hessian(o2, w.X.astype(np.float64), w.Y.astype(np.float64))
+            lref, _ = oeig.topk_eigh(Href, 4)
+            l2, q2 = out[0].cpu().numpy(), out[1].cpu().numpy()
+            # residual against the exact H: solver tolerance plus the FP32 operator error
+            bound = 1e-5 * abs(lref[0]) + 1e-5 * np.linalg.norm(Href)
+            res = oeig.residuals(lambda B: Href @ B, l2, q2)
+            assert res.max() <= bound, (j, res, bound)
+            e, tol = float(np.abs(l2 - lref).max()), bound
+        worst[kind] = max(worst.get(kind, 0.0), e)
+        assert e <= tol, (kind, j, e, tol)
+    print("served results vs the FP64 oracle (worst error per kind): %s"
+          % {k: "%.2e" % v for k, v in worst.items()}, flush=True)
+
+
+def relf(A, R):
+    return float(np.linalg.norm(np.asarray(A) - R) / np.linalg.norm(R))
 
 
 def test_budget_rejection(api):
