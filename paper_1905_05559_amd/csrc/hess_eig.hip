@@ -1105,11 +1105,19 @@ extern "C" hess_status hess_topk_eig(hess_ctx* ctx, const hess_mlp* mlp, const h
     double a = theta[e.b - 1];
     if (!(a > lb)) a = lb + 0.1 * (rho - lb);
     const double c = 0.5 * (a + lb), hw = 0.5 * (a - lb);
+    // The filter grows the top of the spectrum by about T_m(mu_1), mu_1 = (rho - c) / hw,
+    // against at most 1 on [lb, a].  A large growth (a narrow interval far below rho, as
+    // for the OPG with its small trailing eigenvalues) would push the block's wanted
+    // directions near a below the FP64 rounding of the leading ones, and the
+    // orthonormalisation would lose them; so the degree keeps T_m(mu_1) below about 1e8.
+    const double mu1 = (rho - c) / hw;
+    const int deg = mu1 > 1.0 ? std::max(2, std::min(degree, (int)std::floor(std::log(2e8) / std::acosh(mu1))))
+                              : degree;
     if (launch_ok(ex))
       hipLaunchKernelGGL(k_axpbypcz, dim3(grid_for(nb)), dim3(TPB), 0, ex.stream, 1.0 / hw, e.MX, -c / hw, e.X,
                          0.0, nullptr, nb, e.Y);
     hipMemcpyAsync(e.Yp, e.X, nb * sizeof(double), hipMemcpyDeviceToDevice, ex.stream);
-    for (int j = 1; j < degree; ++j) {
+    for (int j = 1; j < deg; ++j) {
       apply_op(r, r.gc, e.Y, e.Z);
       ++applies;
       // Z <- 2 (Z - c Y) / hw - Yp ; then rotate (Yp, Y) <- (Y, Z)

@@ -81,3 +81,68 @@ def test_batched_model_distribution_subset(api):
             e = _relf(Hb.double().cpu().numpy()[:, cols], ref)
             print("batch model %s P=%d N=%d: sampled H relF %.2e" % (w.T, w.P, w.N, e), flush=True)
             assert e <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Verification subset of the 256-network distribution: the 4 smallest and the 4
+# largest networks by P plus 8 seeded others, checked against FP64 oracle references
+# written by tests/golden/make_batched_golden.py (diagonal 64 x 64 blocks exactly,
+# whole 64-column blocks through a 32-row Gaussian sketch).
+# ---------------------------------------------------------------------------
+
+import os  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batched_cfg4_subset.npz")
+
+
+def _sketch(P, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal((32, P))
+
+
+def test_batched_distribution_verification_subset(api):
+    g = np.load(GOLDEN)
+    models = [int(m) for m in g["models"]]
+    ws = {m: workloads.batched_model(m) for m in models}
+    Ps = sorted(ws[m].P for m in ws)
+    assert len(models) == 16 and max(Ps) > 80000
+    # waves whose outputs (H and OPG, FP32) stay within about 120 GB of HBM
+    waves, cur, used = [], [], 0
+    for m in sorted(models, key=lambda m: ws[m].P):
+        b = 2 * 4 * ws[m].P ** 2
+        if cur and used + b > 120e9:
+            waves.append(cur)
+            cur, used = [], 0
+        cur.append(m)
+        used += b
+    waves.append(cur)
+    worst = 0.0
+    for wave in waves:
+        devs = [_dev(api, ws[m]) for m in wave]
+        print("wave of %d networks, P = %s" % (len(wave), [ws[m].P for m in wave]), flush=True)
+        Hs, Gs = api.hess_batched([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs])
+        torch.cuda.synchronize()
+        for m, (model, X, Y), Hb, Gb in zip(wave, devs, Hs, Gs):
+            w = ws[m]
+            S = _sketch(w.P, 9000 + m)
+            for bi in range(2):
+                key = "m%d_b%d" % (m, bi)
+                c0, c1 = (int(c) for c in g[key + "_cols"])
+                for tag, M in (("H", Hb), ("G", Gb)):
+                    cols = M[:, c0:c1].double().cpu().numpy()
+                    ed = _relf(cols[c0:c1, :], g[key + "_%s_diag" % tag])
+                    es = _relf(S @ cols, g[key + "_%s_sketch" % tag])
+                    worst = max(worst, ed, es)
+                    print("  model %3d P=%6d N=%4d %s[:, %d:%d]  diag relF %.2e  sketch relF %.2e"
+                          % (m, w.P, w.N, tag, c0, c1, ed, es), flush=True)
+                    assert ed <= 1e-5 and es <= 1e-5, (m, tag, bi, ed, es)
+        # the largest network of the wave also through the single-network calls: bitwise equal
+        model, X, Y = devs[-1]
+        Hs1 = api.hess_exact(model, X, Y, "f32")
+        assert torch.equal(Hs[-1], Hs1)
+        del Hs1
+        Gs1 = api.hess_opg(model, X, Y, "f32")
+        assert torch.equal(Gs[-1], Gs1)
+        del Hs, Gs, Gs1, devs
+        torch.cuda.empty_cache()
+    print("verification subset: worst relF %.2e over %d networks" % (worst, len(models)), flush=True)
