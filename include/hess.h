@@ -213,6 +213,18 @@ typedef enum {
 hess_status hess_curvature(hess_ctx* ctx, int mode, int64_t K, int64_t P, const double* lambda, const double* Q,
                            double lam_tilde, int64_t nx, const double* X, double* out, void* ws, size_t ws_bytes);
 
+/* hess_curvature without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same modes, arguments, results and errors as hess_curvature, computed by
+ * the same kernels; the scratch (2 nx K + nx doubles, 256-byte aligned per array) lives
+ * in a library-owned 16 MiB device array, one per device, held until the process ends.
+ * HESS_E_WORKSPACE if 2 nx K + nx doubles exceed it (e.g. nx K above about 1.04e6).
+ * The call allocates nothing.  Every call on a device shares that device's array:
+ * calls that overlap on one device (other host threads, other contexts) race and must
+ * be serialised by the caller. */
+hess_status hess_curvature_noalloc(hess_ctx* ctx, int mode, int64_t K, int64_t P, const double* lambda,
+                                   const double* Q, double lam_tilde, int64_t nx, const double* X, double* out);
+
 /* Eigen-decomposition of a dense symmetric n x n FP64 matrix on the device, the
  * projected problem of the Lanczos eigensolver (paper, Sec. 5.3), 1 <= n <= 512.
  * A: device, row-major with row stride lda >= n, used as (A + A^T) / 2, not modified.

@@ -26,7 +26,7 @@ EXPORTS = (
     "hess_topk_eig", "hess_predvar", "hess_profile_read", "hess_profile_reset", "hess_batched",
     "hess_server_create", "hess_server_submit", "hess_server_wait", "hess_server_stats", "hess_server_destroy",
     "hess_mfma_stream_rate", "hess_hvp_prepare", "hess_hvp_apply", "hess_hvp_release", "hess_curvature",
-    "hess_syev",
+    "hess_syev", "hess_curvature_noalloc",
 )
 
 
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
         "hess_hvp_apply": (st, [vp, vp, i64, vp, vp]),
         "hess_hvp_release": (st, [vp]),
         "hess_curvature": (st, [vp, C.c_int, i64, i64, vp, vp, C.c_double, i64, vp, vp, vp, C.c_size_t]),
+        "hess_curvature_noalloc": (st, [vp, C.c_int, i64, i64, vp, vp, C.c_double, i64, vp, vp]),
         "hess_syev": (st, [vp, i64, vp, i64, vp, vp, vp, C.c_size_t]),
         "hess_topk_eig": (st, [vp, pm, pd, i64, C.POINTER(HessEigOpts), vp, vp,
                                C.POINTER(HessEigInfo), vp, C.c_size_t]),

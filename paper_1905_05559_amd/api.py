@@ -244,6 +244,27 @@ def curvature(mode: str, lam: torch.Tensor, Q: torch.Tensor, X: torch.Tensor, la
     return out
 
 
+def curvature_noalloc(mode: str, lam: torch.Tensor, Q: torch.Tensor, X: torch.Tensor,
+                      lam_tilde: Optional[float] = None, out: Optional[torch.Tensor] = None,
+                      ctx: Optional[Context] = None) -> torch.Tensor:
+    """As curvature(), through hess_curvature_noalloc: no workspace argument, the library's
+    own device scratch (include/hess.h).  `out` should be passed by callers that must not
+    allocate; lam, Q and X must already be contiguous FP64 device tensors."""
+    ctx = ctx or default_context()
+    K, P = int(Q.shape[0]), int(Q.shape[1])
+    nx = int(X.shape[0])
+    if not (lam.is_contiguous() and Q.is_contiguous() and X.is_contiguous()):
+        raise ValueError("curvature_noalloc takes contiguous lam, Q and X")
+    lt = float(lam[-1].item()) if lam_tilde is None else float(lam_tilde)
+    m = CURV_MODES[mode]
+    if out is None:
+        shape = (nx,) if m in (0, 1) else (nx, P)
+        out = torch.empty(shape, dtype=torch.float64, device=X.device)
+    ctx._check(ctx.lib.hess_curvature_noalloc(ctx.h, m, K, P, lam.data_ptr(), Q.data_ptr(), lt, nx,
+                                              X.data_ptr(), out.data_ptr()))
+    return out
+
+
 def syev(A: torch.Tensor, ctx: Optional[Context] = None):
     """Eigen-decomposition of a symmetric FP64 device matrix (n <= 512; rows may be
     strided): returns (w descending (n,), U (n x n), row j = eigenvector j), see

@@ -5,6 +5,7 @@
 //   x^T H~~ x.  All FP64: the projections and back-projections are MFMA GEMMs.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "api_internal.h"
@@ -82,6 +83,39 @@ hess_status curvature_workspace(hess_ctx* ctx, int64_t K, int64_t nx, size_t* by
   return HESS_OK;
 }
 
+namespace {
+
+// Library-owned scratch of hess_curvature_noalloc: projections, coefficients and row
+// norms (2 nx K + nx doubles, each array 256-byte aligned).  Every device the library
+// runs on holds its own copy until the process ends.  In host code `scratch` is only a
+// stand-in for the symbol; its device address comes from hipGetSymbolAddress, once per
+// device, and only that address is handed to kernels.
+constexpr size_t kCurvScratchBytes = size_t(16) << 20;
+__device__ __align__(256) unsigned char scratch[kCurvScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (the device is current); nullptr on failure.
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+hess_status curvature_run(Exec& ex, int mode, int64_t K, int64_t P, const double* lambda, const double* Q,
+                          double lam_tilde, int64_t nx, const double* X, double* out, void* ws, size_t ws_bytes);
+
+}  // namespace
 }  // namespace hs
 
 using namespace hs;
@@ -92,6 +126,33 @@ extern "C" hess_status hess_curvature(hess_ctx* ctx, int mode, int64_t K, int64_
   Exec ex;
   hess_status s = begin(ctx, ex);
   if (s != HESS_OK) return s;
+  return curvature_run(ex, mode, K, P, lambda, Q, lam_tilde, nx, X, out, ws, ws_bytes);
+}
+
+extern "C" hess_status hess_curvature_noalloc(hess_ctx* ctx, int mode, int64_t K, int64_t P, const double* lambda,
+                                              const double* Q, double lam_tilde, int64_t nx, const double* X,
+                                              double* out) {
+  Exec ex;
+  hess_status s = begin(ctx, ex);
+  if (s != HESS_OK) return s;
+  size_t need = 0;
+  if ((s = curvature_workspace(ctx, K, nx, &need)) != HESS_OK) return s;
+  if (need > kCurvScratchBytes)
+    return fail(ctx, HESS_E_WORKSPACE, "hess_curvature_noalloc: " + std::to_string(need) +
+                                           " B of scratch needed (2 nx K + nx doubles), above the library's " +
+                                           std::to_string(kCurvScratchBytes) + " B");
+  void* ptr = scratch_address(ctx->device);
+  if (!ptr) return fail(ctx, HESS_E_DEVICE, "hess_curvature_noalloc: hipGetSymbolAddress of the scratch failed");
+  return curvature_run(ex, mode, K, P, lambda, Q, lam_tilde, nx, X, out, ptr, kCurvScratchBytes);
+}
+
+namespace hs {
+namespace {
+
+hess_status curvature_run(Exec& ex, int mode, int64_t K, int64_t P, const double* lambda, const double* Q,
+                          double lam_tilde, int64_t nx, const double* X, double* out, void* ws, size_t ws_bytes) {
+  hess_ctx* ctx = ex.ctx;
+  hess_status s;
   if (mode < 0 || mode > 4) return fail(ctx, HESS_E_ARG, "unknown curvature mode");
   if (K < 1 || P < K || nx < 1) return fail(ctx, HESS_E_SHAPE, "need 1 <= K <= P and nx >= 1");
   if (!lambda || !Q || !X || !out) return fail(ctx, HESS_E_ARG, "NULL pointer");
@@ -133,3 +194,6 @@ extern "C" hess_status hess_curvature(hess_ctx* ctx, int mode, int64_t K, int64_
   gemm_rm<double>(ex, false, false, nx, P, K, 1.0, coef, K, Q, P, 1.0, out, P);
   return finish(ex, "hess_curvature");
 }
+
+}  // namespace
+}  // namespace hs
