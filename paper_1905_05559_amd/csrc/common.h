@@ -199,6 +199,11 @@ void transpose(Exec& ex, const double* src, int64_t rows, int64_t cols, int64_t 
                int64_t ldd);
 template <typename TD>
 void cast_copy(Exec& ex, const double* src, TD* dst, int64_t n);
+// dst[0 .. n) = 0 (a kernel, so that it may also run inside captured sequences); n may be 0
+template <typename TD>
+void fill_zero(Exec& ex, TD* dst, int64_t n);
+// examples per chunk of the split-product tile; its FP32 row sources hold whole chunks
+constexpr int64_t kSrcRows = 32;
 // strided 2D cast: dst[r*ldd + c] = (TD) src[r*lds + c]
 template <typename TD>
 void cast_2d(Exec& ex, const double* src, int64_t rows, int64_t cols, int64_t lds, TD* dst, int64_t ldd);

@@ -374,13 +374,19 @@ void plan_opg_ops(Arena& ar, const Model& m, int64_t N, const Prep& p, OpgBufs<T
   const int L = m.L;
   b.abar.assign(L + 1, nullptr);
   b.delta.assign(L + 1, nullptr);
-  for (int l = 1; l <= L - 1; ++l) b.abar[l] = ar.take<T>(N * p.lda[l]);
+  // abar rows are padded to whole chunks of kSrcRows examples (zero past N): the
+  // split-product tile copies the rows of a chunk with the row offset outside the buffer
+  // range check
+  for (int l = 1; l <= L - 1; ++l) b.abar[l] = ar.take<T>(rup(N, kSrcRows) * p.lda[l]);
   for (int l = 2; l <= L; ++l) b.delta[l] = ar.take<T>(N * m.T[l - 1]);
 }
 
 template <typename T>
 void cast_ops(Exec& ex, const Model& m, const Prep& p, OpgBufs<T>& b) {
-  for (int l = 1; l <= m.L - 1; ++l) cast_copy<T>(ex, p.Abar[l], b.abar[l], p.N * p.lda[l]);
+  for (int l = 1; l <= m.L - 1; ++l) {
+    cast_copy<T>(ex, p.Abar[l], b.abar[l], p.N * p.lda[l]);
+    fill_zero<T>(ex, b.abar[l] + p.N * p.lda[l], (rup(p.N, kSrcRows) - p.N) * p.lda[l]);
+  }
   for (int l = 2; l <= m.L; ++l) cast_copy<T>(ex, p.delta[l], b.delta[l], p.N * m.T[l - 1]);
 }
 

@@ -274,6 +274,16 @@ template <typename TD>
 void cast_2d(Exec& ex, const double* src, int64_t rows, int64_t cols, int64_t lds, TD* dst, int64_t ldd_) {
   LAUNCH(k_cast2d<TD>, rows * cols, src, rows, cols, lds, dst, ldd_);
 }
+template <typename TD>
+__global__ void k_zero(TD* dst, int64_t n) {
+  GRID_STRIDE(i, n) { dst[i] = TD(0); }
+}
+template <typename TD>
+void fill_zero(Exec& ex, TD* dst, int64_t n) {
+  if (n > 0) LAUNCH(k_zero<TD>, n, dst, n);
+}
+template void fill_zero<float>(Exec&, float*, int64_t);
+template void fill_zero<double>(Exec&, double*, int64_t);
 template void cast_copy<float>(Exec&, const double*, float*, int64_t);
 template void cast_copy<double>(Exec&, const double*, double*, int64_t);
 template void cast_2d<float>(Exec&, const double*, int64_t, int64_t, int64_t, float*, int64_t);

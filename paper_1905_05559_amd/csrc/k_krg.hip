@@ -464,20 +464,13 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
     const __amdgpu_buffer_rsrc_t rb = rsrc_of(a.c.src + n0 * a.c.ld, (int64_t)kv * a.c.ld);
     if constexpr (C::BPS) {
       // voffA[m] = voffA[m & 1] + (m / 2) rows of the source: the row part is uniform and
-      // rides in the scalar offset while the chunk is full.  The buffer range check leaves
-      // the scalar offset out, so a partial chunk (the last one, or a slice's last) puts the
-      // row into the per-lane offset: every row at or past kv then reads as zero.
-      if (kv == DKC) {
+      // rides in the scalar offset.  The buffer range check leaves the scalar offset out,
+      // so the rows of a partial chunk past N are read from the source's padding: the row
+      // sources of this tile hold whole chunks of 32 examples, zero past N (cast_ops).
 #pragma unroll
-        for (int m = 0; m < KH; ++m)
-          copy_lds_s(ra, S + ((DKC / 4) * wave + (m >> 1)) * SM::ALD + (m & 1) * 64, voffA[m & 1],
-                     (int)((m >> 1) * a.r.ld * 4));
-      } else {
-#pragma unroll
-        for (int m = 0; m < KH; ++m)
-          copy_lds(ra, S + ((DKC / 4) * wave + (m >> 1)) * SM::ALD + (m & 1) * 64,
-                   voffA[m & 1] + (int)((m >> 1) * a.r.ld * 4));
-      }
+      for (int m = 0; m < KH; ++m)
+        copy_lds_s(ra, S + ((DKC / 4) * wave + (m >> 1)) * SM::ALD + (m & 1) * 64, voffA[m & 1],
+                   (int)((m >> 1) * a.r.ld * 4));
     } else {
 #pragma unroll
       for (int m = 0; m < KH; ++m) copy_lds(ra, S + ((DKC / 4) * wave + (m >> 1)) * SM::ALD + (m & 1) * 64, voffA[m]);
