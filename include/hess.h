@@ -69,8 +69,8 @@ typedef enum { HESS_F64 = 0, HESS_F32 = 1 } hess_dtype;
  *                products h h, h m, m h, h l, l h, m m), which keeps FP32-level error.
  *                hess_hvp, hess_hvp_prepare, hess_exact_cols and the matrix-free operator
  *                of hess_topk_eig accept it too (their FP32 GEMMs take split products,
- *                except contractions of at most 128 terms, which use FP32 MFMAs);
- *                hess_batched does not. */
+ *                except contractions of at most 128 terms, which use FP32 MFMAs), and so
+ *                does hess_batched. */
 typedef enum { HESS_P_F64 = 0, HESS_P_F32 = 1, HESS_P_BF16 = 2, HESS_P_F32_SPLIT = 3 } hess_prec;
 
 typedef struct {
@@ -310,13 +310,18 @@ hess_status hess_predvar(hess_ctx* ctx, const hess_mlp* m, int64_t K, const doub
                          const int32_t* cls, double* s, void* ws, size_t ws_bytes);
 
 /* Exact H and/or OPG of M independent networks with their own data sets (widths and
- * N may differ), FP32 (prec must be HESS_P_F32).  Same definitions as hess_exact and
- * hess_opg (paper, Sec. 3); the per-example passes of each network run as small
- * launches and all P x P tiles of all networks go through one persistent launch
- * (plus one for the cross-layer term of H).  models, datas: host arrays of M entries;
- * H, G: host arrays of M device pointers (P_i x P_i FP32 row-major); H or G (the array)
- * may be NULL, and so may single entries, to skip that output.  Results equal those of
- * the single-network calls bitwise. */
+ * N may differ), FP32 output; prec HESS_P_F32 or HESS_P_F32_SPLIT.  Same definitions as
+ * hess_exact and hess_opg (paper, Sec. 3); the per-example passes of each network run as
+ * small launches and all P x P tiles of all networks go through persistent launches, one
+ * per tile units bound (2, 5 or 9 units of a layer per 128-wide tile side), plus one per
+ * bound for the cross-layer term of H.  With HESS_OPT_AUTOTUNE the tile configuration of
+ * the first-phase launches is tuned like the single-network contractions.
+ * models, datas: host arrays of M entries; H, G: host arrays of M device pointers
+ * (P_i x P_i FP32 row-major); H or G (the array) may be NULL, and so may single entries,
+ * to skip that output.  With HESS_P_F32 the results equal those of the single-network
+ * calls bitwise; with HESS_P_F32_SPLIT every block takes split products with the columns
+ * split in the tile (the single-network calls read some blocks' columns pre-split) and
+ * holds the FP32 tolerance. */
 hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* models, const hess_data* datas, int prec,
                          void* const* H, void* const* G, void* ws, size_t ws_bytes);
 

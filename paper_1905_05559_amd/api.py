@@ -404,8 +404,9 @@ def hess_predvar(model: MLP, lam: torch.Tensor, Q: torch.Tensor, delta: float, X
 
 
 def hess_batched(models: List[MLP], Xs: List[torch.Tensor], Ys: List[torch.Tensor], with_H: bool = True,
-                 with_G: bool = True, outs_H=None, outs_G=None, ctx: Optional[Context] = None):
-    """Exact H and/or OPG (FP32) of several networks in one call, see hess_batched in include/hess.h.
+                 with_G: bool = True, outs_H=None, outs_G=None, ctx: Optional[Context] = None, prec: str = "f32"):
+    """Exact H and/or OPG (FP32; prec "f32" or "f32_split") of several networks in one call,
+    see hess_batched in include/hess.h.
 
     Returns (list of H or None, list of G or None)."""
     ctx = ctx or default_context()
@@ -426,9 +427,9 @@ def hess_batched(models: List[MLP], Xs: List[torch.Tensor], Ys: List[torch.Tenso
     hp = (C.c_void_p * M)(*[h.data_ptr() for h in Hs]) if Hs is not None else None
     gp = (C.c_void_p * M)(*[g.data_ptr() for g in Gs]) if Gs is not None else None
     nb = C.c_size_t()
-    ctx._check(ctx.lib.hess_workspace_size(ctx.h, L.OP["batched"], ms, ds, L.PREC["f32"], M, None, C.byref(nb)))
+    ctx._check(ctx.lib.hess_workspace_size(ctx.h, L.OP["batched"], ms, ds, L.PREC[prec], M, None, C.byref(nb)))
     ws = ctx.workspace(nb.value)
-    ctx._check(ctx.lib.hess_batched(ctx.h, M, ms, ds, L.PREC["f32"], hp, gp, ws.data_ptr(), ws.numel()))
+    ctx._check(ctx.lib.hess_batched(ctx.h, M, ms, ds, L.PREC[prec], hp, gp, ws.data_ptr(), ws.numel()))
     return Hs, Gs
 
 

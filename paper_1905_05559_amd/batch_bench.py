@@ -1,12 +1,14 @@
 """Exact H + OPG of the 256-network batch on one GPU, in HBM-budgeted waves.
 
-Usage: python -m paper_1905_05559_amd.batch_bench [--models M] [--budget-gb B]
+Usage: python -m paper_1905_05559_amd.batch_bench [--models M] [--budget-gb B] [--prec f32|f32_split]
+       [--autotune]
 
 Networks m = 0..M-1 follow the batch distribution (seed 4000 + m: T_1 ~ U{8..128},
 1-2 tanh hidden layers of width U{16..256}, T_L ~ U{2..20}, N ~ U{100..5000}).  Their
 H and OPG (FP32, P_m^2 entries each) total more than the device holds, so networks are
 packed into waves whose outputs plus workspace fit in the budget; each wave is one
-hess_batched call (one persistent contraction launch over all its networks' tiles).
+hess_batched call (persistent contraction launches, one per tile units bound, over all its
+networks' tiles).
 Outputs are views into one buffer allocated once; after a wave, every output is
 reduced to (trace, Frobenius norm) and the buffer is reused by the next wave.  Prints one JSON line with P^2-entries/s and algorithmic TFLOP/s.
 """
@@ -26,10 +28,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--models", type=int, default=256)
     ap.add_argument("--budget-gb", type=float, default=160.0)
+    ap.add_argument("--prec", default="f32", choices=["f32", "f32_split"])
+    ap.add_argument("--autotune", action="store_true")
     args = ap.parse_args()
     dev = "cuda:0"
     ctx = api.Context(0)
     ctx.set_option("profile", 1)
+    if args.autotune:
+        ctx.set_option("autotune", 1)
     nets = []
     t = time.perf_counter()
     for m in range(args.models):
@@ -65,7 +71,8 @@ def main():
             outs.append((pool[off:off + P2].view(n[0], n[0]), pool[off + P2:off + 2 * P2].view(n[0], n[0])))
             off += 2 * P2
         Hs, Gs = api.hess_batched([n[2] for n in wv], [n[3] for n in wv], [n[4] for n in wv],
-                                  outs_H=[o[0] for o in outs], outs_G=[o[1] for o in outs], ctx=ctx)
+                                  outs_H=[o[0] for o in outs], outs_G=[o[1] for o in outs], ctx=ctx,
+                                  prec=args.prec)
         torch.cuda.synchronize()
         t_call = time.perf_counter() - tw
         red = [(float(torch.trace(H)), float(H.norm()), float(torch.trace(G)), float(G.norm())) for H, G in zip(Hs, Gs)]
@@ -80,9 +87,14 @@ def main():
         print("wave %d: %d networks (P <= %d) in %.2f s" % (i, len(wv), wv[0][0], dt), file=sys.stderr, flush=True)
     total = time.perf_counter() - t0
     prof = ctx.profile()
-    out = {"metric": "batched exact-H+OPG P^2-entries/s", "networks": len(nets), "waves": len(waves),
+    out = {"metric": "batched exact-H+OPG P^2-entries/s", "prec": args.prec, "autotune": args.autotune,
+           "networks": len(nets), "waves": len(waves),
            "seconds": total, "p2_entries_per_s": entries / total, "algorithmic_tflops": flops / total / 1e12,
-           "persistent_launch_tflops": {k: v["flops"] / v["ms"] / 1e9 for k, v in prof.items() if "persistent" in k},
+           "persistent_launch_tflops": {k: v["flops"] / v["ms"] / 1e9 for k, v in prof.items()
+                                        if "persistent" in k and v["ms"] > 0},
+           "persistent_launches_overall_tflops": (sum(v["flops"] for k, v in prof.items() if "persistent" in k)
+                                                  / max(1e-9, sum(v["ms"] for k, v in prof.items()
+                                                                  if "persistent" in k)) / 1e9),
            "kernel_ms": {k: round(v["ms"], 1) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])},
            "wave_detail": summary}
     print(json.dumps(out), flush=True)

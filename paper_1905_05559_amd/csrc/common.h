@@ -145,10 +145,16 @@ struct KrgJob {
   int32_t mode;            // KRG_* weight mode
 };
 int64_t krg_tiles(const KrgArgs<float, float>& a, int64_t* tiles_c);
+// Units-per-tile bound of a contraction's tile (2, 5 or 9); the persistent launch runs
+// jobs of one bound together.
+int krg_persistent_maxu(const KrgArgs<float, float>& a);
 // Whether a contraction can run in the persistent launch (its copy offsets fit 32 bits).
 bool krg_persistent_fits(const KrgArgs<float, float>& a);
-void krg_persistent_launch(Exec& ex, const KrgJob* jobs_dev, int njobs, int64_t total, unsigned long long* counter,
-                           double flops, double bytes);
+// One persistent launch over jobs of one units-per-tile bound maxu; counters: 8 device
+// words (zeroed by the launch).  cfg: 0 = (16 examples, 2 stages), 1 = (16, 3),
+// 2 = (32, 2), 3 = split-BF16 products (32, 2); every FP32 configuration gives the same bits.
+void krg_persistent_launch(Exec& ex, const KrgJob* jobs_dev, int njobs, int64_t total, unsigned long long* counters,
+                           double flops, double bytes, int maxu, int cfg);
 // Tile-configuration variants (tuning and tests): register-staged tile 1..4 = (K chunk,
 // LDS stages) in {(16,1), (16,2), (32,1), (32,2)}; FP32 LDS-staged tile 5 = (32, 2),
 // 6 = (16, 3); split products 7 = columns split in the tile, 8 = pre-split columns

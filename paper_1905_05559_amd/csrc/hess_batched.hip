@@ -73,7 +73,7 @@ size_t plan_batched(Arena& ar, int64_t M, const hess_mlp* models, const hess_dat
   bp.scratch_bytes = scratch;
   (void)ar.take<char>(scratch);  // scratch at offset 0
   bp.flags = ar.take<int>(2 * M);
-  bp.counter = ar.take<unsigned long long>(1);
+  bp.counter = ar.take<unsigned long long>(8);
   bp.njobs_max = nj;
   bp.jobs = ar.take<KrgJob>(nj);
   int64_t pf = 0;
@@ -128,7 +128,9 @@ extern "C" hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* mo
   Exec ex;
   hess_status st = begin(ctx, ex);
   if (st != HESS_OK) return st;
-  if (prec != HESS_P_F32) return fail(ctx, HESS_E_UNSUPPORTED, "batched: FP32 only");
+  if (prec != HESS_P_F32 && prec != HESS_P_F32_SPLIT)
+    return fail(ctx, HESS_E_UNSUPPORTED, "batched: HESS_P_F32 or HESS_P_F32_SPLIT");
+  ex.split = prec == HESS_P_F32_SPLIT;
   if (M < 1 || !models || !datas || (!H && !G)) return fail(ctx, HESS_E_ARG, "batched: bad arguments");
   Arena probe(nullptr);
   BPlan bp0;
@@ -165,16 +167,22 @@ extern "C" hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* mo
     }
   }
 
-  // per-network passes and FP32 factors; tile jobs
-  std::vector<KrgJob> jobsA, jobsB;
-  double flopsA = 0, flopsB = 0;
+  // per-network passes and FP32 factors; tile jobs, grouped by units-per-tile bound
+  // (2, 5, 9): one persistent launch per phase and bound, so that every launch reserves
+  // only the LDS its tiles need
+  constexpr int NU = 3;
+  auto ugrp = [](int maxu) { return maxu == 2 ? 0 : (maxu == 5 ? 1 : 2); };
+  std::vector<KrgJob> jobsA[NU], jobsB[NU];
+  double flopsA[NU] = {0, 0, 0}, flopsB[NU] = {0, 0, 0};
   std::vector<KrgArgs<float, float>> missA, missB;  // contractions too large for the persistent launch
   std::vector<KrgArgs<float, float>> pdiag;         // pair-diagonal blocks done as one product
-  auto add = [&](std::vector<KrgJob>& v, const KrgArgs<float, float>& a, double& flops) {
+  auto add = [&](bool phaseA, const KrgArgs<float, float>& a) {
     if (!krg_persistent_fits(a)) {
-      (&v == &jobsA ? missA : missB).push_back(a);
+      (phaseA ? missA : missB).push_back(a);
       return;
     }
+    const int g = ugrp(krg_persistent_maxu(a));
+    std::vector<KrgJob>& v = phaseA ? jobsA[g] : jobsB[g];
     KrgJob j;
     j.a = a;
     j.mode = a.wmode;
@@ -186,7 +194,7 @@ extern "C" hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* mo
     const double Pr = (double)a.r.n_units * a.r.len, Pc = (double)a.c.n_units * a.c.len;
     double e = a.symmetric ? Pr * (Pr + 1) / 2 : Pr * Pc;
     if (a.wmode == KRG_PAIR_DIAG) e = (double)std::min(a.r.n_units, a.c.n_units) * a.r.len * a.c.len;
-    flops += 2.0 * a.N * e;
+    (phaseA ? flopsA : flopsB)[g] += 2.0 * a.N * e;
   };
   for (int64_t i = 0; i < M; ++i) {
     BNet& b = bp.nets[i];
@@ -239,7 +247,7 @@ extern "C" hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* mo
           g.wts = nullptr;
           g.ldw = 0;
           g.out = Gi;
-          add(jobsA, g, flopsA);
+          add(true, g);
         }
         if (Hi) {
           KrgArgs<float, float> h = a;
@@ -247,7 +255,7 @@ extern "C" hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* mo
           h.wts = b.G[mm][l];
           h.ldw = N;
           h.out = Hi;
-          add(jobsA, h, flopsA);
+          add(true, h);
           if (l > mm) {
             KrgArgs<float, float> t2 = h;
             KrgSide<float> r;
@@ -276,27 +284,59 @@ extern "C" hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* mo
               t2.wmode = KRG_PAIR_FULL;
               t2.wts = b.K[mm][l - 1];
             }
-            add(jobsB, t2, flopsB);
+            add(false, t2);
           }
         }
       }
   }
-  // upload both job lists and run the persistent launches (phase A, then B)
-  const int64_t nA = (int64_t)jobsA.size(), nB = (int64_t)jobsB.size();
-  int64_t tc = 0;
-  const int64_t totA = nA ? jobsA.back().first + krg_tiles(jobsA.back().a, &tc) : 0;
-  const int64_t totB = nB ? jobsB.back().first + krg_tiles(jobsB.back().a, &tc) : 0;
-  if (nA) {
-    hipMemcpyAsync(bp.jobs, jobsA.data(), nA * sizeof(KrgJob), hipMemcpyHostToDevice, ex.stream);
-    krg_persistent_launch(ex, bp.jobs, (int)nA, totA, bp.counter, flopsA, 0.0);
+  // upload the job lists and run the persistent launches (phase A, then B)
+  const int u_of[NU] = {2, 5, 9};
+  std::vector<KrgJob> all;
+  int64_t offA[NU], offB[NU];
+  for (int g = 0; g < NU; ++g) {
+    offA[g] = (int64_t)all.size();
+    all.insert(all.end(), jobsA[g].begin(), jobsA[g].end());
+  }
+  for (int g = 0; g < NU; ++g) {
+    offB[g] = (int64_t)all.size();
+    all.insert(all.end(), jobsB[g].begin(), jobsB[g].end());
+  }
+  if (!all.empty())
+    hipMemcpyAsync(bp.jobs, all.data(), all.size() * sizeof(KrgJob), hipMemcpyHostToDevice, ex.stream);
+  auto total_of = [](const std::vector<KrgJob>& v) {
+    int64_t tc = 0;
+    return v.empty() ? (int64_t)0 : v.back().first + krg_tiles(v.back().a, &tc);
+  };
+  // Phase A writes its blocks (no accumulation), so its configuration may be tuned: probes
+  // on the first two device rounds of tiles write outputs that the full launch overwrites.
+  // Every FP32 configuration gives the same bits.  Split products take (32, 2).
+  for (int g = 0; g < NU; ++g) {
+    const int64_t tot = total_of(jobsA[g]);
+    if (tot == 0) continue;
+    int cfg = ex.split ? 3 : 0;
+    if (!ex.split && ctx->autotune) {
+      static const int64_t slots = [] {
+        int dev = 0, cus = 256;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        return 2 * (int64_t)std::max(cus, 1);
+      }();
+      const int64_t ntp = std::min(tot, 2 * slots);
+      auto lg = [](int64_t v) { int b = 0; while (v > 1) { v >>= 1; ++b; } return b; };
+      const std::string key = "krg_f32_persistent u" + std::to_string(u_of[g]) + " tiles2^" + std::to_string(lg(tot));
+      static const char* const cfgs[3] = {"chunk16x2", "chunk16x3", "chunk32x2"};
+      cfg = autotune_pick(ex, key, 3, cfgs, [&](int i) {
+        krg_persistent_launch(ex, bp.jobs + offA[g], (int)jobsA[g].size(), ntp, bp.counter, 0.0, 0.0, u_of[g], i);
+      });
+    }
+    krg_persistent_launch(ex, bp.jobs + offA[g], (int)jobsA[g].size(), tot, bp.counter, flopsA[g], 0.0, u_of[g], cfg);
   }
   for (const auto& a : missA) krg<float, float>(ex, a);
   // they accumulate onto phase A's blocks only, so their place among phase B does not matter
   for (const auto& a : pdiag) krg_pairdiag_gemm(ex, a, bp.pdws);
-  if (nB) {
-    hipMemcpyAsync(bp.jobs + nA, jobsB.data(), nB * sizeof(KrgJob), hipMemcpyHostToDevice, ex.stream);
-    krg_persistent_launch(ex, bp.jobs + nA, (int)nB, totB, bp.counter, flopsB, 0.0);
-  }
+  for (int g = 0; g < NU; ++g)
+    krg_persistent_launch(ex, bp.jobs + offB[g], (int)jobsB[g].size(), total_of(jobsB[g]), bp.counter, flopsB[g],
+                          0.0, u_of[g], ex.split ? 3 : 0);
   for (const auto& a : missB) krg<float, float>(ex, a);
   return finish(ex, "hess_batched");
 }

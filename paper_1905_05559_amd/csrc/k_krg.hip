@@ -829,23 +829,50 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && KC == 16) ? 2 : 1) void krg
   krg_tile<T, TOut, WMODE, SYM, KC, STAGES>(a, t, tiles_c, smem);
 }
 
-// Persistent form for many contractions (several networks): every workgroup takes the
-// next tile from a global counter until all tiles of all jobs are done; a tile's job is
-// found by binary search over the jobs' first-tile offsets.  Each tile is computed by
-// exactly one workgroup, so results do not depend on the schedule; the tile code is
-// the single-launch one, so results equal single-contraction launches bitwise.
-constexpr int PERSIST_LDS = std::max(std::max(DmaSmem<KRG_PAIR_FULL, 9>::SIZE, DmaSmem<KRG_RANK1, 9>::SIZE),
-                                     DmaSmem<KRG_PAIR_DIAG, 9>::SIZE) * 4;
+// Persistent form for many contractions (several networks): every workgroup takes tiles
+// from global counters until all tiles of all jobs are done; a tile's job is found by
+// binary search over the jobs' first-tile offsets.  The tile range is cut into 8
+// contiguous parts, one per XCD (workgroups reach the XCDs round-robin): a workgroup
+// takes the next tile of its own XCD's part and, once that part is exhausted, helps the
+// following parts, so neighbouring tiles (which share operand panels) mostly run in one
+// XCD's L2.  One kernel instance per units-per-tile bound and tile configuration; each
+// tile is computed by exactly one workgroup with the single-launch tile code, so results
+// do not depend on the schedule and equal single-contraction launches bitwise.
+template <int MAXU, class C>
+constexpr int persist_lds_bytes() {
+  return std::max(std::max(DmaSmem<KRG_PAIR_FULL, MAXU, C>::SIZE, DmaSmem<KRG_RANK1, MAXU, C>::SIZE),
+                  DmaSmem<KRG_PAIR_DIAG, MAXU, C>::SIZE) * 4;
+}
+constexpr int PERSIST_PARTS = 8;
 
+template <int MAXU, class C>
 __global__ __launch_bounds__(256, 2) void krg_persistent(const KrgJob* jobs, int njobs, int64_t total,
-                                                         unsigned long long* counter) {
+                                                         unsigned long long* counters) {
   __shared__ int64_t tsh;
+  const int64_t per = (total + PERSIST_PARTS - 1) / PERSIST_PARTS;
+  const int home = (int)(blockIdx.x % PERSIST_PARTS);
+  int visited = 0;  // parts found exhausted (thread 0 only)
   for (;;) {
-    if (threadIdx.x == 0) tsh = (int64_t)atomicAdd(counter, 1ull);
+    if (threadIdx.x == 0) {
+      int64_t t = -1;
+      while (visited < PERSIST_PARTS) {
+        const int x = (home + visited) % PERSIST_PARTS;
+        const int64_t lo = x * per, hi = min(total, lo + per);
+        if (lo < hi) {
+          const int64_t k = (int64_t)atomicAdd(&counters[x], 1ull);
+          if (lo + k < hi) {
+            t = lo + k;
+            break;
+          }
+        }
+        ++visited;
+      }
+      tsh = t;
+    }
     __syncthreads();
     const int64_t t = tsh;
     __syncthreads();
-    if (t >= total) break;
+    if (t < 0) break;
     int lo = 0, hi = njobs - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) / 2;
@@ -854,17 +881,19 @@ __global__ __launch_bounds__(256, 2) void krg_persistent(const KrgJob* jobs, int
     const KrgJob& J = jobs[lo];
     const int64_t lt = t - J.first;
     switch (J.mode * 2 + (J.a.symmetric ? 1 : 0)) {
-      case KRG_RANK1 * 2 + 0: krg_tile_dma<KRG_RANK1, false, 9>(J.a, lt, J.tiles_c, dma_smem); break;
-      case KRG_RANK1 * 2 + 1: krg_tile_dma<KRG_RANK1, true, 9>(J.a, lt, J.tiles_c, dma_smem); break;
-      case KRG_PAIR_FULL * 2 + 0: krg_tile_dma<KRG_PAIR_FULL, false, 9>(J.a, lt, J.tiles_c, dma_smem); break;
-      case KRG_PAIR_FULL * 2 + 1: krg_tile_dma<KRG_PAIR_FULL, true, 9>(J.a, lt, J.tiles_c, dma_smem); break;
-      default: krg_tile_dma<KRG_PAIR_DIAG, false, 9>(J.a, lt, J.tiles_c, dma_smem); break;
+      case KRG_RANK1 * 2 + 0: krg_tile_dma<KRG_RANK1, false, MAXU, C>(J.a, lt, J.tiles_c, dma_smem); break;
+      case KRG_RANK1 * 2 + 1: krg_tile_dma<KRG_RANK1, true, MAXU, C>(J.a, lt, J.tiles_c, dma_smem); break;
+      case KRG_PAIR_FULL * 2 + 0: krg_tile_dma<KRG_PAIR_FULL, false, MAXU, C>(J.a, lt, J.tiles_c, dma_smem); break;
+      case KRG_PAIR_FULL * 2 + 1: krg_tile_dma<KRG_PAIR_FULL, true, MAXU, C>(J.a, lt, J.tiles_c, dma_smem); break;
+      default: krg_tile_dma<KRG_PAIR_DIAG, false, MAXU, C>(J.a, lt, J.tiles_c, dma_smem); break;
     }
     __syncthreads();
   }
 }
 
-__global__ void k_zero_counter(unsigned long long* c) { *c = 0ull; }
+__global__ void k_zero_counters(unsigned long long* c) {
+  if (threadIdx.x < PERSIST_PARTS) c[threadIdx.x] = 0ull;
+}
 
 __global__ __launch_bounds__(256) void k_fill_zero(float* __restrict__ p, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1039,7 +1068,6 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
   prof_end(ex, tok);
 }
 
-bool krg_persistent_fits(const KrgArgs<float, float>& a) { return dma_fits(a, 9); }
 
 // ---- pair-diagonal contraction as one product ----
 namespace {
@@ -1127,23 +1155,51 @@ int64_t krg_tiles(const KrgArgs<float, float>& a, int64_t* tiles_c) {
   return a.symmetric ? tr * (tr + 1) / 2 : tr * tc;
 }
 
-void krg_persistent_launch(Exec& ex, const KrgJob* jobs_dev, int njobs, int64_t total, unsigned long long* counter,
-                           double flops, double bytes) {
-  if (total <= 0) return;
-  if (!launch_ok(ex)) return;
-  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, ex.stream, counter);
-  int dev = 0, cus = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int64_t grid = std::min<int64_t>(total, (int64_t)cus * 2);
-  const int tok = prof_begin(ex, "krg_f32_persistent", flops, bytes);
+namespace {
+template <int MAXU, class C>
+void persistent_one(Exec& ex, const KrgJob* jobs_dev, int njobs, int64_t total, unsigned long long* counters,
+                    int64_t grid) {
+  constexpr int bytes = persist_lds_bytes<MAXU, C>();
   static const bool attr = [] {
-    (void)hipFuncSetAttribute((const void*)krg_persistent, hipFuncAttributeMaxDynamicSharedMemorySize, PERSIST_LDS);
+    (void)hipFuncSetAttribute((const void*)krg_persistent<MAXU, C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              bytes);
     return true;
   }();
   (void)attr;
-  hipLaunchKernelGGL(krg_persistent, dim3((unsigned)grid), dim3(256), PERSIST_LDS, ex.stream, jobs_dev, njobs, total,
-                     counter);
+  hipLaunchKernelGGL((krg_persistent<MAXU, C>), dim3((unsigned)grid), dim3(256), bytes, ex.stream, jobs_dev, njobs,
+                     total, counters);
+}
+template <class C>
+void persistent_u(Exec& ex, int maxu, const KrgJob* jobs_dev, int njobs, int64_t total, unsigned long long* counters,
+                  int64_t grid) {
+  if (maxu == 2) persistent_one<2, C>(ex, jobs_dev, njobs, total, counters, grid);
+  else if (maxu == 5) persistent_one<5, C>(ex, jobs_dev, njobs, total, counters, grid);
+  else persistent_one<9, C>(ex, jobs_dev, njobs, total, counters, grid);
+}
+}  // namespace
+
+int krg_persistent_maxu(const KrgArgs<float, float>& a) { return dma_maxu(std::min(a.r.pad, a.c.pad)); }
+
+bool krg_persistent_fits(const KrgArgs<float, float>& a) { return dma_fits(a, krg_persistent_maxu(a)); }
+
+void krg_persistent_launch(Exec& ex, const KrgJob* jobs_dev, int njobs, int64_t total, unsigned long long* counters,
+                           double flops, double bytes, int maxu, int cfg) {
+  if (total <= 0) return;
+  if (!launch_ok(ex)) return;
+  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, ex.stream, counters);
+  if (!launch_ok(ex)) return;
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t grid = std::min<int64_t>(xcd_grid(total), xcd_grid((int64_t)cus * 2));
+  std::string label = std::string(cfg == 3 ? "krg_bf16x6_persistent_u" : "krg_f32_persistent_u") + std::to_string(maxu);
+  const int tok = prof_begin(ex, label.c_str(), flops, bytes);
+  switch (cfg) {
+    case 1: persistent_u<DmaCfg<16, 3>>(ex, maxu, jobs_dev, njobs, total, counters, grid); break;
+    case 2: persistent_u<DmaCfg<32, 2>>(ex, maxu, jobs_dev, njobs, total, counters, grid); break;
+    case 3: persistent_u<DmaCfg<32, 2, true>>(ex, maxu, jobs_dev, njobs, total, counters, grid); break;
+    default: persistent_u<DmaDefault>(ex, maxu, jobs_dev, njobs, total, counters, grid); break;
+  }
   prof_end(ex, tok);
 }
 

@@ -146,3 +146,38 @@ def test_batched_distribution_verification_subset(api):
         del Hs, Gs, Gs1, devs
         torch.cuda.empty_cache()
     print("verification subset: worst relF %.2e over %d networks" % (worst, len(models)), flush=True)
+
+
+def test_batched_split_products_and_autotune(api):
+    # split-BF16 products in the persistent launches: against the oracle at the FP32
+    # tolerance and against the single-network split calls; autotuned FP32 configuration:
+    # bitwise equal to the default
+    ws = [workloads.mlp_gaussian(T, a, N, s, dtype="float32") for T, a, N, s in NETS]
+    ws += [workloads.batched_model(m) for m in (58, 76, 148)]
+    devs = [_dev(api, w) for w in ws]
+    args = ([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs])
+    Hs, Gs = api.hess_batched(*args, prec="f32_split")
+    for w, (model, X, Y), Hb, Gb in zip(ws, devs, Hs, Gs):
+        om = mlp.model_from(w.T, w.acts, w.W, w.b)
+        Xo, Yo = w.X.astype(np.float64), w.Y.astype(np.float64)
+        eh = _relf(Hb.double().cpu().numpy(), mlp.hessian(om, Xo, Yo, block=256))
+        eg = _relf(Gb.double().cpu().numpy(), mlp.opg(om, Xo, Yo))
+        H1 = api.hess_exact(model, X, Y, "f32_split")
+        G1 = api.hess_opg(model, X, Y, "f32_split")
+        same = torch.equal(Hb, H1) and torch.equal(Gb, G1)
+        d1 = max(_relf(Hb.double().cpu().numpy(), H1.double().cpu().numpy()),
+                 _relf(Gb.double().cpu().numpy(), G1.double().cpu().numpy()))
+        print("batched split %-20s H relF %.2e  OPG relF %.2e  vs single split: bitwise %s (relF %.1e)"
+              % (w.T, eh, eg, same, d1), flush=True)
+        assert eh <= 1e-5 and eg <= 1e-5 and d1 <= 1e-5
+        assert np.array_equal(Hb.cpu().numpy(), Hb.cpu().numpy().T)
+    ref = api.hess_batched(*args)
+    ctx = api.Context(0)
+    ctx.set_option("autotune", 1)
+    tuned = api.hess_batched(*args, ctx=ctx)
+    rep = ctx.autotune_report()
+    print("autotune report:\n" + rep, flush=True)
+    assert "krg_f32_persistent" in rep
+    for a, b in zip(ref[0] + ref[1], tuned[0] + tuned[1]):
+        assert torch.equal(a, b)
+    ctx.close()
