@@ -17,8 +17,12 @@ value = 2 P^2 / step time  ("exact-H+OPG P^2-entries/s": P^2 entries of each mat
 with the per-phase times, HVPs/s and query rates reported beside it.
 
 The JSON line also carries the roofline of the dominant kernel (algorithmic flops
-per launch / average launch time from HIP events on the library's stream) and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+per launch / average launch time from HIP events on the library's stream), the
+FP64 CPU oracle timed on a bounded sample of the same workload, and (after the timed
+steps, skipped with --no-serving) the served-vs-plain request mix of
+paper_1905_05559_amd/serve_bench.py against this network and the last step's
+eigenpairs: p50/p99 per request type and throughput at saturation and at 80 % of each
+mode's saturation, plus the alone-vs-mix consistency check.
 """
 from __future__ import annotations
 
@@ -130,6 +134,8 @@ def main():
                          "configurations, MFMA stream rate), e.g. for a profile of the steps alone")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the served-vs-plain request mix after the timed steps")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -179,6 +185,7 @@ def main():
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     phase_ms = {"opg": 0.0, "exact_H": 0.0, "topk": 0.0, "hvp": 0.0, "predvar": 0.0}
     eig_info = {}
+    pairs = {}
 
     def step(record=False):
         s = ctx.stream
@@ -199,6 +206,7 @@ def main():
             for i, k in enumerate(("opg", "exact_H", "topk", "hvp", "predvar")):
                 phase_ms[k] += ev[i].elapsed_time(ev[i + 1])
             eig_info.update(info)
+        pairs["lam"], pairs["Q"] = lam, Q
 
     for i in range(args.warmup):
         t = time.perf_counter()
@@ -336,6 +344,16 @@ def main():
     del H, G, V, HV
     ctx.release_workspace()
     torch.cuda.empty_cache()
+    if not args.no_serving and args.workload == "mnist":
+        # Served vs plain request mix against the resident network and the eigenpairs of the
+        # last step (outside the timed steps); see paper_1905_05559_amd/serve_bench.py
+        from paper_1905_05559_amd import serve_bench
+        t = time.perf_counter()
+        world = serve_bench.World(model, X, Y, pairs["lam"], pairs["Q"])
+        out["serving"] = serve_bench.measure(world, log=log)
+        del world
+        torch.cuda.empty_cache()
+        log("serving block took %.1f s" % (time.perf_counter() - t))
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(w, 20.0)
