@@ -74,6 +74,24 @@ struct HFactors {
 };
 void compute_factors(Exec& ex, const Model& m, int64_t N, Prep& p, HFactors& f, int mm);
 
+// A matrix split in three BF16 planes (h, m, l; x = h + m + l): part x of element (r, k)
+// at p[x * plane + r * ld + k]; k runs over kpad (a multiple of 32), zero past the true
+// length.  See k_gemm_ps.hip.
+struct SplitMat {
+  __bf16* p = nullptr;
+  int64_t ld = 0, plane = 0, kpad = 0;
+};
+// Takes the planes of a rows x kpad split matrix from an arena.
+SplitMat take_split(Arena& ar, int64_t rows, int64_t kpad);
+// dst = split of src (rows x K, row stride lds), k padded with zeros to dst.kpad.
+void split_rows(Exec& ex, const float* src, int64_t rows, int64_t K, int64_t lds, SplitMat dst);
+// dst = split of src^T (src: R x Cc, row stride lds; dst: Cc rows, k over R padded to dst.kpad).
+void split_transpose(Exec& ex, const float* src, int64_t R, int64_t Cc, int64_t lds, SplitMat dst);
+// C (M x N, row stride ldc) = alpha A B^T + beta C with A (M x K) and B (N x K) pre-split,
+// K = A.kpad = B.kpad; FP32 accumulation of the six BF16 products of each product.
+void gemm_presplit(Exec& ex, int64_t M, int64_t N, const SplitMat& A, const SplitMat& B, float alpha, float beta,
+                   float* C, int64_t ldc);
+
 // Buffers of the R-operator (dense-direction) passes; see hess_hvp.hip.
 template <typename T>
 struct HvpBufs {
@@ -82,9 +100,15 @@ struct HvpBufs {
   T* S = nullptr;
   T* Tacc = nullptr;  // T_l x (B T_{l-1}) partial of the delta^T R{A} accumulation
   int64_t Nc = 0, Bmax = 0;
+  // split products (FP32 only): the shared operands of the large products split once,
+  // per call (Vps: Vbar^(l)) or per chunk of examples (Aps: abar^(l-1) rows, ATps: its
+  // transpose, RDps: R{delta^(l)} transposed, one layer at a time); empty where unused
+  bool split = false;
+  std::vector<SplitMat> Vps, Aps, ATps;
+  SplitMat RDps;
 };
 template <typename T>
-size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h);
+size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, bool split = false);
 template <typename T>
 void hvp_setup(Exec& ex, const Model& m, int64_t N, Prep& p, HvpBufs<T>& h);
 template <typename T>

@@ -428,7 +428,7 @@ static size_t plan_eig(Arena& ar, const Model* m, int64_t N, int64_t P, int64_t 
     if (prec == HESS_P_F64)
       plan_hvp<double>(ar, *m, N, b, e.p, e.hd);
     else
-      plan_hvp<float>(ar, *m, N, b, e.p, e.hf);
+      plan_hvp<float>(ar, *m, N, b, e.p, e.hf, prec == HESS_P_F32_SPLIT);
   }
   return ar.used;
 }

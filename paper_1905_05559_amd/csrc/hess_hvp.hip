@@ -143,8 +143,14 @@ int64_t hvp_chunk(const Model& m, int64_t N, int64_t B, size_t esz) {
 
 }  // namespace
 
+// Products of the sweep that take pre-split operands (split products, FP32): R{Z^(l)} when
+// its contraction (T_{l-1} + 1 inputs) is longer than 128 (shorter ones keep the FP32 MFMA
+// tile), and the accumulation over a chunk of examples when the chunk is.
+static bool presplit_rz(const Model& m, int l) { return m.T[l - 2] + 1 > 128; }
+static bool presplit_acc(int64_t Nc) { return Nc > 128; }
+
 template <typename T>
-size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h) {
+size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, bool split) {
   const int L = m.L;
   plan_prep(ar, m, N, p, false);
   h.abar.assign(L + 1, nullptr);
@@ -181,6 +187,26 @@ size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBuf
   for (int l = 3; l <= L; ++l) tacc = std::max<int64_t>(tacc, m.T[l - 1] * B * m.T[l - 2]);
   h.Tacc = tacc > 0 ? ar.take<T>(tacc) : nullptr;
   h.Bmax = B;
+  h.split = split && sizeof(T) == 4;
+  h.Vps.assign(L + 1, SplitMat());
+  h.Aps.assign(L + 1, SplitMat());
+  h.ATps.assign(L + 1, SplitMat());
+  h.RDps = SplitMat();
+  if (h.split) {
+    int64_t rd_rows = 0;
+    for (int l = 2; l <= L; ++l) {
+      const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
+      if (presplit_rz(m, l)) {
+        h.Vps[l] = take_split(ar, B * Tl, rup(Tin + 1, 32));
+        h.Aps[l] = take_split(ar, h.Nc, rup(Tin + 1, 32));
+      }
+      if (presplit_acc(h.Nc)) {
+        h.ATps[l] = take_split(ar, Tin + 1, rup(h.Nc, 32));
+        rd_rows = std::max(rd_rows, B * Tl);
+      }
+    }
+    if (rd_rows > 0) h.RDps = take_split(ar, rd_rows, rup(h.Nc, 32));
+  }
   return ar.used;
 }
 
@@ -235,6 +261,10 @@ void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<
   }
 
   const T invN = (T)(1.0 / (double)N);
+  if constexpr (sizeof(T) == 4) {  // the direction block, split once for all chunks
+    for (int l = 2; l <= L; ++l)
+      if (h.Vps[l].p) split_rows(ex, h.Vbar[l], B * m.T[l - 1], m.T[l - 2] + 1, m.T[l - 2] + 1, h.Vps[l]);
+  }
   for (int64_t n0 = 0; n0 < N; n0 += h.Nc) {
     const int64_t Nc = std::min(h.Nc, N - n0);
     const T beta_acc = n0 == 0 ? T(0) : T(1);
@@ -242,8 +272,17 @@ void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<
     for (int l = 2; l <= L; ++l) {
       const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
       // R{Z^(l)} = Abar^(l-1) Vbar^T  (N_c x (B T_l)) ...
-      gemm_rm<T>(ex, false, true, Nc, B * Tl, Tin + 1, T(1), h.abar[l - 1] + n0 * p.lda[l - 1], p.lda[l - 1],
-                 h.Vbar[l], Tin + 1, T(0), h.RZ[l], B * Tl);
+      bool done = false;
+      if constexpr (sizeof(T) == 4) {
+        if (h.Vps[l].p) {
+          split_rows(ex, h.abar[l - 1] + n0 * p.lda[l - 1], Nc, Tin + 1, p.lda[l - 1], h.Aps[l]);
+          gemm_presplit(ex, Nc, B * Tl, h.Aps[l], h.Vps[l], 1.f, 0.f, h.RZ[l], B * Tl);
+          done = true;
+        }
+      }
+      if (!done)
+        gemm_rm<T>(ex, false, true, Nc, B * Tl, Tin + 1, T(1), h.abar[l - 1] + n0 * p.lda[l - 1], p.lda[l - 1],
+                   h.Vbar[l], Tin + 1, T(0), h.RZ[l], B * Tl);
       // ... + R{A^(l-1)} W^(l-1)^T  ((N_c B) x T_l)
       if (l >= 3)
         gemm_rm<T>(ex, false, true, Nc * B, Tl, Tin, T(1), h.RA[l - 1], Tin, h.W[l], Tin, T(1), h.RZ[l], Tl);
@@ -269,8 +308,20 @@ void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<
     for (int l = 2; l <= L; ++l) {
       const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
       // R{delta^(l)}^T Abar^(l-1): ((B T_l) x (T_in + 1)), contraction over n
-      gemm_rm<T>(ex, true, false, B * Tl, Tin + 1, Nc, invN, h.RD[l], B * Tl, h.abar[l - 1] + n0 * p.lda[l - 1],
-                 p.lda[l - 1], beta_acc, h.HVbar[l], Tin + 1);
+      bool done = false;
+      if constexpr (sizeof(T) == 4) {
+        if (h.ATps[l].p && presplit_acc(Nc)) {
+          SplitMat a = h.RDps, b = h.ATps[l];
+          a.kpad = b.kpad = rup(Nc, 32);
+          split_transpose(ex, h.RD[l], Nc, B * Tl, B * Tl, a);
+          split_transpose(ex, h.abar[l - 1] + n0 * p.lda[l - 1], Nc, Tin + 1, p.lda[l - 1], b);
+          gemm_presplit(ex, B * Tl, Tin + 1, a, b, invN, beta_acc, h.HVbar[l], Tin + 1);
+          done = true;
+        }
+      }
+      if (!done)
+        gemm_rm<T>(ex, true, false, B * Tl, Tin + 1, Nc, invN, h.RD[l], B * Tl, h.abar[l - 1] + n0 * p.lda[l - 1],
+                   p.lda[l - 1], beta_acc, h.HVbar[l], Tin + 1);
       if (l >= 3) {
         // + delta^(l)^T R{A^(l-1)}_b for all directions at once: R{A} of the chunk is
         // N_c x (B T_in), so this is one T_l x (B T_in) product (rather than B products of
@@ -351,8 +402,8 @@ void jv_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T
 
 template void jv_apply<double>(Exec&, const Model&, int64_t, int64_t, Prep&, HvpBufs<double>&, const double*,
                                int64_t, double*);
-template size_t plan_hvp<float>(Arena&, const Model&, int64_t, int64_t, Prep&, HvpBufs<float>&);
-template size_t plan_hvp<double>(Arena&, const Model&, int64_t, int64_t, Prep&, HvpBufs<double>&);
+template size_t plan_hvp<float>(Arena&, const Model&, int64_t, int64_t, Prep&, HvpBufs<float>&, bool);
+template size_t plan_hvp<double>(Arena&, const Model&, int64_t, int64_t, Prep&, HvpBufs<double>&, bool);
 template void hvp_setup<float>(Exec&, const Model&, int64_t, Prep&, HvpBufs<float>&);
 template void hvp_setup<double>(Exec&, const Model&, int64_t, Prep&, HvpBufs<double>&);
 template void hvp_apply<float>(Exec&, const Model&, int64_t, int64_t, Prep&, HvpBufs<float>&, const float*,
@@ -392,9 +443,10 @@ __global__ void k_cols_from_rows(const T* HV, int64_t B, int64_t P, T* out, int6
 }
 
 template <typename T>
-size_t plan_exact_cols(Arena& ar, const Model& m, int64_t N, int64_t ncols, Prep& p, HvpBufs<T>& h, T*& V, T*& HV) {
+size_t plan_exact_cols(Arena& ar, const Model& m, int64_t N, int64_t ncols, Prep& p, HvpBufs<T>& h, T*& V, T*& HV,
+                       bool split) {
   const int64_t B = std::min(ncols, EXC_B);
-  plan_hvp<T>(ar, m, N, B, p, h);
+  plan_hvp<T>(ar, m, N, B, p, h, split);
   V = ar.take<T>(B * m.P);
   HV = ar.take<T>(B * m.P);
   return ar.used;
@@ -420,11 +472,11 @@ size_t ws_exact_cols(const Model& m, int64_t N, int prec, int64_t ncols) {
   if (prec == HESS_P_F64) {
     HvpBufs<double> h;
     double *V, *HV;
-    return plan_exact_cols<double>(ar, m, N, ncols, p, h, V, HV);
+    return plan_exact_cols<double>(ar, m, N, ncols, p, h, V, HV, false);
   }
   HvpBufs<float> h;
   float *V, *HV;
-  return plan_exact_cols<float>(ar, m, N, ncols, p, h, V, HV);
+  return plan_exact_cols<float>(ar, m, N, ncols, p, h, V, HV, prec == HESS_P_F32_SPLIT);
 }
 
 size_t ws_hvp(const Model& m, int64_t N, int prec, int64_t B) {
@@ -435,7 +487,7 @@ size_t ws_hvp(const Model& m, int64_t N, int prec, int64_t B) {
     return plan_hvp<double>(ar, m, N, B, p, h);
   }
   HvpBufs<float> h;
-  return plan_hvp<float>(ar, m, N, B, p, h);
+  return plan_hvp<float>(ar, m, N, B, p, h, prec == HESS_P_F32_SPLIT);
 }
 
 }  // namespace
@@ -487,7 +539,7 @@ extern "C" hess_status hess_hvp(hess_ctx* ctx, const hess_mlp* mlp, const hess_d
     hvp_apply<double>(ex, m, d->N, B, p, h, static_cast<const double*>(V), m.P, static_cast<double*>(HV));
   } else {
     HvpBufs<float> h;
-    plan_hvp<float>(ar, m, d->N, B, p, h);
+    plan_hvp<float>(ar, m, d->N, B, p, h, prec == HESS_P_F32_SPLIT);
     if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
     run_prep(ex, m, d, p, false);
     hvp_setup<float>(ex, m, d->N, p, h);
@@ -517,14 +569,14 @@ extern "C" hess_status hess_exact_cols(hess_ctx* ctx, const hess_mlp* mlp, const
   if (prec == HESS_P_F64) {
     HvpBufs<double> h;
     double *V, *HV;
-    plan_exact_cols<double>(ar, m, d->N, ncols, p, h, V, HV);
+    plan_exact_cols<double>(ar, m, d->N, ncols, p, h, V, HV, false);
     if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
     run_prep(ex, m, d, p, false);
     run_exact_cols<double>(ex, m, d->N, p, h, V, HV, col0, ncols, static_cast<double*>(Hcols));
   } else {
     HvpBufs<float> h;
     float *V, *HV;
-    plan_exact_cols<float>(ar, m, d->N, ncols, p, h, V, HV);
+    plan_exact_cols<float>(ar, m, d->N, ncols, p, h, V, HV, prec == HESS_P_F32_SPLIT);
     if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
     run_prep(ex, m, d, p, false);
     run_exact_cols<float>(ex, m, d->N, p, h, V, HV, col0, ncols, static_cast<float*>(Hcols));
@@ -566,7 +618,7 @@ extern "C" hess_status hess_hvp_prepare(hess_ctx* ctx, const hess_mlp* mlp, cons
   if (prec == HESS_P_F64) {
     plan_hvp<double>(ar, o->m, d->N, max_B, o->p, o->hd);
   } else {
-    plan_hvp<float>(ar, o->m, d->N, max_B, o->p, o->hf);
+    plan_hvp<float>(ar, o->m, d->N, max_B, o->p, o->hf, prec == HESS_P_F32_SPLIT);
   }
   if ((s = check_inputs(ex, o->m, d, o->p)) != HESS_OK) {
     delete o;
