@@ -120,9 +120,15 @@ const char* hess_last_error(const hess_ctx* ctx);
  * another is at least 3% faster on the sample (contractions that accumulate into their
  * output keep the default); all configurations give bitwise identical results.
  * hess_autotune_report lists the decisions. */
+/* HESS_OPT_FACTOR_BYTES (default 0 = 32 GiB): cap on the bytes of hess_exact's per-example
+ * curvature factors (about sum T_l T_m N doubles per column layer m).  Above it hess_exact
+ * runs the factor computation and the contraction over chunks of examples (a multiple of
+ * 32, at least 32) and accumulates H chunk by chunk, the mini-batch sum of Sec. 5.1; the
+ * workspace then holds one chunk's factors.  Results agree with the one-pass H to FP
+ * rounding (the sum over examples is split at the chunk boundaries). */
 typedef enum {
   HESS_OPT_CHECK_INPUTS = 0, HESS_OPT_HBM_BUDGET = 1, HESS_OPT_FAULT_AFTER = 2, HESS_OPT_PROFILE = 3,
-  HESS_OPT_GRAPHS = 4, HESS_OPT_AUTOTUNE = 5
+  HESS_OPT_GRAPHS = 4, HESS_OPT_AUTOTUNE = 5, HESS_OPT_FACTOR_BYTES = 6
 } hess_opt;
 hess_status hess_set_option(hess_ctx* ctx, int opt, int64_t value);
 

@@ -17,7 +17,8 @@ ACT = {"tanh": 0, "sigmoid": 1, "relu": 2}
 DTYPE = {"float64": 0, "float32": 1}
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "f32_split": 3}
 OP = {"exact": 0, "opg": 1, "hvp": 2, "topk": 3, "predvar": 4, "batched": 5, "exact_cols": 6, "curvature": 7, "syev": 8}
-OPT = {"check_inputs": 0, "hbm_budget": 1, "fault_after": 2, "profile": 3, "graphs": 4, "autotune": 5}
+OPT = {"check_inputs": 0, "hbm_budget": 1, "fault_after": 2, "profile": 3, "graphs": 4, "autotune": 5,
+       "factor_bytes": 6}
 
 # Every symbol include/hess.h declares.
 EXPORTS = (

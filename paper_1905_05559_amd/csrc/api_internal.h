@@ -72,7 +72,7 @@ constexpr int64_t kPairdiagMaxBytes = int64_t(2) << 30;
 struct HFactors {
   std::vector<double*> F, K, G;   // indexed by layer, layout [T_a][T_m][N]
 };
-void compute_factors(Exec& ex, const Model& m, int64_t N, Prep& p, HFactors& f, int mm);
+void compute_factors(Exec& ex, const Model& m, int64_t Nc, int64_t n0, Prep& p, HFactors& f, int mm);
 
 // A matrix split in three BF16 planes (h, m, l; x = h + m + l): part x of element (r, k)
 // at p[x * plane + r * ld + k]; k runs over kpad (a multiple of 32), zero past the true

@@ -213,19 +213,21 @@ constexpr int64_t kSrcRows = 32;
 // strided 2D cast: dst[r*ldd + c] = (TD) src[r*lds + c]
 template <typename TD>
 void cast_2d(Exec& ex, const double* src, int64_t rows, int64_t cols, int64_t lds, TD* dst, int64_t ldd);
-// Curvature-factor helpers on the [T_a][T_m][N] layout (n fastest)
+// Curvature-factor helpers on the [T_a][T_m][N] layout (n fastest, N examples of a chunk);
+// the per-example caches D1T, CT, PT are [T][ldc] (ldc = the full example count), passed
+// already offset to the chunk's first example.
 // F[i2][i][n] = W[i2*ldw + i] * D1T[i][n]
-void factor_first(Exec& ex, const double* W, int64_t T2, int64_t Tm, const double* D1T, int64_t N,
+void factor_first(Exec& ex, const double* W, int64_t T2, int64_t Tm, const double* D1T, int64_t ldc, int64_t N,
                   double* F);
 // K[k][i][n] = D1T[k][n] * F[k][i][n]
-void factor_rowscale(Exec& ex, const double* F, int64_t Tk, int64_t Tm, const double* D1T, int64_t N,
+void factor_rowscale(Exec& ex, const double* F, int64_t Tk, int64_t Tm, const double* D1T, int64_t ldc, int64_t N,
                      double* K);
 // G[k][i][n] = p[k][n] * (F[k][i][n] - sum_k' p[k'][n] F[k'][i][n]); F == nullptr means identity
-void factor_softmax(Exec& ex, const double* F, int64_t TL, int64_t Tm, const double* PT, int64_t N,
+void factor_softmax(Exec& ex, const double* F, int64_t TL, int64_t Tm, const double* PT, int64_t ldc, int64_t N,
                     double* G);
 // G[k][i][n] = D1T[k][n] * G[k][i][n] + CT[k][n] * (F ? F[k][i][n] : (k == i))
 void factor_combine(Exec& ex, double* G, int64_t Tk, int64_t Tm, const double* D1T,
-                    const double* CT, const double* F, int64_t N);
+                    const double* CT, int64_t ldc, const double* F, int64_t N);
 
 }  // namespace hs
 
@@ -255,6 +257,7 @@ struct hess_ctx {
   bool fault_hit = false;
   int graphs = 1;                       // capture repeated operator applications as HIP graphs
   int autotune = 0;                     // time the tile configurations per shape class
+  int64_t factor_cap = 0;               // hess_exact factor-region cap in bytes (0 = default)
   std::vector<std::pair<std::string, int>> tuned;  // shape class -> chosen configuration
   std::string tune_log;                 // one line per decision
   hipStream_t capture_stream = nullptr;  // created on first capture (graphs cannot be captured on the null stream)

@@ -485,14 +485,57 @@ static bool presplit_layer(const Model& m, int mm) {
   return pad % 32 == 0 && pad >= 128;
 }
 
+// Bytes per example of the factor region of hess_exact (max over column layers): the FP64
+// factors, their operand-precision copies and sigma' of the column layer, the pre-split
+// column source and the pair-diagonal product.
+static int64_t factor_bytes_per_example(const Model& m, bool same_type, bool split) {
+  const int L = m.L;
+  int64_t peak = 0;
+  for (int mm = 2; mm <= L; ++mm) {
+    const int64_t Tm = m.T[mm - 1];
+    int64_t d = 0, c = 0;
+    for (int l = mm + 1; l <= L; ++l) d += m.T[l - 1] * Tm;
+    for (int l = mm + 1; l <= L - 1; ++l) d += m.T[l - 1] * Tm;
+    for (int l = mm; l <= L; ++l) d += m.T[l - 1] * Tm;
+    if (!same_type) {
+      for (int l = mm; l <= L; ++l) c += m.T[l - 1] * Tm;
+      for (int l = mm + 1; l <= L - 1; ++l) c += m.T[l - 1] * Tm;
+    }
+    c += Tm;
+    peak = std::max(peak, d * 8 + c * (same_type ? 8 : 4));
+  }
+  int64_t extra = 0;
+  if (!same_type) {
+    for (int mm = 2; mm <= L; ++mm) {
+      if (split && presplit_layer(m, mm)) extra = std::max(extra, 6 * rup(m.T[mm - 2] + 1, 32));
+    }
+    int64_t pd = 0;
+    for (int mm = 2; mm <= L - 1; ++mm) pd = std::max(pd, 4 * m.T[mm - 1] * m.T[mm]);
+    extra += pd;
+  }
+  return peak + extra;
+}
+
+// Examples per chunk of hess_exact: all N when the factor region fits the context's cap
+// (HESS_OPT_FACTOR_BYTES, default kFactorCapDefault), else the largest multiple of 32 that
+// fits (at least 32).  H is then accumulated chunk by chunk (the mini-batch sum of Sec. 5.1).
+constexpr int64_t kFactorCapDefault = int64_t(32) << 30;
+int64_t exact_chunk(const hess_ctx* ctx, const Model& m, int64_t N, bool same_type, bool split) {
+  const int64_t cap = (ctx && ctx->factor_cap > 0) ? ctx->factor_cap : kFactorCapDefault;
+  const int64_t bpe = std::max<int64_t>(1, factor_bytes_per_example(m, same_type, split));
+  if (bpe * N <= cap) return N;
+  return std::min(N, std::max<int64_t>(32, cap / bpe / 32 * 32));
+}
+
 template <typename T>
-size_t plan_exact(const Model& m, int64_t N, void* ws, Prep& p, HOps<T>& ops, std::vector<HFactors>& fac,
+size_t plan_exact(const Model& m, int64_t N, int64_t Nc, void* ws, Prep& p, HOps<T>& ops, std::vector<HFactors>& fac,
                   bool same_type, bool split = false) {
   Arena ar(ws);
   const int L = m.L;
   plan_prep(ar, m, N, p, true);
   if (!same_type) plan_opg_ops<T>(ar, m, N, p, ops.base);
-  // factors are planned per column layer in one reusable region (max over m)
+  // factors of one chunk of Nc examples are planned per column layer in one reusable
+  // region (max over m)
   const size_t base_used = ar.used;
   size_t peak = base_used;
   fac.assign(L + 1, HFactors());
@@ -504,28 +547,28 @@ size_t plan_exact(const Model& m, int64_t N, void* ws, Prep& p, HOps<T>& ops, st
     f.K.assign(L + 1, nullptr);
     f.G.assign(L + 1, nullptr);
     const int64_t Tm = m.T[mm - 1];
-    for (int l = mm + 1; l <= L; ++l) f.F[l] = a2.take<double>(m.T[l - 1] * Tm * N);
-    for (int l = mm + 1; l <= L - 1; ++l) f.K[l] = a2.take<double>(m.T[l - 1] * Tm * N);
-    for (int l = mm; l <= L; ++l) f.G[l] = a2.take<double>(m.T[l - 1] * Tm * N);
+    for (int l = mm + 1; l <= L; ++l) f.F[l] = a2.take<double>(m.T[l - 1] * Tm * Nc);
+    for (int l = mm + 1; l <= L - 1; ++l) f.K[l] = a2.take<double>(m.T[l - 1] * Tm * Nc);
+    for (int l = mm; l <= L; ++l) f.G[l] = a2.take<double>(m.T[l - 1] * Tm * Nc);
     if (!same_type) {
       // operand-precision copies live after the FP64 factors of the same m
-      for (int l = mm; l <= L; ++l) a2.take<T>(m.T[l - 1] * Tm * N);
-      for (int l = mm + 1; l <= L - 1; ++l) a2.take<T>(m.T[l - 1] * Tm * N);
-      a2.take<T>(Tm * N);
+      for (int l = mm; l <= L; ++l) a2.take<T>(m.T[l - 1] * Tm * Nc);
+      for (int l = mm + 1; l <= L - 1; ++l) a2.take<T>(m.T[l - 1] * Tm * Nc);
     }
+    a2.take<T>(Tm * Nc);  // sigma'^(m) of the chunk, [T_m][Nc]
     peak = std::max(peak, a2.used);
   }
   ar.used = peak;
   if (split && !same_type) {  // one region for the pre-split column source, reused per layer
     int64_t dw = 0;
     for (int mm = 2; mm <= L; ++mm)
-      if (presplit_layer(m, mm)) dw = std::max(dw, bsplit_dwords(N, (int32_t)rup(m.T[mm - 2] + 1, 16)));
+      if (presplit_layer(m, mm)) dw = std::max(dw, bsplit_dwords(Nc, (int32_t)rup(m.T[mm - 2] + 1, 16)));
     if (dw > 0) ops.bparts = ar.take<uint32_t>((size_t)dw);
   }
   if (!same_type) {
     int64_t pf = 0;
     for (int mm = 2; mm <= L - 1; ++mm) {
-      const int64_t f = pairdiag_block_floats(m, N, mm);
+      const int64_t f = pairdiag_block_floats(m, Nc, mm);
       if (f * 4 <= kPairdiagMaxBytes) pf = std::max(pf, f);
     }
     if (pf > 0) ops.pdws = ar.take<float>((size_t)pf);
@@ -533,29 +576,30 @@ size_t plan_exact(const Model& m, int64_t N, void* ws, Prep& p, HOps<T>& ops, st
   return ar.used;
 }
 
-// FP64 factors F, K, G of column layer mm (layout [T_a][T_m][N]) from the per-example caches.
-void compute_factors(Exec& ex, const Model& m, int64_t N, Prep& p, HFactors& f, int mm) {
+// FP64 factors F, K, G of column layer mm (layout [T_a][T_m][Nc]) for the Nc examples
+// n0 .. n0 + Nc - 1, from the per-example caches (transposed caches [T][N], read at offset n0).
+void compute_factors(Exec& ex, const Model& m, int64_t Nc, int64_t n0, Prep& p, HFactors& f, int mm) {
   const int L = m.L;
-  const int64_t Tm = m.T[mm - 1];
+  const int64_t Tm = m.T[mm - 1], ldc = p.N;
   // forward factors
-  if (mm < L) factor_first(ex, p.W64[mm - 1], m.T[mm], Tm, p.D1T[mm], N, f.F[mm + 1]);
+  if (mm < L) factor_first(ex, p.W64[mm - 1], m.T[mm], Tm, p.D1T[mm] + n0, ldc, Nc, f.F[mm + 1]);
   for (int l = mm + 2; l <= L; ++l) {
-    factor_rowscale(ex, f.F[l - 1], m.T[l - 2], Tm, p.D1T[l - 1], N, f.K[l - 1]);
-    gemm_rm<double>(ex, false, false, m.T[l - 1], Tm * N, m.T[l - 2], 1.0, p.W64[l - 2], m.T[l - 2], f.K[l - 1],
-                    Tm * N, 0.0, f.F[l], Tm * N);
+    factor_rowscale(ex, f.F[l - 1], m.T[l - 2], Tm, p.D1T[l - 1] + n0, ldc, Nc, f.K[l - 1]);
+    gemm_rm<double>(ex, false, false, m.T[l - 1], Tm * Nc, m.T[l - 2], 1.0, p.W64[l - 2], m.T[l - 2], f.K[l - 1],
+                    Tm * Nc, 0.0, f.F[l], Tm * Nc);
   }
   // backward factors
-  factor_softmax(ex, mm < L ? f.F[L] : nullptr, m.T[L - 1], Tm, p.PT, N, f.G[L]);
+  factor_softmax(ex, mm < L ? f.F[L] : nullptr, m.T[L - 1], Tm, p.PT + n0, ldc, Nc, f.G[L]);
   for (int l = L - 1; l >= mm; --l) {
-    gemm_rm<double>(ex, true, false, m.T[l - 1], Tm * N, m.T[l], 1.0, p.W64[l - 1], m.T[l - 1], f.G[l + 1],
-                    Tm * N, 0.0, f.G[l], Tm * N);
-    factor_combine(ex, f.G[l], m.T[l - 1], Tm, p.D1T[l], p.CT[l], l == mm ? nullptr : f.F[l], N);
+    gemm_rm<double>(ex, true, false, m.T[l - 1], Tm * Nc, m.T[l], 1.0, p.W64[l - 1], m.T[l - 1], f.G[l + 1],
+                    Tm * Nc, 0.0, f.G[l], Tm * Nc);
+    factor_combine(ex, f.G[l], m.T[l - 1], Tm, p.D1T[l] + n0, p.CT[l] + n0, ldc, l == mm ? nullptr : f.F[l], Nc);
   }
 }
 
 template <typename T, typename TOut>
-void run_exact(Exec& ex, const Model& m, int64_t N, Prep& p, HOps<T>& ops, std::vector<HFactors>& fac,
-               void* ws, size_t base_used_hint, TOut* H, bool same_type) {
+void run_exact(Exec& ex, const Model& m, int64_t N, int64_t Nc, Prep& p, HOps<T>& ops, std::vector<HFactors>& fac,
+               void* ws, size_t base_used, TOut* H, bool same_type) {
   const int L = m.L;
   if (!same_type) cast_ops<T>(ex, m, p, ops.base);
   std::vector<T*> abar(L + 1), delta(L + 1);
@@ -568,107 +612,117 @@ void run_exact(Exec& ex, const Model& m, int64_t N, Prep& p, HOps<T>& ops, std::
       delta[l] = (l >= 2) ? ops.base.delta[l] : nullptr;
     }
   }
-  for (int mm = 2; mm <= L; ++mm) {
-    HFactors& f = fac[mm];
-    const int64_t Tm = m.T[mm - 1];
-    compute_factors(ex, m, N, p, f, mm);
-    // operand-precision weights
-    std::vector<const T*> Gw(L + 1, nullptr), Kw(L + 1, nullptr);
-    const T* D1w = nullptr;
-    if (same_type) {
-      for (int l = mm; l <= L; ++l) Gw[l] = reinterpret_cast<const T*>(f.G[l]);
-      for (int l = mm + 1; l <= L - 1; ++l) Kw[l] = reinterpret_cast<const T*>(f.K[l]);
-      if (mm < L) D1w = reinterpret_cast<const T*>(p.D1T[mm]);
-    } else {
-      // carve the copies right after this m's FP64 factors (mirrors plan_exact)
+  // chunks of Nc examples (one chunk unless the factors exceed the context's cap); the
+  // first chunk writes H, later chunks add to it.  Nc is a multiple of 32 below N, so the
+  // split-product tile meets partial chunks of 32 examples only at N, where the row
+  // sources are zero-padded.
+  for (int64_t n0 = 0; n0 < N; n0 += Nc) {
+    const int64_t nc = std::min(Nc, N - n0);
+    const int acc1 = n0 > 0 ? 1 : 0;
+    for (int mm = 2; mm <= L; ++mm) {
+      HFactors& f = fac[mm];
+      const int64_t Tm = m.T[mm - 1];
+      compute_factors(ex, m, nc, n0, p, f, mm);
+      // operand-precision weights, carved right after this m's FP64 factors (mirrors plan_exact)
+      std::vector<const T*> Gw(L + 1, nullptr), Kw(L + 1, nullptr);
+      const T* D1w = nullptr;
       Arena a2(ws);
-      a2.used = base_used_hint;
-      for (int l = mm + 1; l <= L; ++l) a2.take<double>(m.T[l - 1] * Tm * N);
-      for (int l = mm + 1; l <= L - 1; ++l) a2.take<double>(m.T[l - 1] * Tm * N);
-      for (int l = mm; l <= L; ++l) a2.take<double>(m.T[l - 1] * Tm * N);
-      for (int l = mm; l <= L; ++l) {
-        T* g = a2.take<T>(m.T[l - 1] * Tm * N);
-        cast_copy<T>(ex, f.G[l], g, m.T[l - 1] * Tm * N);
-        Gw[l] = g;
-      }
-      for (int l = mm + 1; l <= L - 1; ++l) {
-        T* k = a2.take<T>(m.T[l - 1] * Tm * N);
-        cast_copy<T>(ex, f.K[l], k, m.T[l - 1] * Tm * N);
-        Kw[l] = k;
-      }
-      T* d1 = a2.take<T>(Tm * N);
-      if (mm < L) {
-        cast_copy<T>(ex, p.D1T[mm], d1, Tm * N);
-        D1w = d1;
-      }
-    }
-    // split products: the column source abar^(m-1) split once for all blocks of this m
-    uint32_t* bp = nullptr;
-    if constexpr (sizeof(T) == 4) {
-      if (ex.split && ops.bparts && presplit_layer(m, mm)) {
-        const KrgSide<T> cs = side_layer<T>(m, mm, abar[mm - 1], p.lda[mm - 1], nullptr, 0);
-        bsplit(ex, abar[mm - 1], p.lda[mm - 1], cs.len, cs.pad, N, ops.bparts);
-        bp = ops.bparts;
-      }
-    }
-    // term 1: weighted Gram of abar^(l-1) and abar^(m-1)
-    for (int l = mm; l <= L; ++l) {
-      KrgArgs<T, TOut> a;
-      a.r = side_layer<T>(m, l, abar[l - 1], p.lda[l - 1], nullptr, 0);
-      a.c = side_layer<T>(m, mm, abar[mm - 1], p.lda[mm - 1], nullptr, 0);
-      a.bparts = bp;
-      a.bp_nblk = a.c.pad / 32;
-      a.wmode = KRG_PAIR_FULL;
-      a.wts = Gw[l];
-      a.ldw = N;
-      a.out = H;
-      a.ldo = m.P;
-      a.symmetric = (l == mm);
-      a.accumulate = 0;
-      a.mirror = 1;
-      a.scale = 1.0 / (double)N;
-      a.N = N;
-      krg<T, TOut>(ex, a);
-    }
-    // term 2 (l > m): delta^(l)_{i'} abar^(m-1)_j weighted by K^(l-1,m)[j', i]
-    for (int l = mm + 1; l <= L; ++l) {
-      KrgArgs<T, TOut> a;
-      KrgSide<T> r;
-      r.src = delta[l];
-      r.ld = m.T[l - 1];
-      r.n_units = (int32_t)m.T[l - 2];   // units j' (inputs of layer l, no bias)
-      r.len = (int32_t)m.T[l - 1];       // slots i'
-      r.pad = (int32_t)rup(r.len, 16);
-      r.scale = nullptr;
-      r.ld_scale = 0;
-      r.perm = 1;
-      r.off = m.offW[l - 2];
-      r.Tin = (int32_t)m.T[l - 2];
-      r.Tout = (int32_t)m.T[l - 1];
-      a.r = r;
-      a.c = side_layer<T>(m, mm, abar[mm - 1], p.lda[mm - 1], nullptr, 0);
-      if (l - 1 == mm) {
-        a.wmode = KRG_PAIR_DIAG;
-        a.wts = D1w;
+      a2.used = base_used;
+      for (int l = mm + 1; l <= L; ++l) a2.take<double>(m.T[l - 1] * Tm * Nc);
+      for (int l = mm + 1; l <= L - 1; ++l) a2.take<double>(m.T[l - 1] * Tm * Nc);
+      for (int l = mm; l <= L; ++l) a2.take<double>(m.T[l - 1] * Tm * Nc);
+      if (same_type) {
+        for (int l = mm; l <= L; ++l) Gw[l] = reinterpret_cast<const T*>(f.G[l]);
+        for (int l = mm + 1; l <= L - 1; ++l) Kw[l] = reinterpret_cast<const T*>(f.K[l]);
       } else {
-        a.wmode = KRG_PAIR_FULL;
-        a.wts = Kw[l - 1];
-      }
-      a.ldw = N;
-      a.out = H;
-      a.ldo = m.P;
-      a.symmetric = 0;
-      a.accumulate = 1;
-      a.mirror = 1;
-      a.scale = 1.0 / (double)N;
-      a.N = N;
-      if constexpr (sizeof(T) == 4 && sizeof(TOut) == 4) {
-        if (l - 1 == mm && ops.pdws && pairdiag_block_floats(m, N, mm) * 4 <= kPairdiagMaxBytes) {
-          krg_pairdiag_gemm(ex, a, ops.pdws);
-          continue;
+        for (int l = mm; l <= L; ++l) {
+          T* g = a2.take<T>(m.T[l - 1] * Tm * Nc);
+          cast_copy<T>(ex, f.G[l], g, m.T[l - 1] * Tm * nc);
+          Gw[l] = g;
+        }
+        for (int l = mm + 1; l <= L - 1; ++l) {
+          T* k = a2.take<T>(m.T[l - 1] * Tm * Nc);
+          cast_copy<T>(ex, f.K[l], k, m.T[l - 1] * Tm * nc);
+          Kw[l] = k;
         }
       }
-      krg<T, TOut>(ex, a);
+      T* d1 = a2.take<T>(Tm * Nc);
+      if (mm < L) {
+        if (same_type && nc == N) {
+          D1w = reinterpret_cast<const T*>(p.D1T[mm]);
+        } else {
+          cast_2d<T>(ex, p.D1T[mm] + n0, Tm, nc, p.N, d1, nc);
+          D1w = d1;
+        }
+      }
+      // split products: the column source abar^(m-1) of the chunk split once for all blocks of this m
+      uint32_t* bp = nullptr;
+      if constexpr (sizeof(T) == 4) {
+        if (ex.split && ops.bparts && presplit_layer(m, mm)) {
+          const KrgSide<T> cs = side_layer<T>(m, mm, abar[mm - 1] + n0 * p.lda[mm - 1], p.lda[mm - 1], nullptr, 0);
+          bsplit(ex, abar[mm - 1] + n0 * p.lda[mm - 1], p.lda[mm - 1], cs.len, cs.pad, nc, ops.bparts);
+          bp = ops.bparts;
+        }
+      }
+      // term 1: weighted Gram of abar^(l-1) and abar^(m-1)
+      for (int l = mm; l <= L; ++l) {
+        KrgArgs<T, TOut> a;
+        a.r = side_layer<T>(m, l, abar[l - 1] + n0 * p.lda[l - 1], p.lda[l - 1], nullptr, 0);
+        a.c = side_layer<T>(m, mm, abar[mm - 1] + n0 * p.lda[mm - 1], p.lda[mm - 1], nullptr, 0);
+        a.bparts = bp;
+        a.bp_nblk = a.c.pad / 32;
+        a.wmode = KRG_PAIR_FULL;
+        a.wts = Gw[l];
+        a.ldw = nc;
+        a.out = H;
+        a.ldo = m.P;
+        a.symmetric = (l == mm);
+        a.accumulate = acc1;
+        a.mirror = 1;
+        a.scale = 1.0 / (double)N;
+        a.N = nc;
+        krg<T, TOut>(ex, a);
+      }
+      // term 2 (l > m): delta^(l)_{i'} abar^(m-1)_j weighted by K^(l-1,m)[j', i]
+      for (int l = mm + 1; l <= L; ++l) {
+        KrgArgs<T, TOut> a;
+        KrgSide<T> r;
+        r.src = delta[l] + n0 * m.T[l - 1];
+        r.ld = m.T[l - 1];
+        r.n_units = (int32_t)m.T[l - 2];   // units j' (inputs of layer l, no bias)
+        r.len = (int32_t)m.T[l - 1];       // slots i'
+        r.pad = (int32_t)rup(r.len, 16);
+        r.scale = nullptr;
+        r.ld_scale = 0;
+        r.perm = 1;
+        r.off = m.offW[l - 2];
+        r.Tin = (int32_t)m.T[l - 2];
+        r.Tout = (int32_t)m.T[l - 1];
+        a.r = r;
+        a.c = side_layer<T>(m, mm, abar[mm - 1] + n0 * p.lda[mm - 1], p.lda[mm - 1], nullptr, 0);
+        if (l - 1 == mm) {
+          a.wmode = KRG_PAIR_DIAG;
+          a.wts = D1w;
+        } else {
+          a.wmode = KRG_PAIR_FULL;
+          a.wts = Kw[l - 1];
+        }
+        a.ldw = nc;
+        a.out = H;
+        a.ldo = m.P;
+        a.symmetric = 0;
+        a.accumulate = 1;
+        a.mirror = 1;
+        a.scale = 1.0 / (double)N;
+        a.N = nc;
+        if constexpr (sizeof(T) == 4 && sizeof(TOut) == 4) {
+          if (l - 1 == mm && ops.pdws && pairdiag_block_floats(m, Nc, mm) * 4 <= kPairdiagMaxBytes) {
+            krg_pairdiag_gemm(ex, a, ops.pdws);
+            continue;
+          }
+        }
+        krg<T, TOut>(ex, a);
+      }
     }
   }
 }
@@ -754,6 +808,10 @@ hess_status hess_set_option(hess_ctx* ctx, int opt, int64_t value) {
     case HESS_OPT_PROFILE: ctx->profile = value != 0; return HESS_OK;
     case HESS_OPT_GRAPHS: ctx->graphs = value != 0; return HESS_OK;
     case HESS_OPT_AUTOTUNE: ctx->autotune = value != 0; return HESS_OK;
+    case HESS_OPT_FACTOR_BYTES:
+      if (value < 0) return fail(ctx, HESS_E_ARG, "factor cap must be >= 0");
+      ctx->factor_cap = value;
+      return HESS_OK;
   }
   return fail(ctx, HESS_E_ARG, "unknown option");
 }
@@ -784,15 +842,17 @@ static size_t ws_opg(const Model& m, int64_t N, int prec) {
   OpgBufs<float> b;
   return plan_opg(m, N, prec, nullptr, p, &b);
 }
-static size_t ws_exact(const Model& m, int64_t N, int prec) {
+static size_t ws_exact(const hess_ctx* ctx, const Model& m, int64_t N, int prec) {
   Prep p;
   std::vector<HFactors> fac;
-  if (prec == HESS_P_F64) {
+  const bool same = prec == HESS_P_F64, split = prec == HESS_P_F32_SPLIT;
+  const int64_t Nc = exact_chunk(ctx, m, N, same, split);
+  if (same) {
     HOps<double> o;
-    return plan_exact<double>(m, N, nullptr, p, o, fac, true);
+    return plan_exact<double>(m, N, Nc, nullptr, p, o, fac, true);
   }
   HOps<float> o;
-  return plan_exact<float>(m, N, nullptr, p, o, fac, false, prec == HESS_P_F32_SPLIT);
+  return plan_exact<float>(m, N, Nc, nullptr, p, o, fac, false, split);
 }
 
 hess_status hess_workspace_size(hess_ctx* ctx, int op, const hess_mlp* mlp, const hess_data* d, int prec,
@@ -805,7 +865,7 @@ hess_status hess_workspace_size(hess_ctx* ctx, int op, const hess_mlp* mlp, cons
     case HESS_OP_OPG:
       if ((s = validate_mlp(ctx, mlp, m, false)) != HESS_OK) return s;
       if ((s = validate_data(ctx, d, false)) != HESS_OK) return s;
-      *bytes = op == HESS_OP_EXACT ? ws_exact(m, d->N, prec) : ws_opg(m, d->N, prec);
+      *bytes = op == HESS_OP_EXACT ? ws_exact(ctx, m, d->N, prec) : ws_opg(m, d->N, prec);
       return HESS_OK;
     case HESS_OP_HVP:
       if ((s = validate_mlp(ctx, mlp, m, false)) != HESS_OK) return s;
@@ -881,29 +941,31 @@ hess_status hess_exact(hess_ctx* ctx, const hess_mlp* mlp, const hess_data* d, i
     return fail(ctx, HESS_E_ARG, "bad precision");
   ex.split = prec == HESS_P_F32_SPLIT;
   if (!H) return fail(ctx, HESS_E_ARG, "output is NULL");
-  const size_t need = ws_exact(m, d->N, prec);
+  const size_t need = ws_exact(ctx, m, d->N, prec);
   const size_t out_bytes = (size_t)m.P * m.P * (prec == HESS_P_F64 ? 8 : 4);
   if ((s = check_ws(ctx, need, ws, ws_bytes, out_bytes)) != HESS_OK) return s;
   Prep p;
   std::vector<HFactors> fac;
+  const int64_t Nc = exact_chunk(ctx, m, d->N, prec == HESS_P_F64, ex.split);
+  // base offset of the per-m factor region = arena usage after prep (+ operand copies)
+  Arena ar(ws);
+  Prep p0;
+  plan_prep(ar, m, d->N, p0, true);
   if (prec == HESS_P_F64) {
+    const size_t base_used = ar.used;
     HOps<double> o;
-    plan_exact<double>(m, d->N, ws, p, o, fac, true);
+    plan_exact<double>(m, d->N, Nc, ws, p, o, fac, true);
     if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
     run_prep(ex, m, d, p, true);
-    run_exact<double, double>(ex, m, d->N, p, o, fac, ws, 0, static_cast<double*>(H), true);
+    run_exact<double, double>(ex, m, d->N, Nc, p, o, fac, ws, base_used, static_cast<double*>(H), true);
   } else {
     HOps<float> o;
-    // base offset of the per-m factor region = arena usage after prep + operand copies
-    Arena ar(ws);
-    Prep p0;
-    plan_prep(ar, m, d->N, p0, true);
     plan_opg_ops<float>(ar, m, d->N, p0, o.base);
     const size_t base_used = ar.used;
-    plan_exact<float>(m, d->N, ws, p, o, fac, false, ex.split);
+    plan_exact<float>(m, d->N, Nc, ws, p, o, fac, false, ex.split);
     if ((s = check_inputs(ex, m, d, p)) != HESS_OK) return s;
     run_prep(ex, m, d, p, true);
-    run_exact<float, float>(ex, m, d->N, p, o, fac, ws, base_used, static_cast<float*>(H), false);
+    run_exact<float, float>(ex, m, d->N, Nc, p, o, fac, ws, base_used, static_cast<float*>(H), false);
   }
   return finish(ex, "hess_exact");
 }

@@ -220,7 +220,7 @@ extern "C" hess_status hess_batched(hess_ctx* ctx, int64_t M, const hess_mlp* mo
       for (int l = mm + 1; l <= L; ++l) f.F[l] = a2.take<double>(m.T[l - 1] * Tm * N);
       for (int l = mm + 1; l <= L - 1; ++l) f.K[l] = a2.take<double>(m.T[l - 1] * Tm * N);
       for (int l = mm; l <= L; ++l) f.G[l] = a2.take<double>(m.T[l - 1] * Tm * N);
-      compute_factors(ex, m, N, p, f, mm);
+      compute_factors(ex, m, N, 0, p, f, mm);
       for (int l = mm; l <= L; ++l) cast_copy<float>(ex, f.G[l], b.G[mm][l], m.T[l - 1] * Tm * N);
       for (int l = mm + 1; l <= L - 1; ++l) cast_copy<float>(ex, f.K[l], b.K[mm][l], m.T[l - 1] * Tm * N);
       if (mm < L) cast_copy<float>(ex, p.D1T[mm], b.D1[mm], Tm * N);

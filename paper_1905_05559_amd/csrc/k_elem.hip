@@ -174,46 +174,46 @@ __global__ void k_cast2d(const double* src, int64_t rows, int64_t cols, int64_t 
   }
 }
 
-__global__ void k_factor_first(const double* W, int64_t T2, int64_t Tm, const double* D1T, int64_t N,
+__global__ void k_factor_first(const double* W, int64_t T2, int64_t Tm, const double* D1T, int64_t ldc, int64_t N,
                                double* F) {
   GRID_STRIDE(idx, T2 * Tm * N) {
     const int64_t n = idx % N, i = (idx / N) % Tm, i2 = idx / (N * Tm);
-    F[idx] = W[i2 * Tm + i] * D1T[i * N + n];
+    F[idx] = W[i2 * Tm + i] * D1T[i * ldc + n];
   }
 }
 
-__global__ void k_factor_rowscale(const double* F, int64_t Tk, int64_t Tm, const double* D1T, int64_t N,
-                                  double* K) {
+__global__ void k_factor_rowscale(const double* F, int64_t Tk, int64_t Tm, const double* D1T, int64_t ldc,
+                                  int64_t N, double* K) {
   GRID_STRIDE(idx, Tk * Tm * N) {
     const int64_t n = idx % N, k = idx / (N * Tm);
-    K[idx] = D1T[k * N + n] * F[idx];
+    K[idx] = D1T[k * ldc + n] * F[idx];
   }
 }
 
 // G = S_n F with S_n = diag(p_n) - p_n p_n^T (the softmax Jacobian), per (i, n).
-__global__ void k_factor_softmax(const double* F, int64_t TL, int64_t Tm, const double* PT, int64_t N,
-                                 double* G) {
+__global__ void k_factor_softmax(const double* F, int64_t TL, int64_t Tm, const double* PT, int64_t ldc,
+                                 int64_t N, double* G) {
   GRID_STRIDE(idx, Tm * N) {
     const int64_t n = idx % N, i = idx / N;
     double s = 0.0;
     if (F) {
-      for (int64_t k = 0; k < TL; ++k) s += PT[k * N + n] * F[(k * Tm + i) * N + n];
+      for (int64_t k = 0; k < TL; ++k) s += PT[k * ldc + n] * F[(k * Tm + i) * N + n];
     } else {
-      s = PT[i * N + n];
+      s = PT[i * ldc + n];
     }
     for (int64_t k = 0; k < TL; ++k) {
       const double f = F ? F[(k * Tm + i) * N + n] : (k == i ? 1.0 : 0.0);
-      G[(k * Tm + i) * N + n] = PT[k * N + n] * (f - s);
+      G[(k * Tm + i) * N + n] = PT[k * ldc + n] * (f - s);
     }
   }
 }
 
 __global__ void k_factor_combine(double* G, int64_t Tk, int64_t Tm, const double* D1T, const double* CT,
-                                 const double* F, int64_t N) {
+                                 int64_t ldc, const double* F, int64_t N) {
   GRID_STRIDE(idx, Tk * Tm * N) {
     const int64_t n = idx % N, i = (idx / N) % Tm, k = idx / (N * Tm);
     const double f = F ? F[idx] : (k == i ? 1.0 : 0.0);
-    G[idx] = D1T[k * N + n] * G[idx] + CT[k * N + n] * f;
+    G[idx] = D1T[k * ldc + n] * G[idx] + CT[k * ldc + n] * f;
   }
 }
 
@@ -289,21 +289,21 @@ template void cast_copy<double>(Exec&, const double*, double*, int64_t);
 template void cast_2d<float>(Exec&, const double*, int64_t, int64_t, int64_t, float*, int64_t);
 template void cast_2d<double>(Exec&, const double*, int64_t, int64_t, int64_t, double*, int64_t);
 
-void factor_first(Exec& ex, const double* W, int64_t T2, int64_t Tm, const double* D1T, int64_t N,
+void factor_first(Exec& ex, const double* W, int64_t T2, int64_t Tm, const double* D1T, int64_t ldc, int64_t N,
                   double* F) {
-  LAUNCH(k_factor_first, T2 * Tm * N, W, T2, Tm, D1T, N, F);
+  LAUNCH(k_factor_first, T2 * Tm * N, W, T2, Tm, D1T, ldc, N, F);
 }
-void factor_rowscale(Exec& ex, const double* F, int64_t Tk, int64_t Tm, const double* D1T, int64_t N,
+void factor_rowscale(Exec& ex, const double* F, int64_t Tk, int64_t Tm, const double* D1T, int64_t ldc, int64_t N,
                      double* K) {
-  LAUNCH(k_factor_rowscale, Tk * Tm * N, F, Tk, Tm, D1T, N, K);
+  LAUNCH(k_factor_rowscale, Tk * Tm * N, F, Tk, Tm, D1T, ldc, N, K);
 }
-void factor_softmax(Exec& ex, const double* F, int64_t TL, int64_t Tm, const double* PT, int64_t N,
+void factor_softmax(Exec& ex, const double* F, int64_t TL, int64_t Tm, const double* PT, int64_t ldc, int64_t N,
                     double* G) {
-  LAUNCH(k_factor_softmax, Tm * N, F, TL, Tm, PT, N, G);
+  LAUNCH(k_factor_softmax, Tm * N, F, TL, Tm, PT, ldc, N, G);
 }
-void factor_combine(Exec& ex, double* G, int64_t Tk, int64_t Tm, const double* D1T, const double* CT,
+void factor_combine(Exec& ex, double* G, int64_t Tk, int64_t Tm, const double* D1T, const double* CT, int64_t ldc,
                     const double* F, int64_t N) {
-  LAUNCH(k_factor_combine, Tk * Tm * N, G, Tk, Tm, D1T, CT, F, N);
+  LAUNCH(k_factor_combine, Tk * Tm * N, G, Tk, Tm, D1T, CT, ldc, F, N);
 }
 
 }  // namespace hs

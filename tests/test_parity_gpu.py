@@ -418,3 +418,34 @@ def test_per_example_hessians_batched(api):
                       np.outer(J[i], J[i])) <= TOL["f32"]
     Hmean = sum(h.double() for h in Hs).cpu().numpy() / n
     assert report("mean of per-example H vs full H", Hmean, mlp.hessian(om, Xo, Yo)) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("T,acts,N,seed,cap", [
+    ([64, 64, 10], ["sigmoid"], 1000, 2, 20_000_000),    # chunks of 288 examples, last one 136
+    ([127, 24, 10], ["relu"], 700, 15, 4_000_000),       # pre-split columns, chunks of 288
+])
+def test_exact_chunked_over_examples(api, T, acts, N, seed, cap):
+    # a small factor cap forces hess_exact to accumulate H over chunks of examples (the
+    # mini-batch sum of Sec. 5.1); against the oracle and the one-pass H
+    om_w = {}
+    for prec in ("f64", "f32", "f32_split"):
+        w = workloads.mlp_gaussian(T, acts, N, seed, dtype="float64" if prec == "f64" else "float32")
+        model, X, Y = to_dev(api, w, w.dtype)
+        if "H" not in om_w:
+            om, Xo, Yo = oracle_of(w)
+            om_w["H"] = mlp.hessian(om, Xo, Yo, block=256)
+        ctx1 = api.Context(0)
+        H1 = api.hess_exact(model, X, Y, prec, ctx=ctx1).double().cpu().numpy()
+        ws1 = api.workspace_size("exact", model, X, Y, prec, ctx=ctx1)
+        ctx = api.Context(0)
+        ctx.set_option("factor_bytes", cap)
+        wsc = api.workspace_size("exact", model, X, Y, prec, ctx=ctx)
+        print("case chunked exact T=%s N=%d %s: workspace %.1f MB one pass, %.1f MB chunked"
+              % (T, N, prec, ws1 / 1e6, wsc / 1e6), flush=True)
+        assert wsc < ws1
+        Hc = api.hess_exact(model, X, Y, prec, ctx=ctx).double().cpu().numpy()
+        assert np.array_equal(Hc, Hc.T)
+        assert report("H chunked %s %s" % (T, prec), Hc, om_w["H"]) <= TOL[prec]
+        assert report("H chunked vs one pass %s %s" % (T, prec), Hc, H1) <= (1e-13 if prec == "f64" else 2e-6)
+        ctx.close()
+        ctx1.close()
