@@ -736,6 +736,37 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
     cok[j] = uc < a.c.n_units && sc < a.c.len;
     fcol[j] = cok[j] ? flat_index(a.c.perm, a.c.off, a.c.Tin, a.c.Tout, uc, sc) : 0;
   }
+  // With the row mapping 16 q + 4 v + i a lane holds 16 consecutive rows of each of its
+  // columns.  When they are 16 weights of one unit (consecutive flat indices) and every
+  // (r, c) of the tile is stored (off the diagonal of a symmetric contraction), the mirrored
+  // entries of a column are 64 contiguous bytes, written as 8-byte pairs instead of 16
+  // scattered floats.  Otherwise (bias or padding slots, transposed index map, diagonal
+  // tiles, accumulation) every entry takes the general path.
+  if constexpr (C::BPS) {
+    const int64_t rf = r0 + wr * 64 + 16 * q;
+    const int64_t urf = rf / a.r.pad, srf = rf % a.r.pad;
+    const bool vec = a.mirror && !a.accumulate && a.r.perm == 0 && (a.ldo & 1) == 0 &&
+                     (reinterpret_cast<uintptr_t>(a.out) & 7) == 0 && !(SYM && r0 == c0) && urf < a.r.n_units &&
+                     srf + 15 < a.r.len && srf + 15 < a.r.Tin;
+    if (vec) {
+      const int64_t fr0 = a.r.off + urf * a.r.Tin + srf;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!cok[j]) continue;
+        float val[16];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) val[4 * v + i] = (float)(a.scale * (double)acc[i][j][v]);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) a.out[(fr0 + e) * a.ldo + fcol[j]] = val[e];
+        f2_t* m = reinterpret_cast<f2_t*>(a.out + fcol[j] * a.ldo + fr0);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) m[e] = f2_t{val[2 * e], val[2 * e + 1]};
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll

@@ -9,7 +9,8 @@
 // 2) gram_bf16: C[p][q] = scale * sum_n Jt[p][n] Jt[q][n] for the lower triangle of
 //    256 x 256 tiles, mirrored, FP32 accumulation (v_mfma_f32_16x16x32_bf16).
 //    4 wavefronts (2 x 2), each 128 x 128 = 8 x 8 MFMA blocks; K staged through LDS
-//    in chunks of 64 with 16-byte vector loads prefetched one chunk ahead.
+//    in chunks of 32 by direct HBM -> LDS copies, several chunks ahead, with the MFMA
+//    operands of the next chunk read from LDS while the current chunk's MFMAs run.
 #include <algorithm>
 #include <string>
 
@@ -200,6 +201,56 @@ __device__ __forceinline__ int seg_swz(int row) {
 
 extern __shared__ __attribute__((aligned(16))) unsigned char gram_smem[];
 
+// Stores of a 256 x 256 tile's accumulators (wavefront (wr, wc), lane (row16, q)): entry
+// (r, c) = (r0 + 128 wr + 16 i + 4 q + v, c0 + 128 wc + 16 j + row16) goes to C[r][c] and,
+// mirrored, to C[c][r].  A lane's four v of one block are four consecutive r, so on interior
+// off-diagonal tiles the mirror is written as one 16-byte store (two 8-byte stores when the
+// rows are only 8-byte aligned) instead of four scattered floats; diagonal and edge tiles keep
+// the per-entry form.
+__device__ __forceinline__ void gram_store(const f4_t (&acc)[8][8], int64_t P, int64_t r0, int64_t c0, bool diag,
+                                           int wr, int wc, int row16, int q, float scale, float* __restrict__ C,
+                                           int64_t ldc) {
+  if (!diag && r0 + GB <= P && c0 + GB <= P) {
+    const uintptr_t base = reinterpret_cast<uintptr_t>(C);
+    const bool a16 = (ldc & 3) == 0 && (base & 15) == 0, a8 = (ldc & 1) == 0 && (base & 7) == 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t rb = r0 + wr * 128 + i * 16 + 4 * q, c = c0 + wc * 128 + j * 16 + row16;
+        const f4_t val = scale * acc[i][j];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) C[(rb + v) * ldc + c] = val[v];
+        float* m = C + c * ldc + rb;
+        if (a16) {
+          *reinterpret_cast<f4_t*>(m) = val;
+        } else if (a8) {
+          reinterpret_cast<f2_t*>(m)[0] = f2_t{val[0], val[1]};
+          reinterpret_cast<f2_t*>(m)[1] = f2_t{val[2], val[3]};
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) m[v] = val[v];
+        }
+      }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = r0 + wr * 128 + i * 16 + 4 * q + v;
+      if (r >= P) continue;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t c = c0 + wc * 128 + j * 16 + row16;
+        if (c >= P || (diag && r < c)) continue;
+        const float val = scale * acc[i][j][v];
+        C[r * ldc + c] = val;
+        if (r != c) C[c * ldc + r] = val;
+      }
+    }
+}
+
 // DIST: the next chunk's copies are spread over the current chunk's MFMA rows (one copy
 // after each row of 8 MFMAs) instead of issued together after the barrier: a full copy
 // queue then holds up a few MFMAs instead of the whole chunk's.
@@ -309,21 +360,135 @@ __device__ __forceinline__ void gram_dma_tile(const __bf16* __restrict__ Jt, int
     }
   }
 
+  gram_store(acc, P, r0, c0, diag, wr, wc, row16, q, scale, C, ldc);
+}
+
+// Software-pipelined form: chunks of 32 examples in GS >= 3 stages.  The barrier at the top
+// of chunk kc also covers chunk kc + 1 (its copies are waited for one chunk early), so each
+// wavefront reads its MFMA operands of chunk kc + 1 from LDS while the MFMAs of chunk kc run
+// on the operands read during chunk kc - 1: no LDS latency between the barrier and the first
+// MFMA.  The copies of chunk kc + GS - 1 are spread over the MFMA rows of chunk kc; they refill
+// the stage of chunk kc - 1, whose operand reads (issued during chunk kc - 2) completed before
+// the barrier of chunk kc - 1.  Same products in the same order as gram_dma_tile.
+template <int GS>
+__device__ __forceinline__ void gram_pipe_tile(const __bf16* __restrict__ Jt, int64_t P, int64_t ldk, float scale,
+                                               float* __restrict__ C, int64_t ldc, int64_t ntiles) {
+  static_assert(GS >= 3, "the pipelined form needs three stages or more");
+  constexpr int GD = 32, NSEG = 4, RPC = 16, CPW = GB / RPC / 4;  // 4 copies per panel and wavefront
+  constexpr int GSTAGE = 2 * GB * GD;
+  __bf16* S = reinterpret_cast<__bf16*>(gram_smem);
+
+  const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
+  if (t < 0) return;
+  int64_t tr, tc;
+  grouped_lower_tile(t, (P + GB - 1) / GB, tr, tc);
+  const int64_t r0 = tr * GB, c0 = tc * GB;
+  const bool diag = (tr == tc);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int row16 = lane & 15, q = lane >> 4;
+
+  int voffA[CPW], voffB[CPW];
+#pragma unroll
+  for (int m = 0; m < CPW; ++m) {
+    const int row = RPC * (CPW * wave + m) + lane / NSEG;
+    const int seg = (lane % NSEG) ^ seg_swz<GD>(row);
+    const int64_t ra = std::min<int64_t>(r0 + row, P - 1) - r0, rb = std::min<int64_t>(c0 + row, P - 1) - c0;
+    voffA[m] = (int)((ra * ldk + seg * 8) * 2);
+    voffB[m] = (int)((rb * ldk + seg * 8) * 2);
+  }
+  const int64_t nk = ldk / GD;
+  // copy s (0 .. 2 CPW - 1) of chunk k0 / GD into stage st: A copy s / 2 for even s, B copy
+  // s / 2 for odd s; past the last chunk the buffer is empty and the copy writes zeros into a
+  // stage that is not read again
+  auto issue_one = [&](int st, int64_t k0, int s, bool live) {
+    __bf16* D = S + st * GSTAGE;
+    const int m = s >> 1;
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<__bf16*>(Jt + ((s & 1) ? c0 : r0) * ldk + (live ? k0 : 0)), (short)0, live ? 0x7ffffff0 : 0,
+        0x00020000);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        r, (__attribute__((address_space(3))) void*)(D + ((s & 1) ? GB * GD : 0) + (CPW * wave + m) * RPC * GD), 16,
+        (s & 1) ? voffB[m] : voffA[m], 0, 0, 0);
+  };
+  const int sw = seg_swz<GD>(row16);
+  const int off = (q ^ sw) * 8;
+  auto read_ops = [&](int st, bf8_t (&av)[8], bf8_t (&bv)[8]) {
+    const __bf16* As = S + st * GSTAGE;
+    const __bf16* Bs = diag ? As : As + GB * GD;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) av[i] = *reinterpret_cast<const bf8_t*>(&As[(wr * 128 + i * 16 + row16) * GD + off]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bv[j] = *reinterpret_cast<const bf8_t*>(&Bs[(wc * 128 + j * 16 + row16) * GD + off]);
+  };
+
+  f4_t acc[8][8];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = r0 + wr * 128 + i * 16 + 4 * q + v;
-      if (r >= P) continue;
+    for (int j = 0; j < 8; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int64_t c = c0 + wc * 128 + j * 16 + row16;
-        if (c >= P || (diag && r < c)) continue;
-        const float val = scale * acc[i][j][v];
-        C[r * ldc + c] = val;
-        if (r != c) C[c * ldc + r] = val;
-      }
+  for (int c = 0; c < GS - 1; ++c)
+#pragma unroll
+    for (int s = 0; s < 2 * CPW; ++s) issue_one(c, (int64_t)c * GD, s, c < nk);
+  // chunk 0 landed (GS - 2 later chunks may stay in flight)
+  wait_vmcnt<(GS - 2) * 2 * CPW>();
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  // two operand sets, alternated by unrolling two chunks per iteration (no register moves);
+  // st = stage of chunk kc
+  bf8_t a0[8], b0[8], a1[8], b1[8];
+  read_ops(0, a0, b0);
+  auto step = [&](int64_t kc, int st, bf8_t (&ac)[8], bf8_t (&bc)[8], bf8_t (&an)[8], bf8_t (&bn)[8]) {
+    // chunk kc + 1 landed: of the copies issued so far (through chunk kc + GS - 2, every one
+    // issued, live or not) those of chunks kc + 2 .. kc + GS - 2 may stay in flight
+    wait_vmcnt<(GS - 3) * 2 * CPW>();
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    read_ops(st + 1 == GS ? 0 : st + 1, an, bn);
+    const bool more = kc + GS - 1 < nk;
+    const int nst = st == 0 ? GS - 1 : st - 1;  // stage of chunk kc + GS - 1 (= that of kc - 1)
+    const int64_t nk0 = (kc + GS - 1) * GD;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[i][j] = mma_bf16(ac[i], bc[j], acc[i][j]);
+      __builtin_amdgcn_sched_barrier(0);
+      issue_one(nst, nk0, i, more);
+      __builtin_amdgcn_sched_barrier(0);
     }
+  };
+  int st = 0;
+  int64_t kc = 0;
+  for (; kc + 1 < nk; kc += 2) {
+    step(kc, st, a0, b0, a1, b1);
+    st = st + 1 == GS ? 0 : st + 1;
+    step(kc + 1, st, a1, b1, a0, b0);
+    st = st + 1 == GS ? 0 : st + 1;
+  }
+  if (kc < nk) step(kc, st, a0, b0, a1, b1);
+  gram_store(acc, P, r0, c0, diag, wr, wc, row16, q, scale, C, ldc);
+}
+
+template <int GS>
+__global__ __launch_bounds__(256) void gram_bf16_pipe_kernel(const __bf16* __restrict__ Jt, int64_t P, int64_t ldk,
+                                                             float scale, float* __restrict__ C, int64_t ldc,
+                                                             int64_t ntiles) {
+  gram_pipe_tile<GS>(Jt, P, ldk, scale, C, ldc, ntiles);
+}
+
+template <int GS>
+void launch_gram_pipe(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, float scale, float* C, int64_t ldc,
+                      int64_t nt) {
+  constexpr int shm = GS * 2 * GB * 32 * (int)sizeof(__bf16);
+  static const bool attr = [] {
+    (void)hipFuncSetAttribute((const void*)gram_bf16_pipe_kernel<GS>, hipFuncAttributeMaxDynamicSharedMemorySize, shm);
+    return true;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL((gram_bf16_pipe_kernel<GS>), dim3((unsigned)xcd_grid(nt)), dim3(256), shm, ex.stream, Jt, P, ldk,
+                     scale, C, ldc, nt);
 }
 
 template <int GD, int GS, bool DIST>
@@ -369,13 +534,13 @@ void gram_bf16_variant(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64
   const double entries = (double)P * (P + 1) / 2;
   // LDS-staged form needs every copy offset below 2^31 bytes (255 rows of ldk BF16)
   const bool dma = variant != 1 && (int64_t)GB * ldk * 2 < 0x7fff0000;
-  // configuration of the LDS-staged form: 0 = (64 examples, 2 stages, copies spread over
-  // the MFMA rows; measured 358 ms against 387 ms with the copies issued together),
-  // 1 = (32, 4), 2 = (64, 2) with the copies issued together after the barrier
+  // configuration of the LDS-staged form: 0 = software-pipelined chunks of 32 in 4 stages
+  // (measured 321 ms on the MNIST-shaped OPG), 1 = (32 examples, 4 stages), 2 = (64, 2) with
+  // the copies spread over the MFMA rows (338 ms); all bitwise equal
   auto go = [&](int cfg, int64_t ntl) {
     if (cfg == 1) launch_gram_dma<32, 4>(ex, Jt, P, ldk, scale, C, ldc, ntl);
-    else if (cfg == 2) launch_gram_dma<64, 2>(ex, Jt, P, ldk, scale, C, ldc, ntl);
-    else launch_gram_dma<64, 2, true>(ex, Jt, P, ldk, scale, C, ldc, ntl);
+    else if (cfg == 2) launch_gram_dma<64, 2, true>(ex, Jt, P, ldk, scale, C, ldc, ntl);
+    else launch_gram_pipe<4>(ex, Jt, P, ldk, scale, C, ldc, ntl);
   };
   int cfg = variant == 2 ? 1 : (variant == 3 ? 2 : 0);
   if (dma && variant == 0 && ex.ctx->autotune) {
@@ -386,8 +551,8 @@ void gram_bf16_variant(Exec& ex, const __bf16* Jt, int64_t P, int64_t ldk, int64
     const int64_t ntp = std::min<int64_t>(nt, 2 * (int64_t)std::max(cus, 1));
     auto lg = [](int64_t v) { int b = 0; while (v > 1) { v >>= 1; ++b; } return b; };
     const std::string key = "gram_bf16 P2^" + std::to_string(lg(P)) + " N2^" + std::to_string(lg(ldk));
-    static const char* const cfgs[2] = {"chunk64x2", "chunk32x4"};
-    cfg = autotune_pick(ex, key, 2, cfgs, [&](int i) { go(i, ntp); });
+    static const char* const cfgs[3] = {"pipe32x4", "chunk32x4", "chunk64x2"};
+    cfg = autotune_pick(ex, key, 3, cfgs, [&](int i) { go(i, ntp); });
   }
   const int tok = prof_begin(ex, "gram_bf16_sym", 2.0 * N * entries, (double)P * ldk * 2.0 + (double)P * P * 4.0);
   if (dma) {
