@@ -91,6 +91,119 @@ __global__ void k_rdelta(T* RD, const T* RZ, const T* D1, const T* CE, int64_t N
   }
 }
 
+// R{delta^(l)} of one example chunk when the next layer has at most RDS_TN units, computed
+// in one pass and written directly as the split transpose that the accumulation product
+// R{delta^(l)}^T abar^(l-1) reads (row c = b T_l + t, k = n; the three BF16 planes of the
+// compensated split, zero for Nc <= n < rpad):
+//   RD[n][b][t] = D1[n][t] (sum_k RDn[n][b][k] Wn[k][t] + sum_k dn[n][k] Vn_b[k][t])
+//                 + CE[n][t] RZ[n][b][t]
+// (the two K = T_{l+1} products and the sigma' / sigma'' terms of the R-backward step,
+// which otherwise take two GEMMs, an elementwise pass and a transpose pass over the
+// N_c x B T_l tensor).  Tiles of 64 examples x 64 columns (T_l >= 32, so a tile spans at
+// most three directions b): a lane owns one column c and keeps its W and V_b columns in
+// registers; the tile's rows of RDn (its directions) and of dn are staged in LDS and read
+// as broadcasts; RZ, D1 and CE are read along c; the finished tile is split and written
+// transposed through LDS as in k_split_transpose.
+constexpr int RDS_TN = 32;
+template <int TN>
+__global__ __launch_bounds__(256) void k_rdelta_split(const float* __restrict__ RZ, const float* __restrict__ RDn,
+                                                      const float* __restrict__ Wn, const float* __restrict__ dn,
+                                                      const float* __restrict__ Vn, const float* __restrict__ D1,
+                                                      const float* __restrict__ CE, int64_t Nc, int64_t B, int Tl,
+                                                      int Tn, int64_t rpad, uint32_t* __restrict__ dst, int64_t ld,
+                                                      int64_t pl) {
+  __shared__ __attribute__((aligned(16))) float rdn_s[64][3 * TN];
+  __shared__ __attribute__((aligned(16))) float dn_s[64][TN];
+  __shared__ float tile[64][65];
+  const int64_t BT = B * Tl;
+  const int64_t tn = (rpad + 63) / 64;
+  const int64_t n0 = (int64_t)(blockIdx.x % tn) * 64, c0 = (int64_t)(blockIdx.x / tn) * 64;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t blo = c0 / Tl;
+  const int nbt = (int)(std::min(c0 + 63, BT - 1) / Tl - blo + 1);  // directions in the tile (<= 3)
+  // every global read of the tile is issued before any is used (fully unrolled loops), so
+  // a wavefront waits for memory once rather than once per row
+  constexpr int RE = 64 * 3 * TN / 256, DE = 64 * TN / 256;
+  float rv[RE], dv[DE];
+#pragma unroll
+  for (int x = 0; x < RE; ++x) {
+    const int e = threadIdx.x + 256 * x;
+    const int y = e / (3 * TN), j = e - y * (3 * TN), bq = j / TN, k = j - bq * TN;
+    const int64_t n = n0 + y;
+    rv[x] = (n < Nc && bq < nbt && k < Tn) ? RDn[(n * B + blo + bq) * Tn + k] : 0.f;
+  }
+#pragma unroll
+  for (int x = 0; x < DE; ++x) {
+    const int e = threadIdx.x + 256 * x;
+    const int y = e / TN, k = e - y * TN;
+    const int64_t n = n0 + y;
+    dv[x] = (n < Nc && k < Tn) ? dn[n * Tn + k] : 0.f;
+  }
+  const int64_t c = c0 + lane;
+  const bool cok = c < BT;
+  const int64_t b = cok ? c / Tl : blo;
+  const int t = cok ? (int)(c - b * Tl) : 0;
+  const int bb = (int)(b - blo);
+  float wr[TN], vr[TN];
+#pragma unroll
+  for (int k = 0; k < TN; ++k) {
+    wr[k] = cok && k < Tn ? Wn[(int64_t)k * Tl + t] : 0.f;
+    vr[k] = cok && k < Tn ? Vn[(b * Tn + k) * (Tl + 1) + t] : 0.f;
+  }
+  // this wavefront's rows y = wave + 4 i
+  float zr[16], d1r[16], cer[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int64_t n = n0 + wave + 4 * i;
+    const bool ok = cok && n < Nc;
+    zr[i] = ok ? RZ[n * BT + c] : 0.f;
+    d1r[i] = ok ? D1[n * Tl + t] : 0.f;
+    cer[i] = ok ? CE[n * Tl + t] : 0.f;
+  }
+#pragma unroll
+  for (int x = 0; x < RE; ++x) (&rdn_s[0][0])[threadIdx.x + 256 * x] = rv[x];
+#pragma unroll
+  for (int x = 0; x < DE; ++x) (&dn_s[0][0])[threadIdx.x + 256 * x] = dv[x];
+  __syncthreads();
+  const int nq = (Tn + 3) / 4;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int y = wave + 4 * i;
+    const f4_t* rp = reinterpret_cast<const f4_t*>(&rdn_s[y][bb * TN]);
+    const f4_t* dp = reinterpret_cast<const f4_t*>(&dn_s[y][0]);
+    float acc = 0.f;
+#pragma unroll
+    for (int qd = 0; qd < TN / 4; ++qd) {
+      if (qd < nq) {
+        const f4_t r4 = rp[qd];
+        acc += r4[0] * wr[4 * qd] + r4[1] * wr[4 * qd + 1] + r4[2] * wr[4 * qd + 2] + r4[3] * wr[4 * qd + 3];
+      }
+    }
+#pragma unroll
+    for (int qd = 0; qd < TN / 4; ++qd) {
+      if (qd < nq) {
+        const f4_t d4 = dp[qd];
+        acc += d4[0] * vr[4 * qd] + d4[1] * vr[4 * qd + 1] + d4[2] * vr[4 * qd + 2] + d4[3] * vr[4 * qd + 3];
+      }
+    }
+    tile[y][lane] = d1r[i] * acc + cer[i] * zr[i];  // zero outside the chunk and past the columns
+  }
+  __syncthreads();
+  const SplitC sc = split_consts();
+  const int pr = threadIdx.x & 31;  // pair of rows 2 pr, 2 pr + 1 of the tile
+  for (int cc = threadIdx.x >> 5; cc < 64; cc += 8) {
+    const int64_t col = c0 + cc, r = n0 + 2 * pr;
+    if (col >= BT || r >= rpad) continue;
+    bf2_t h, m, l;
+    split3x2(f2_t{tile[2 * pr][cc], tile[2 * pr + 1][cc]}, h, m, l, sc);
+    const int64_t o = (col * ld + r) / 2;
+    dst[o] = __builtin_bit_cast(uint32_t, h);
+    dst[o + pl / 2] = __builtin_bit_cast(uint32_t, m);
+    dst[o + pl] = __builtin_bit_cast(uint32_t, l);
+  }
+}
+
 // S[n][b] = sum_i delta2[n][i] U2[n][b][i] + (same for layers 3 and 4 when present)
 template <typename T>
 __global__ void k_jv(const T* U2, const T* U3, const T* U4, const T* d2, const T* d3, const T* d4, int64_t T2,
@@ -147,7 +260,18 @@ int64_t hvp_chunk(const Model& m, int64_t N, int64_t B, size_t esz) {
 // its contraction (T_{l-1} + 1 inputs) is longer than 128 (shorter ones keep the FP32 MFMA
 // tile), and the accumulation over a chunk of examples when the chunk is.
 static bool presplit_rz(const Model& m, int l) { return m.T[l - 2] + 1 > 128; }
-static bool presplit_acc(int64_t Nc) { return Nc > 128; }
+// The accumulation takes pre-split operands when the chunk is longer than 128 examples and
+// its output (B T_l x (T_{l-1} + 1)) has enough 256 x 128 tiles to fill the device; a small
+// output (the output layer of a classifier) keeps the FP32 tile, which spreads it over more
+// workgroups.
+static bool presplit_acc(int64_t Nc, int64_t rows, int64_t cols) {
+  return Nc > 128 && ((rows + 255) / 256) * ((cols + 127) / 128) >= 128;
+}
+// R{delta^(2)} of a chunk formed and split in one pass (k_rdelta_split) when its
+// accumulation takes pre-split operands and the next layer is narrow.
+static bool fused_rdelta(const Model& m, int l, int64_t Nc, int64_t B) {
+  return l == 2 && m.L >= 3 && m.T[l] <= RDS_TN && m.T[l - 1] >= 32 && presplit_acc(Nc, B * m.T[l - 1], m.T[l - 2] + 1);
+}
 
 template <typename T>
 size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, bool split) {
@@ -200,7 +324,7 @@ size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBuf
         h.Vps[l] = take_split(ar, B * Tl, rup(Tin + 1, 32));
         h.Aps[l] = take_split(ar, h.Nc, rup(Tin + 1, 32));
       }
-      if (presplit_acc(h.Nc)) {
+      if (presplit_acc(h.Nc, B * Tl, Tin + 1)) {
         h.ATps[l] = take_split(ar, Tin + 1, rup(h.Nc, 32));
         rd_rows = std::max(rd_rows, B * Tl);
       }
@@ -292,6 +416,23 @@ void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<
     LAUNCH(k_ryhat<T>, Nc * B, h.RZ[L], h.Yhat + n0 * m.T[L - 1], Nc, B, m.T[L - 1], h.RD[L]);
     for (int l = L - 1; l >= 2; --l) {
       const int64_t Tl = m.T[l - 1], Tn = m.T[l];
+      if constexpr (sizeof(T) == 4) {
+        if (h.ATps[l].p && fused_rdelta(m, l, Nc, B)) {
+          // formed, split and transposed at once into the accumulation operand
+          SplitMat a = h.RDps;
+          a.kpad = rup(Nc, 32);
+          const int64_t blocks = ((a.kpad + 63) / 64) * ((B * Tl + 63) / 64);
+          if (!launch_ok(ex)) return;
+          auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, ex.stream, h.RZ[l], h.RD[l + 1],
+                               h.W[l + 1], h.delta[l + 1] + n0 * Tn, h.Vbar[l + 1], h.D1[l] + n0 * Tl,
+                               h.CE[l] + n0 * Tl, Nc, B, (int)Tl, (int)Tn, a.kpad,
+                               reinterpret_cast<uint32_t*>(a.p), a.ld, a.plane);
+          };
+          if (Tn <= 16) go(k_rdelta_split<16>); else go(k_rdelta_split<RDS_TN>);
+          continue;
+        }
+      }
       // R{delta^(l+1)} W^(l)   ((N_c B) x T_l)
       gemm_rm<T>(ex, false, false, Nc * B, Tl, Tn, T(1), h.RD[l + 1], Tn, h.W[l + 1], Tl, T(0), h.RD[l], Tl);
       // + delta^(l+1) V_W^(l)_b, batched over directions b
@@ -310,10 +451,10 @@ void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<
       // R{delta^(l)}^T Abar^(l-1): ((B T_l) x (T_in + 1)), contraction over n
       bool done = false;
       if constexpr (sizeof(T) == 4) {
-        if (h.ATps[l].p && presplit_acc(Nc)) {
+        if (h.ATps[l].p && presplit_acc(Nc, B * Tl, Tin + 1)) {
           SplitMat a = h.RDps, b = h.ATps[l];
           a.kpad = b.kpad = rup(Nc, 32);
-          split_transpose(ex, h.RD[l], Nc, B * Tl, B * Tl, a);
+          if (!fused_rdelta(m, l, Nc, B)) split_transpose(ex, h.RD[l], Nc, B * Tl, B * Tl, a);
           split_transpose(ex, h.abar[l - 1] + n0 * p.lda[l - 1], Nc, Tin + 1, p.lda[l - 1], b);
           gemm_presplit(ex, B * Tl, Tin + 1, a, b, invN, beta_acc, h.HVbar[l], Tin + 1);
           done = true;

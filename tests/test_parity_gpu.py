@@ -200,15 +200,20 @@ def test_presplit_ragged_n_ignores_stale_workspace(api, T, acts, N, seed):
 MNIST_BLOCKS = [(0, 16), (29784, 29800), (78490, 78506), (79494, 79510)]
 
 
-def test_mnist_shaped_full_size_sampled_columns(api):
-    # the configuration the bench times: full N = 60000, FP32 H and OPG, BF16 OPG
-    print("case mnist-shaped [784, 100, 10] relu N=60000, column blocks %s" % MNIST_BLOCKS, flush=True)
+@pytest.fixture(scope="module")
+def mnist_refs():
     w = workloads.mnist_relu()
     om, Xo, Yo = oracle_of(w)
+    return w, om, Xo, Yo, {b: mlp.hessian_cols(om, Xo, Yo, b[0], b[1]) for b in MNIST_BLOCKS}
+
+
+def test_mnist_shaped_full_size_sampled_columns(api, mnist_refs):
+    # the configuration the bench times: full N = 60000, FP32 H and OPG, BF16 OPG
+    print("case mnist-shaped [784, 100, 10] relu N=60000, column blocks %s" % MNIST_BLOCKS, flush=True)
+    w, om, Xo, Yo, refs = mnist_refs
     model = api.MLP.from_workload(w, dtype=torch.float32)
     X = torch.from_numpy(w.X).to("cuda")
     Y = torch.from_numpy(w.Y).to("cuda")
-    refs = {b: mlp.hessian_cols(om, Xo, Yo, b[0], b[1]) for b in MNIST_BLOCKS}
     for prec in ("f32", "f32_split"):
         H = api.hess_exact(model, X, Y, prec)
         rowsH = {b: H[b[0]:b[1], :].double().cpu().numpy() for b in MNIST_BLOCKS}
@@ -227,6 +232,42 @@ def test_mnist_shaped_full_size_sampled_columns(api):
         del G
         torch.cuda.empty_cache()
         assert report("mnist OPG[:, blocks] %s" % prec, Gc, Gref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f32_split"])
+def test_mnist_shaped_full_size_hvp_block(api, mnist_refs, prec):
+    # 64 directions at full N = 60000 (the bench's HVP configuration in width, in chunks of
+    # examples): the basis vectors of the four column blocks, so that H V^T holds those
+    # columns of H; with split products the R-backward step of the hidden layer is formed,
+    # split and transposed in one pass (a block of 64 directions fills the device)
+    w, om, Xo, Yo, refs = mnist_refs
+    print("case mnist-shaped HVP, 64 basis directions, full N, %s" % prec, flush=True)
+    model = api.MLP.from_workload(w, dtype=torch.float32)
+    X = torch.from_numpy(w.X).to("cuda")
+    Y = torch.from_numpy(w.Y).to("cuda")
+    cols = [c for b in MNIST_BLOCKS for c in range(b[0], b[1])]
+    V = torch.zeros((len(cols), model.P), dtype=torch.float32, device="cuda")
+    for k, c in enumerate(cols):
+        V[k, c] = 1.0
+    HV = api.hess_hvp(model, X, Y, V, prec).double().cpu().numpy()
+    ref = np.concatenate([refs[b] for b in MNIST_BLOCKS], axis=1).T
+    assert report("mnist HV (64 basis directions) %s" % prec, HV, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("N", [2000, 333])
+@pytest.mark.parametrize("prec", ["f32", "f32_split"])
+def test_wide_direction_block_hvp(api, N, prec):
+    # MNIST-shaped layers at a small N: 64 random directions against the oracle (the
+    # one-pass R-backward step with split products); both example counts end in a partial
+    # 64-example tile and a zero-padded 32-example chunk of the contraction
+    print("case wide-block HVP [784, 100, 10] relu N=%d B=64 %s" % (N, prec), flush=True)
+    w = workloads.mlp_gaussian([784, 100, 10], ["relu"], N, 21, dtype="float32")
+    model, X, Y = to_dev(api, w, w.dtype)
+    om, Xo, Yo = oracle_of(w)
+    V = workloads.gaussian_directions(64, model.P, 5, dtype="float32")
+    ref = mlp.hvp(om, Xo, Yo, V.astype(np.float64))
+    HV = api.hess_hvp(model, X, Y, torch.from_numpy(V).cuda(), prec).double().cpu().numpy()
+    assert report("wide-block HV N=%d %s" % (N, prec), HV, ref) <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f32_split"])
