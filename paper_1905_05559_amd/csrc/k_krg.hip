@@ -876,40 +876,65 @@ constexpr int persist_lds_bytes() {
 }
 constexpr int PERSIST_PARTS = 8;
 
+// Next tile of a persistent launch for this workgroup (the same value in every lane), or -1
+// once every part is exhausted.  visited: parts found exhausted so far (thread 0's copy).
+__device__ __forceinline__ int64_t persistent_next(int64_t total, unsigned long long* counters, int& visited,
+                                                   int64_t* tsh) {
+  const int64_t per = (total + PERSIST_PARTS - 1) / PERSIST_PARTS;
+  const int home = (int)(blockIdx.x % PERSIST_PARTS);
+  if (threadIdx.x == 0) {
+    int64_t t = -1;
+    while (visited < PERSIST_PARTS) {
+      const int x = (home + visited) % PERSIST_PARTS;
+      const int64_t lo = x * per, hi = min(total, lo + per);
+      if (lo < hi) {
+        const int64_t k = (int64_t)atomicAdd(&counters[x], 1ull);
+        if (lo + k < hi) {
+          t = lo + k;
+          break;
+        }
+      }
+      ++visited;
+    }
+    *tsh = t;
+  }
+  __syncthreads();
+  // the tile (hence the job and its arguments) is the same for the whole workgroup:
+  // uniform values let the job's arguments live in scalar registers
+  const uint64_t tu = (uint64_t)*tsh;
+  const int64_t t = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((int)(tu >> 32)) << 32) |
+                              (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)tu));
+  __syncthreads();
+  return t;
+}
+
+// The job list is read through the constant address space: with a workgroup-uniform job
+// index its fields are scalar loads, so the buffer descriptors the tile builds from them
+// are uniform (a descriptor the compiler cannot prove uniform costs a loop around every
+// buffer load).
+typedef const __attribute__((address_space(4))) KrgJob* cjob_ptr;
+
+// Job of tile t: the last job whose first tile is at most t.
+__device__ __forceinline__ const KrgJob& persistent_job(const KrgJob* jobs, int njobs, int64_t t) {
+  cjob_ptr cj = (cjob_ptr)jobs;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (cj[mid].first <= t) lo = mid; else hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  return *(const KrgJob*)(cj + lo);
+}
+
 template <int MAXU, class C>
 __global__ __launch_bounds__(256, 2) void krg_persistent(const KrgJob* jobs, int njobs, int64_t total,
                                                          unsigned long long* counters) {
   __shared__ int64_t tsh;
-  const int64_t per = (total + PERSIST_PARTS - 1) / PERSIST_PARTS;
-  const int home = (int)(blockIdx.x % PERSIST_PARTS);
-  int visited = 0;  // parts found exhausted (thread 0 only)
+  int visited = 0;
   for (;;) {
-    if (threadIdx.x == 0) {
-      int64_t t = -1;
-      while (visited < PERSIST_PARTS) {
-        const int x = (home + visited) % PERSIST_PARTS;
-        const int64_t lo = x * per, hi = min(total, lo + per);
-        if (lo < hi) {
-          const int64_t k = (int64_t)atomicAdd(&counters[x], 1ull);
-          if (lo + k < hi) {
-            t = lo + k;
-            break;
-          }
-        }
-        ++visited;
-      }
-      tsh = t;
-    }
-    __syncthreads();
-    const int64_t t = tsh;
-    __syncthreads();
+    const int64_t t = persistent_next(total, counters, visited, &tsh);
     if (t < 0) break;
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) / 2;
-      if (jobs[mid].first <= t) lo = mid; else hi = mid - 1;
-    }
-    const KrgJob& J = jobs[lo];
+    const KrgJob& J = persistent_job(jobs, njobs, t);
     const int64_t lt = t - J.first;
     switch (J.mode * 2 + (J.a.symmetric ? 1 : 0)) {
       case KRG_RANK1 * 2 + 0: krg_tile_dma<KRG_RANK1, false, MAXU, C>(J.a, lt, J.tiles_c, dma_smem); break;

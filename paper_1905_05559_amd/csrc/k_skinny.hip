@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256, SR <= 32 ? 4 : 2) void k_skinny_f32(const floa
   using L = SkinnyLds<SR>;
   constexpr int RB = SR / 16;                // 16-row blocks
   constexpr int QPT = SR * SKC / 256;        // Q values loaded per thread per chunk
-  __shared__ float sm[2 * L::STAGE];
+  __shared__ __attribute__((aligned(16))) float sm[2 * L::STAGE];
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
   if (t < 0) return;
   const int64_t sp = t / ncb, cb = t - sp * ncb;
@@ -52,10 +52,15 @@ __global__ __launch_bounds__(256, SR <= 32 ? 4 : 2) void k_skinny_f32(const floa
   // rows only (none past the slice); invalid columns and rows get offsets beyond it.
   const __amdgpu_buffer_rsrc_t rq =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Q), (short)0, (int)(b * ldq * 4), 0x00020000);
-  const int64_t col = c0 + tid;
-  const uint32_t coff = col < P ? (uint32_t)(col * 4) : 0x80000000u;
+  // M: each lane loads 16 bytes (4 columns) of 4 rows of the chunk (rows 4 w .. 4 w + 3):
+  // one 1 KB row segment per wavefront load instead of four.  Columns past P in a row
+  // before the last read the next row's first entries and feed only output columns that
+  // are never stored; past the resource's extent the load reads zeros.
+  const int64_t col4 = c0 + 4 * lane;
+  const uint32_t coff = col4 < P ? (uint32_t)(col4 * 4) : 0x80000000u;
+  constexpr int RPW = SKC / 4;  // rows of a chunk per wavefront
   struct Regs {
-    float m[SKC];
+    f4_t m[RPW];
     float q[QPT];
   };
   auto load = [&](int ch, Regs& g) {
@@ -64,8 +69,9 @@ __global__ __launch_bounds__(256, SR <= 32 ? 4 : 2) void k_skinny_f32(const floa
     const __amdgpu_buffer_rsrc_t rm = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float*>(M + (rows > 0 ? kk : k0) * ldm), (short)0, (int)(rows * ldm * 4), 0x00020000);
 #pragma unroll
-    for (int r = 0; r < SKC; ++r)
-      g.m[r] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rm, coff + (uint32_t)(r * ldm * 4), 0, 0));
+    for (int r = 0; r < RPW; ++r)
+      g.m[r] = __builtin_bit_cast(
+          f4_t, __builtin_amdgcn_raw_buffer_load_b128(rm, coff + (uint32_t)((RPW * w + r) * ldm * 4), 0, 0));
 #pragma unroll
     for (int i = 0; i < QPT; ++i) {
       const int e = tid + 256 * i;               // e = row * SKC + kq
@@ -79,7 +85,7 @@ __global__ __launch_bounds__(256, SR <= 32 ? 4 : 2) void k_skinny_f32(const floa
     float* ms = sm + buf * L::STAGE;
     float* qs = ms + L::M;
 #pragma unroll
-    for (int r = 0; r < SKC; ++r) ms[r * MSTR + tid] = g.m[r];
+    for (int r = 0; r < RPW; ++r) *reinterpret_cast<f4_t*>(&ms[(RPW * w + r) * MSTR + 4 * lane]) = g.m[r];
 #pragma unroll
     for (int i = 0; i < QPT; ++i) {
       const int e = tid + 256 * i;
