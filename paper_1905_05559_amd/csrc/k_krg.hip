@@ -354,6 +354,12 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 
 __device__ __forceinline__ int64_t mn64(int64_t x, int64_t y) { return x < y ? x : y; }
+// A value known to be the same in every lane, moved to scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
+}
 
 // Raw buffer over `elems` (>= 0) floats from base; the byte count is capped below 2^31
 // (copy offsets are checked on the host to stay below the cap).
@@ -901,9 +907,7 @@ __device__ __forceinline__ int64_t persistent_next(int64_t total, unsigned long 
   __syncthreads();
   // the tile (hence the job and its arguments) is the same for the whole workgroup:
   // uniform values let the job's arguments live in scalar registers
-  const uint64_t tu = (uint64_t)*tsh;
-  const int64_t t = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((int)(tu >> 32)) << 32) |
-                              (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)tu));
+  const int64_t t = uniform64(*tsh);
   __syncthreads();
   return t;
 }
