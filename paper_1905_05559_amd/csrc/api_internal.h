@@ -106,6 +106,9 @@ struct HvpBufs {
   bool split = false;
   std::vector<SplitMat> Vps, Aps, ATps;
   SplitMat RDps;
+  // one-pass R-backward step of a last hidden layer (FP32 split products): per-tile partials
+  // of delta^(L)^T R{A^(L-1)} over 64-example tiles, summed by the accumulation
+  T* RApart = nullptr;
 };
 template <typename T>
 size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, bool split = false);

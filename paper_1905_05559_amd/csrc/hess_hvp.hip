@@ -105,41 +105,25 @@ __global__ void k_rdelta(T* RD, const T* RZ, const T* D1, const T* CE, int64_t N
 // as broadcasts; RZ, D1 and CE are read along c; the finished tile is split and written
 // transposed through LDS as in k_split_transpose.
 constexpr int RDS_TN = 32;
+constexpr int RDS_SUB = 1;  // 64-example subtiles of a workgroup (4 measured slower: 21 against 16 ms per 512 HVPs)
 template <int TN>
 __global__ __launch_bounds__(256) void k_rdelta_split(const float* __restrict__ RZ, const float* __restrict__ RDn,
                                                       const float* __restrict__ Wn, const float* __restrict__ dn,
                                                       const float* __restrict__ Vn, const float* __restrict__ D1,
                                                       const float* __restrict__ CE, int64_t Nc, int64_t B, int Tl,
                                                       int Tn, int64_t rpad, uint32_t* __restrict__ dst, int64_t ld,
-                                                      int64_t pl) {
+                                                      int64_t pl, float* __restrict__ part) {
   __shared__ __attribute__((aligned(16))) float rdn_s[64][3 * TN];
   __shared__ __attribute__((aligned(16))) float dn_s[64][TN];
   __shared__ float tile[64][65];
+  __shared__ float red[4][TN][64];
   const int64_t BT = B * Tl;
-  const int64_t tn = (rpad + 63) / 64;
-  const int64_t n0 = (int64_t)(blockIdx.x % tn) * 64, c0 = (int64_t)(blockIdx.x / tn) * 64;
+  const int64_t tn = (rpad + 64 * RDS_SUB - 1) / (64 * RDS_SUB);
+  const int64_t grp = (int64_t)(blockIdx.x % tn), c0 = (int64_t)(blockIdx.x / tn) * 64;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t blo = c0 / Tl;
   const int nbt = (int)(std::min(c0 + 63, BT - 1) / Tl - blo + 1);  // directions in the tile (<= 3)
-  // every global read of the tile is issued before any is used (fully unrolled loops), so
-  // a wavefront waits for memory once rather than once per row
-  constexpr int RE = 64 * 3 * TN / 256, DE = 64 * TN / 256;
-  float rv[RE], dv[DE];
-#pragma unroll
-  for (int x = 0; x < RE; ++x) {
-    const int e = threadIdx.x + 256 * x;
-    const int y = e / (3 * TN), j = e - y * (3 * TN), bq = j / TN, k = j - bq * TN;
-    const int64_t n = n0 + y;
-    rv[x] = (n < Nc && bq < nbt && k < Tn) ? RDn[(n * B + blo + bq) * Tn + k] : 0.f;
-  }
-#pragma unroll
-  for (int x = 0; x < DE; ++x) {
-    const int e = threadIdx.x + 256 * x;
-    const int y = e / TN, k = e - y * TN;
-    const int64_t n = n0 + y;
-    dv[x] = (n < Nc && k < Tn) ? dn[n * Tn + k] : 0.f;
-  }
   const int64_t c = c0 + lane;
   const bool cok = c < BT;
   const int64_t b = cok ? c / Tl : blo;
@@ -151,57 +135,171 @@ __global__ __launch_bounds__(256) void k_rdelta_split(const float* __restrict__ 
     wr[k] = cok && k < Tn ? Wn[(int64_t)k * Tl + t] : 0.f;
     vr[k] = cok && k < Tn ? Vn[(b * Tn + k) * (Tl + 1) + t] : 0.f;
   }
-  // this wavefront's rows y = wave + 4 i
-  float zr[16], d1r[16], cer[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int64_t n = n0 + wave + 4 * i;
-    const bool ok = cok && n < Nc;
-    zr[i] = ok ? RZ[n * BT + c] : 0.f;
-    d1r[i] = ok ? D1[n * Tl + t] : 0.f;
-    cer[i] = ok ? CE[n * Tl + t] : 0.f;
-  }
-#pragma unroll
-  for (int x = 0; x < RE; ++x) (&rdn_s[0][0])[threadIdx.x + 256 * x] = rv[x];
-#pragma unroll
-  for (int x = 0; x < DE; ++x) (&dn_s[0][0])[threadIdx.x + 256 * x] = dv[x];
-  __syncthreads();
   const int nq = (Tn + 3) / 4;
+  float pacc[TN];  // this wavefront's rows of sum_n dn[n][k] R{A}[n][c] (R{A} = D1 * RZ)
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int y = wave + 4 * i;
-    const f4_t* rp = reinterpret_cast<const f4_t*>(&rdn_s[y][bb * TN]);
-    const f4_t* dp = reinterpret_cast<const f4_t*>(&dn_s[y][0]);
-    float acc = 0.f;
-#pragma unroll
-    for (int qd = 0; qd < TN / 4; ++qd) {
-      if (qd < nq) {
-        const f4_t r4 = rp[qd];
-        acc += r4[0] * wr[4 * qd] + r4[1] * wr[4 * qd + 1] + r4[2] * wr[4 * qd + 2] + r4[3] * wr[4 * qd + 3];
-      }
-    }
-#pragma unroll
-    for (int qd = 0; qd < TN / 4; ++qd) {
-      if (qd < nq) {
-        const f4_t d4 = dp[qd];
-        acc += d4[0] * vr[4 * qd] + d4[1] * vr[4 * qd + 1] + d4[2] * vr[4 * qd + 2] + d4[3] * vr[4 * qd + 3];
-      }
-    }
-    tile[y][lane] = d1r[i] * acc + cer[i] * zr[i];  // zero outside the chunk and past the columns
-  }
-  __syncthreads();
+  for (int k = 0; k < TN; ++k) pacc[k] = 0.f;
   const SplitC sc = split_consts();
-  const int pr = threadIdx.x & 31;  // pair of rows 2 pr, 2 pr + 1 of the tile
-  for (int cc = threadIdx.x >> 5; cc < 64; cc += 8) {
-    const int64_t col = c0 + cc, r = n0 + 2 * pr;
-    if (col >= BT || r >= rpad) continue;
-    bf2_t h, m, l;
-    split3x2(f2_t{tile[2 * pr][cc], tile[2 * pr + 1][cc]}, h, m, l, sc);
-    const int64_t o = (col * ld + r) / 2;
-    dst[o] = __builtin_bit_cast(uint32_t, h);
-    dst[o + pl / 2] = __builtin_bit_cast(uint32_t, m);
-    dst[o + pl] = __builtin_bit_cast(uint32_t, l);
+  constexpr int RE = 64 * 3 * TN / 256, DE = 64 * TN / 256;
+  for (int sub = 0; sub < RDS_SUB; ++sub) {
+    const int64_t n0 = (grp * RDS_SUB + sub) * 64;
+    if (n0 >= rpad) break;
+    // every global read of the subtile is issued before any is used (fully unrolled loops),
+    // so a wavefront waits for memory once rather than once per row
+    float rv[RE], dv[DE];
+#pragma unroll
+    for (int x = 0; x < RE; ++x) {
+      const int e = threadIdx.x + 256 * x;
+      const int y = e / (3 * TN), j = e - y * (3 * TN), bq = j / TN, k = j - bq * TN;
+      const int64_t n = n0 + y;
+      rv[x] = (n < Nc && bq < nbt && k < Tn) ? RDn[(n * B + blo + bq) * Tn + k] : 0.f;
+    }
+#pragma unroll
+    for (int x = 0; x < DE; ++x) {
+      const int e = threadIdx.x + 256 * x;
+      const int y = e / TN, k = e - y * TN;
+      const int64_t n = n0 + y;
+      dv[x] = (n < Nc && k < Tn) ? dn[n * Tn + k] : 0.f;
+    }
+    // this wavefront's rows y = wave + 4 i
+    float zr[16], d1r[16], cer[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int64_t n = n0 + wave + 4 * i;
+      const bool ok = cok && n < Nc;
+      zr[i] = ok ? RZ[n * BT + c] : 0.f;
+      d1r[i] = ok ? D1[n * Tl + t] : 0.f;
+      cer[i] = ok ? CE[n * Tl + t] : 0.f;
+    }
+    __syncthreads();  // the previous subtile's LDS reads are done
+#pragma unroll
+    for (int x = 0; x < RE; ++x) (&rdn_s[0][0])[threadIdx.x + 256 * x] = rv[x];
+#pragma unroll
+    for (int x = 0; x < DE; ++x) (&dn_s[0][0])[threadIdx.x + 256 * x] = dv[x];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int y = wave + 4 * i;
+      const f4_t* rp = reinterpret_cast<const f4_t*>(&rdn_s[y][bb * TN]);
+      const f4_t* dp = reinterpret_cast<const f4_t*>(&dn_s[y][0]);
+      if (part) {
+        const float ra = d1r[i] * zr[i];
+#pragma unroll
+        for (int qd = 0; qd < TN / 4; ++qd) {
+          if (qd < nq) {
+            const f4_t d4 = dp[qd];
+            pacc[4 * qd] += d4[0] * ra;
+            pacc[4 * qd + 1] += d4[1] * ra;
+            pacc[4 * qd + 2] += d4[2] * ra;
+            pacc[4 * qd + 3] += d4[3] * ra;
+          }
+        }
+      }
+      float acc = 0.f;
+#pragma unroll
+      for (int qd = 0; qd < TN / 4; ++qd) {
+        if (qd < nq) {
+          const f4_t r4 = rp[qd];
+          acc += r4[0] * wr[4 * qd] + r4[1] * wr[4 * qd + 1] + r4[2] * wr[4 * qd + 2] + r4[3] * wr[4 * qd + 3];
+        }
+      }
+#pragma unroll
+      for (int qd = 0; qd < TN / 4; ++qd) {
+        if (qd < nq) {
+          const f4_t d4 = dp[qd];
+          acc += d4[0] * vr[4 * qd] + d4[1] * vr[4 * qd + 1] + d4[2] * vr[4 * qd + 2] + d4[3] * vr[4 * qd + 3];
+        }
+      }
+      tile[y][lane] = d1r[i] * acc + cer[i] * zr[i];  // zero outside the chunk and past the columns
+    }
+    __syncthreads();
+    const int pr = threadIdx.x & 31;  // pair of rows 2 pr, 2 pr + 1 of the tile
+    for (int cc = threadIdx.x >> 5; cc < 64; cc += 8) {
+      const int64_t col = c0 + cc, r = n0 + 2 * pr;
+      if (col >= BT || r >= rpad) continue;
+      bf2_t h, m, l;
+      split3x2(f2_t{tile[2 * pr][cc], tile[2 * pr + 1][cc]}, h, m, l, sc);
+      const int64_t o = (col * ld + r) / 2;
+      dst[o] = __builtin_bit_cast(uint32_t, h);
+      dst[o + pl / 2] = __builtin_bit_cast(uint32_t, m);
+      dst[o + pl] = __builtin_bit_cast(uint32_t, l);
+    }
   }
+  if (part) {
+#pragma unroll
+    for (int k = 0; k < TN; ++k) red[wave][k][lane] = pacc[k];
+    __syncthreads();
+    // the group's partial over its examples: waves summed in order
+    if (cok)
+      for (int k = wave; k < Tn; k += 4)
+        part[(grp * Tn + k) * BT + c] = ((red[0][k][lane] + red[1][k][lane]) + red[2][k][lane]) + red[3][k][lane];
+  }
+}
+
+// HVbar_next_b[k][t] += invN sum_j part[j][k][b T_l + t] for the weight columns t < T_l of the
+// next layer's block of every direction b: the delta^(l+1)^T R{A^(l)} term of the accumulation,
+// summed over the example tiles of a chunk in tile order.
+__global__ __launch_bounds__(256) void k_sum_rapart(const float* __restrict__ part, int64_t ntiles, int Tn,
+                                                    int64_t B, int Tl, float invN, float* __restrict__ HVn) {
+  const int64_t BT = B * Tl;
+  GRID_STRIDE(e, (int64_t)Tn * BT) {
+    const int64_t k = e / BT, c = e - k * BT, b = c / Tl, t = c - b * Tl;
+    float sum = 0.f;
+    for (int64_t j = 0; j < ntiles; ++j) sum += part[(j * Tn + k) * BT + c];
+    HVn[(b * Tn + k) * (Tl + 1) + t] += invN * sum;
+  }
+}
+
+// RZn[r][k] += sum_t D1[n][t] RZ[r][t] Wn[k][t] for the rows r = n B + b of a chunk: the
+// R{A^(l)} W^(l)^T term of the next layer's R{Z} with R{A^(l)} = sigma'(Z^(l)) * R{Z^(l)} formed
+// on the fly.  A wavefront owns 64 rows (a lane one row and its T_{l+1} <= TN sums); chunks
+// of 32 of the T_l columns of its rows and of sigma' are staged in LDS with reads along t.
+template <int TN>
+__global__ __launch_bounds__(256) void k_rz_next(const float* __restrict__ RZ, const float* __restrict__ D1,
+                                                 const float* __restrict__ Wn, int64_t rows, int64_t B, int Tl, int Tn,
+                                                 float* __restrict__ RZn) {
+  __shared__ float ras[4][64][33];  // R{A} of this wavefront's rows, 32 columns at a time
+  __shared__ float ws[TN][32];
+  __shared__ int64_t nrow[4][64];   // example of each row
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r0 = (int64_t)blockIdx.x * 256 + wave * 64;
+  nrow[wave][lane] = (r0 + lane) / B;
+  float acc[TN];
+#pragma unroll
+  for (int k = 0; k < TN; ++k) acc[k] = 0.f;
+  for (int t0 = 0; t0 < Tl; t0 += 32) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < TN * 32; e += 256) {
+      const int k = e >> 5, tt = e & 31;
+      ws[k][tt] = (k < Tn && t0 + tt < Tl) ? Wn[(int64_t)k * Tl + t0 + tt] : 0.f;
+    }
+    // all 32 reads of R{Z} and of sigma' issued before any is used
+    float zv[32], dv[32];
+#pragma unroll
+    for (int x = 0; x < 32; ++x) {
+      const int e = lane + 64 * x, i = e >> 5, tt = e & 31;
+      const int64_t rr = r0 + i;
+      const bool ok = rr < rows && t0 + tt < Tl;
+      zv[x] = ok ? RZ[rr * Tl + t0 + tt] : 0.f;
+      dv[x] = ok ? D1[nrow[wave][i] * Tl + t0 + tt] : 0.f;
+    }
+#pragma unroll
+    for (int x = 0; x < 32; ++x) {
+      const int e = lane + 64 * x;
+      ras[wave][e >> 5][e & 31] = dv[x] * zv[x];
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int tt = 0; tt < 32; ++tt) {
+      const float ra = ras[wave][lane][tt];
+#pragma unroll
+      for (int k = 0; k < TN; ++k) acc[k] += ra * ws[k][tt];
+    }
+  }
+  const int64_t r = r0 + lane;
+  if (r < rows)
+    for (int k = 0; k < Tn; ++k) RZn[r * Tn + k] += acc[k];
 }
 
 // S[n][b] = sum_i delta2[n][i] U2[n][b][i] + (same for layers 3 and 4 when present)
@@ -272,6 +370,11 @@ static bool presplit_acc(int64_t Nc, int64_t rows, int64_t cols) {
 static bool fused_rdelta(const Model& m, int l, int64_t Nc, int64_t B) {
   return l == 2 && m.L >= 3 && m.T[l] <= RDS_TN && m.T[l - 1] >= 32 && presplit_acc(Nc, B * m.T[l - 1], m.T[l - 2] + 1);
 }
+// ... and, when that layer is the last hidden one, R{A^(2)} = sigma' * R{Z^(2)} is never
+// stored: the output layer's R{Z} reads R{Z^(2)} and sigma' (k_rz_next) and the one-pass
+// step leaves the partials of delta^(3)^T R{A^(2)} (k_sum_rapart).
+static bool fused_ra(const Model& m, int64_t Nc, int64_t B) { return m.L == 3 && fused_rdelta(m, 2, Nc, B); }
+static int64_t rapart_tiles(int64_t Nc) { return (rup(Nc, 32) + 64 * RDS_SUB - 1) / (64 * RDS_SUB); }
 
 template <typename T>
 size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<T>& h, bool split) {
@@ -330,6 +433,7 @@ size_t plan_hvp(Arena& ar, const Model& m, int64_t N, int64_t B, Prep& p, HvpBuf
       }
     }
     if (rd_rows > 0) h.RDps = take_split(ar, rd_rows, rup(h.Nc, 32));
+    if (fused_ra(m, h.Nc, B)) h.RApart = ar.take<T>(rapart_tiles(h.Nc) * m.T[2] * B * m.T[1]);
   }
   return ar.used;
 }
@@ -392,6 +496,7 @@ void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<
   for (int64_t n0 = 0; n0 < N; n0 += h.Nc) {
     const int64_t Nc = std::min(h.Nc, N - n0);
     const T beta_acc = n0 == 0 ? T(0) : T(1);
+    const bool fra = sizeof(T) == 4 && h.RApart && h.ATps[2].p && fused_ra(m, Nc, B);
     // ---- R-forward
     for (int l = 2; l <= L; ++l) {
       const int64_t Tl = m.T[l - 1], Tin = m.T[l - 2];
@@ -408,9 +513,21 @@ void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<
         gemm_rm<T>(ex, false, true, Nc, B * Tl, Tin + 1, T(1), h.abar[l - 1] + n0 * p.lda[l - 1], p.lda[l - 1],
                    h.Vbar[l], Tin + 1, T(0), h.RZ[l], B * Tl);
       // ... + R{A^(l-1)} W^(l-1)^T  ((N_c B) x T_l)
+      if constexpr (sizeof(T) == 4) {
+        if (l == 3 && fra) {
+          const int64_t rows = Nc * B;
+          if (!launch_ok(ex)) return;
+          auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, ex.stream, h.RZ[2],
+                               h.D1[2] + n0 * Tin, h.W[3], rows, B, (int)Tin, (int)Tl, h.RZ[3]);
+          };
+          if (Tl <= 16) go(k_rz_next<16>); else go(k_rz_next<RDS_TN>);
+          continue;  // (l == L: no R{A^(3)})
+        }
+      }
       if (l >= 3)
         gemm_rm<T>(ex, false, true, Nc * B, Tl, Tin, T(1), h.RA[l - 1], Tin, h.W[l], Tin, T(1), h.RZ[l], Tl);
-      if (l < L) LAUNCH(k_ra<T>, Nc * B * Tl, h.RZ[l], h.D1[l] + n0 * Tl, Nc, B, Tl, h.RA[l]);
+      if (l < L && !fra) LAUNCH(k_ra<T>, Nc * B * Tl, h.RZ[l], h.D1[l] + n0 * Tl, Nc, B, Tl, h.RA[l]);
     }
     // ---- R-backward
     LAUNCH(k_ryhat<T>, Nc * B, h.RZ[L], h.Yhat + n0 * m.T[L - 1], Nc, B, m.T[L - 1], h.RD[L]);
@@ -421,13 +538,13 @@ void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<
           // formed, split and transposed at once into the accumulation operand
           SplitMat a = h.RDps;
           a.kpad = rup(Nc, 32);
-          const int64_t blocks = ((a.kpad + 63) / 64) * ((B * Tl + 63) / 64);
+          const int64_t blocks = ((a.kpad + 64 * RDS_SUB - 1) / (64 * RDS_SUB)) * ((B * Tl + 63) / 64);
           if (!launch_ok(ex)) return;
           auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, ex.stream, h.RZ[l], h.RD[l + 1],
                                h.W[l + 1], h.delta[l + 1] + n0 * Tn, h.Vbar[l + 1], h.D1[l] + n0 * Tl,
                                h.CE[l] + n0 * Tl, Nc, B, (int)Tl, (int)Tn, a.kpad,
-                               reinterpret_cast<uint32_t*>(a.p), a.ld, a.plane);
+                               reinterpret_cast<uint32_t*>(a.p), a.ld, a.plane, fra ? h.RApart : nullptr);
           };
           if (Tn <= 16) go(k_rdelta_split<16>); else go(k_rdelta_split<RDS_TN>);
           continue;
@@ -463,6 +580,15 @@ void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<
       if (!done)
         gemm_rm<T>(ex, true, false, B * Tl, Tin + 1, Nc, invN, h.RD[l], B * Tl, h.abar[l - 1] + n0 * p.lda[l - 1],
                    p.lda[l - 1], beta_acc, h.HVbar[l], Tin + 1);
+      if constexpr (sizeof(T) == 4) {
+        if (l == 3 && fra) {  // + delta^(3)^T R{A^(2)}_b from the one-pass step's partials
+          const int64_t tot = Tl * B * Tin;
+          if (!launch_ok(ex)) return;
+          hipLaunchKernelGGL(k_sum_rapart, dim3(grid_for(tot)), dim3(TPB), 0, ex.stream, h.RApart,
+                             rapart_tiles(Nc), (int)Tl, B, (int)Tin, (float)invN, h.HVbar[3]);
+          continue;
+        }
+      }
       if (l >= 3) {
         // + delta^(l)^T R{A^(l-1)}_b for all directions at once: R{A} of the chunk is
         // N_c x (B T_in), so this is one T_l x (B T_in) product (rather than B products of
