@@ -44,9 +44,9 @@ __device__ __forceinline__ int64_t flat_index(int32_t perm, int64_t off, int32_t
 __device__ __forceinline__ void tile_of(int64_t t, bool symmetric, int64_t tiles_c, int64_t tiles_r, int64_t& tr,
                                         int64_t& tc) {
   if (symmetric)
-    grouped_lower_tile(t, tiles_r, tr, tc);
+    grouped_lower_tile<16>(t, tiles_r, tr, tc);
   else
-    grouped_full_tile(t, tiles_c, tiles_r, tr, tc);
+    grouped_full_tile<16>(t, tiles_c, tiles_r, tr, tc);
 }
 
 template <typename TOut>

@@ -98,12 +98,14 @@ inline int64_t xcd_grid(int64_t ntiles) { return (ntiles + 7) & ~int64_t(7); }
 // Grouped tile orders: consecutive tile ids walk TILE_GROUP row panels column by column,
 // so the tiles an XCD runs at once (a contiguous id range, see xcd_tile) share a few row
 // and column panels in its L2 instead of one row panel and many column panels.
+// G = 8 suits the BF16 Gram (321 ms on the MNIST-shaped OPG, 336 at 16); the Khatri-Rao
+// contractions take 16 (their dominant launch 1 598 -> 1 580 ms; 1 584 at 32).
 constexpr int64_t TILE_GROUP = 8;
 
 // Full tiles_r x tiles_c grid.
+template <int64_t G = TILE_GROUP>
 __device__ __forceinline__ void grouped_full_tile(int64_t t, int64_t tiles_c, int64_t tiles_r, int64_t& tr,
                                                   int64_t& tc) {
-  const int64_t G = TILE_GROUP;
   const int64_t g = t / (G * tiles_c), u = t - g * G * tiles_c;
   const int64_t Gg = tiles_r - g * G < G ? tiles_r - g * G : G;
   tc = u / Gg;
@@ -112,10 +114,10 @@ __device__ __forceinline__ void grouped_full_tile(int64_t t, int64_t tiles_c, in
 
 // Lower triangle (tc <= tr) of a tiles_r x tiles_r grid: group g (rows gG .. gG + Gg - 1)
 // holds gG full columns of Gg tiles and then a lower triangle of Gg columns.
+template <int64_t G = TILE_GROUP>
 __device__ __forceinline__ void grouped_lower_tile(int64_t t, int64_t tiles_r, int64_t& tr, int64_t& tc) {
-  const int64_t G = TILE_GROUP;
   // tiles before group g (all full): G^2 g (g - 1) / 2 + g G (G + 1) / 2
-  auto before = [G](int64_t g) { return G * G * g * (g - 1) / 2 + g * G * (G + 1) / 2; };
+  auto before = [](int64_t g) { return G * G * g * (g - 1) / 2 + g * G * (G + 1) / 2; };
   int64_t g = (int64_t)(sqrt(2.0 * (double)t) / (double)G);
   while (g > 0 && before(g) > t) --g;
   while (before(g + 1) <= t && (g + 1) * G < tiles_r) ++g;
