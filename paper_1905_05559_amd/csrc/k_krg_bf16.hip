@@ -266,7 +266,7 @@ __device__ __forceinline__ void gram_dma_tile(const __bf16* __restrict__ Jt, int
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
   if (t < 0) return;
   int64_t tr, tc;
-  grouped_lower_tile(t, (P + GB - 1) / GB, tr, tc);
+  grouped_lower_tile<4>(t, (P + GB - 1) / GB, tr, tc);
   const int64_t r0 = tr * GB, c0 = tc * GB;
   const bool diag = (tr == tc);
 
@@ -381,7 +381,7 @@ __device__ __forceinline__ void gram_pipe_tile(const __bf16* __restrict__ Jt, in
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x, ntiles);
   if (t < 0) return;
   int64_t tr, tc;
-  grouped_lower_tile(t, (P + GB - 1) / GB, tr, tc);
+  grouped_lower_tile<4>(t, (P + GB - 1) / GB, tr, tc);
   const int64_t r0 = tr * GB, c0 = tc * GB;
   const bool diag = (tr == tc);
 

@@ -98,8 +98,8 @@ inline int64_t xcd_grid(int64_t ntiles) { return (ntiles + 7) & ~int64_t(7); }
 // Grouped tile orders: consecutive tile ids walk TILE_GROUP row panels column by column,
 // so the tiles an XCD runs at once (a contiguous id range, see xcd_tile) share a few row
 // and column panels in its L2 instead of one row panel and many column panels.
-// G = 8 suits the BF16 Gram (321 ms on the MNIST-shaped OPG, 336 at 16); the Khatri-Rao
-// contractions take 16 (their dominant launch 1 598 -> 1 580 ms; 1 584 at 32).
+// Measured on the MNIST-shaped step: the BF16 Gram takes G = 4 (318 ms; 323 at 8, 336 at 16),
+// the Khatri-Rao contractions G = 16 (their dominant launch 1 581 ms; 1 598 at 8, 1 584 at 32).
 constexpr int64_t TILE_GROUP = 8;
 
 // Full tiles_r x tiles_c grid.
