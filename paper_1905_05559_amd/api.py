@@ -403,6 +403,25 @@ def hess_predvar(model: MLP, lam: torch.Tensor, Q: torch.Tensor, delta: float, X
     return s
 
 
+def batched_workspace_size(models: List[MLP], Xs: List[torch.Tensor], Ys: List[torch.Tensor],
+                           ctx: Optional[Context] = None, prec: str = "f32") -> int:
+    """Workspace bytes hess_batched needs for these networks (hess_workspace_size, op batched)."""
+    ctx = ctx or default_context()
+    M = len(models)
+    ms = (L.HessMlp * M)()
+    ds = (L.HessData * M)()
+    keep = []
+    for i, (m, X, Y) in enumerate(zip(models, Xs, Ys)):
+        s = m.struct()
+        d = _data(X, Y)
+        keep.append((s, d))
+        ms[i] = s
+        ds[i] = d
+    nb = C.c_size_t()
+    ctx._check(ctx.lib.hess_workspace_size(ctx.h, L.OP["batched"], ms, ds, L.PREC[prec], M, None, C.byref(nb)))
+    return nb.value
+
+
 def hess_batched(models: List[MLP], Xs: List[torch.Tensor], Ys: List[torch.Tensor], with_H: bool = True,
                  with_G: bool = True, outs_H=None, outs_G=None, ctx: Optional[Context] = None, prec: str = "f32"):
     """Exact H and/or OPG (FP32; prec "f32" or "f32_split") of several networks in one call,

@@ -59,6 +59,11 @@ def main():
     # allocation or release of tens of GB); the library workspace only grows
     cap = max(sum(2 * n[0] * n[0] for n in wv) for wv in waves)
     pool = torch.empty(cap, dtype=torch.float32, device=dev)
+    # the library workspace sized once for the largest wave, before the timed loop (a
+    # workspace that grows between waves costs an allocation of several GB inside it)
+    ws_need = max(api.batched_workspace_size([n[2] for n in wv], [n[3] for n in wv], [n[4] for n in wv], ctx=ctx,
+                                             prec=args.prec) for wv in waves)
+    ctx.workspace(ws_need)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     flops = 0.0
