@@ -75,11 +75,12 @@ struct HFactors {
 void compute_factors(Exec& ex, const Model& m, int64_t Nc, int64_t n0, Prep& p, HFactors& f, int mm);
 
 // A matrix split in three BF16 planes (h, m, l; x = h + m + l): part x of element (r, k)
-// at p[x * plane + r * ld + k]; k runs over kpad (a multiple of 32), zero past the true
-// length.  See k_gemm_ps.hip.
+// at p[x * plane + ps_off(r, k, nrb)] (blocks of 16 rows x 32 k in MFMA operand order, see
+// mfma.h); k runs over kpad (a multiple of 32), zero past the true length; rows of the last
+// block past the true count are never written.  See k_gemm_ps.hip.
 struct SplitMat {
   __bf16* p = nullptr;
-  int64_t ld = 0, plane = 0, kpad = 0;
+  int64_t nrb = 0, plane = 0, kpad = 0;  // row blocks of 16 (ps_off layout), plane length, k extent
 };
 // Takes the planes of a rows x kpad split matrix from an arena.
 SplitMat take_split(Arena& ar, int64_t rows, int64_t kpad);

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_rdelta_split(const float* __restrict__ 
                                                       const float* __restrict__ Wn, const float* __restrict__ dn,
                                                       const float* __restrict__ Vn, const float* __restrict__ D1,
                                                       const float* __restrict__ CE, int64_t Nc, int64_t B, int Tl,
-                                                      int Tn, int64_t rpad, uint32_t* __restrict__ dst, int64_t ld,
+                                                      int Tn, int64_t rpad, uint32_t* __restrict__ dst, int64_t nrb,
                                                       int64_t pl, float* __restrict__ part) {
   __shared__ __attribute__((aligned(16))) float rdn_s[64][3 * TN];
   __shared__ __attribute__((aligned(16))) float dn_s[64][TN];
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_rdelta_split(const float* __restrict__ 
       if (col >= BT || r >= rpad) continue;
       bf2_t h, m, l;
       split3x2(f2_t{tile[2 * pr][cc], tile[2 * pr + 1][cc]}, h, m, l, sc);
-      const int64_t o = (col * ld + r) / 2;
+      const int64_t o = ps_off(col, r, nrb) / 2;
       dst[o] = __builtin_bit_cast(uint32_t, h);
       dst[o + pl / 2] = __builtin_bit_cast(uint32_t, m);
       dst[o + pl] = __builtin_bit_cast(uint32_t, l);
@@ -544,7 +544,7 @@ void hvp_apply(Exec& ex, const Model& m, int64_t N, int64_t B, Prep& p, HvpBufs<
             hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, ex.stream, h.RZ[l], h.RD[l + 1],
                                h.W[l + 1], h.delta[l + 1] + n0 * Tn, h.Vbar[l + 1], h.D1[l] + n0 * Tl,
                                h.CE[l] + n0 * Tl, Nc, B, (int)Tl, (int)Tn, a.kpad,
-                               reinterpret_cast<uint32_t*>(a.p), a.ld, a.plane, fra ? h.RApart : nullptr);
+                               reinterpret_cast<uint32_t*>(a.p), a.nrb, a.plane, fra ? h.RApart : nullptr);
           };
           if (Tn <= 16) go(k_rdelta_split<16>); else go(k_rdelta_split<RDS_TN>);
           continue;

@@ -31,10 +31,10 @@ inline unsigned grid_for(int64_t n) {
 
 // ---- split passes ----------------------------------------------------------
 
-// planes of dst (rows x kpad, row stride ld, plane stride pl): the split of
-// src[r * lds + k] for k < K, zero for K <= k < kpad; one thread per pair of k.
+// planes of dst (rows x kpad in the ps_off layout with nrb row blocks, plane stride pl): the
+// split of src[r * lds + k] for k < K, zero for K <= k < kpad; one thread per pair of k.
 __global__ void k_split_rows(const float* __restrict__ src, int64_t rows, int64_t K, int64_t lds, int64_t kpad,
-                             uint32_t* __restrict__ dst, int64_t ld, int64_t pl) {
+                             uint32_t* __restrict__ dst, int64_t nrb, int64_t pl) {
   const SplitC sc = split_consts();
   const int64_t hp = kpad / 2;
   GRID_STRIDE(e, rows * hp) {
@@ -43,19 +43,19 @@ __global__ void k_split_rows(const float* __restrict__ src, int64_t rows, int64_
     const float x1 = k + 1 < K ? src[r * lds + k + 1] : 0.f;
     bf2_t h, m, l;
     split3x2(f2_t{x0, x1}, h, m, l, sc);
-    const int64_t o = (r * ld + k) / 2;
+    const int64_t o = ps_off(r, k, nrb) / 2;
     dst[o] = __builtin_bit_cast(uint32_t, h);
     dst[o + pl / 2] = __builtin_bit_cast(uint32_t, m);
     dst[o + pl] = __builtin_bit_cast(uint32_t, l);
   }
 }
 
-// planes of dst (cols x rpad, row stride ld, plane stride pl): the split of the transpose,
-// dst[c][r] = split(src[r * lds + c]) for r < R, zero for R <= r < rpad; 64 x 64 tiles
-// through LDS (reads coalesced along c, writes along r).
+// planes of dst (cols x rpad in the ps_off layout, plane stride pl): the split of the
+// transpose, dst[c][r] = split(src[r * lds + c]) for r < R, zero for R <= r < rpad; 64 x 64
+// tiles through LDS (reads coalesced along c, writes along r).
 __global__ __launch_bounds__(256) void k_split_transpose(const float* __restrict__ src, int64_t R, int64_t Cc,
                                                          int64_t lds, int64_t rpad, uint32_t* __restrict__ dst,
-                                                         int64_t ld, int64_t pl) {
+                                                         int64_t nrb, int64_t pl) {
   __shared__ float tile[64][65];
   const int64_t tr = (rpad + 63) / 64;
   const int64_t r0 = (int64_t)(blockIdx.x % tr) * 64, c0 = (int64_t)(blockIdx.x / tr) * 64;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_split_transpose(const float* __restrict
     if (c >= Cc || r >= rpad) continue;
     bf2_t h, m, l;
     split3x2(f2_t{tile[2 * p][cc], tile[2 * p + 1][cc]}, h, m, l, sc);
-    const int64_t o = (c * ld + r) / 2;
+    const int64_t o = ps_off(c, r, nrb) / 2;
     dst[o] = __builtin_bit_cast(uint32_t, h);
     dst[o + pl / 2] = __builtin_bit_cast(uint32_t, m);
     dst[o + pl] = __builtin_bit_cast(uint32_t, l);
@@ -102,16 +102,13 @@ struct PsTile {
   static constexpr int GA = BM / 16 / W, GB = PN / 16 / W;  // 16-row copy groups per wavefront
 };
 
-// segment swizzle of a row: the 16 lanes of an operand read (16 consecutive rows, one
-// segment) land on distinct bank groups
-__device__ __forceinline__ int ps_swz(int row) { return ((row >> 1) ^ ((row >> 3) & 1)) & 3; }
 
 extern __shared__ __attribute__((aligned(16))) unsigned char ps_smem[];
 
 struct PsArgs {
-  const __bf16* A;  // part x of A(m, k) at A[x * pa + m * lda + k]
-  const __bf16* B;  // part x of B(n, k) at B[x * pb + n * ldb + k]
-  int64_t lda, ldb, pa, pb;
+  const __bf16* A;  // part x of A(m, k) at A[x * pa + ps_off(m, k, nrba)]
+  const __bf16* B;  // part x of B(n, k) at B[x * pb + ps_off(n, k, nrbb)]
+  int64_t nrba, nrbb, pa, pb;
   int64_t M, N, K;  // K a multiple of 32 (parts zero past the true contraction length)
   float* C;
   int64_t scm, scn;
@@ -129,44 +126,34 @@ __device__ __forceinline__ void gemm_ps_tile(const PsArgs& g, int64_t tiles_n, i
   const int wr = wave >> 1, wc = wave & 1;
   const int row16 = lane & 15, q = lane >> 4;
 
-  // copies: 16 rows x 64 bytes of one part per instruction; wavefront w moves A row
-  // groups GA w .. GA w + GA - 1 and B row groups GB w .. of every part.  Lane: row
-  // 16 g + lane / 4, LDS segment lane % 4, which holds the row's global segment
-  // (lane % 4) ^ swz(row).  Rows past M (N) read the last row (outputs discarded).
-  int voffA[TL::GA], voffB[TL::GB];
+  // copies: one 1 KB block (16 rows x 32 k of one part, in MFMA operand order) per
+  // instruction, 16 bytes a lane; wavefront w moves A row blocks GA w .. GA w + GA - 1 and
+  // B row blocks GB w .. of every part.  Blocks past M (N) read the last block (outputs
+  // discarded).
+  int64_t rbA[TL::GA], rbB[TL::GB];
 #pragma unroll
-  for (int ga = 0; ga < TL::GA; ++ga) {
-    const int row = 16 * (TL::GA * wave + ga) + lane / PSEG;
-    const int seg = (lane % PSEG) ^ ps_swz(row);
-    const int64_t ra = std::min<int64_t>(m0 + row, g.M - 1) - m0;
-    voffA[ga] = (int)((ra * g.lda + seg * 8) * 2);
-  }
+  for (int ga = 0; ga < TL::GA; ++ga) rbA[ga] = std::min<int64_t>(m0 / 16 + TL::GA * wave + ga, g.nrba - 1);
 #pragma unroll
-  for (int gb = 0; gb < TL::GB; ++gb) {
-    const int row = 16 * (TL::GB * wave + gb) + lane / PSEG;
-    const int seg = (lane % PSEG) ^ ps_swz(row);
-    const int64_t rb = std::min<int64_t>(n0 + row, g.N - 1) - n0;
-    voffB[gb] = (int)((rb * g.ldb + seg * 8) * 2);
-  }
-  auto issue = [&](int st, int64_t k0) {
+  for (int gb = 0; gb < TL::GB; ++gb) rbB[gb] = std::min<int64_t>(n0 / 16 + TL::GB * wave + gb, g.nrbb - 1);
+  auto issue = [&](int st, int64_t kc) {
     unsigned char* D = ps_smem + st * TL::STAGE;
 #pragma unroll
     for (int x = 0; x < 3; ++x) {
       const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<__bf16*>(g.A + x * g.pa + m0 * g.lda + k0), (short)0, 0x7ffffff0, 0x00020000);
+          const_cast<__bf16*>(g.A + x * g.pa + kc * g.nrba * 512), (short)0, 0x7ffffff0, 0x00020000);
       const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<__bf16*>(g.B + x * g.pb + n0 * g.ldb + k0), (short)0, 0x7ffffff0, 0x00020000);
+          const_cast<__bf16*>(g.B + x * g.pb + kc * g.nrbb * 512), (short)0, 0x7ffffff0, 0x00020000);
 #pragma unroll
       for (int ga = 0; ga < TL::GA; ++ga)
         __builtin_amdgcn_raw_ptr_buffer_load_lds(
             ra, (__attribute__((address_space(3))) void*)(D + x * TL::A_PART + (TL::GA * wave + ga) * 1024), 16,
-            voffA[ga], 0, 0, 0);
+            (int)(rbA[ga] * 1024 + 16 * lane), 0, 0, 0);
 #pragma unroll
       for (int gb = 0; gb < TL::GB; ++gb)
         __builtin_amdgcn_raw_ptr_buffer_load_lds(
             rb,
             (__attribute__((address_space(3))) void*)(D + 3 * TL::A_PART + x * TL::B_PART + (TL::GB * wave + gb) * 1024),
-            16, voffB[gb], 0, 0, 0);
+            16, (int)(rbB[gb] * 1024 + 16 * lane), 0, 0, 0);
     }
   };
 
@@ -176,30 +163,30 @@ __device__ __forceinline__ void gemm_ps_tile(const PsArgs& g, int64_t tiles_n, i
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-  const int soff = ((q ^ ps_swz(row16)) * 16);  // byte offset of this lane's segment in a row
   const int64_t nk = g.K / PKC;
   issue(0, 0);
   for (int64_t kc = 0; kc < nk; ++kc) {
     // this chunk's copies have landed and every wavefront is done reading the stage that
     // is refilled next
     asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    if (kc + 1 < nk) issue((int)((kc + 1) % PSTAGES), (kc + 1) * PKC);
+    if (kc + 1 < nk) issue((int)((kc + 1) % PSTAGES), kc + 1);
     const unsigned char* S = ps_smem + (kc % PSTAGES) * TL::STAGE;
     const unsigned char* SB = S + 3 * TL::A_PART;
+    const int lo = 16 * lane;  // this lane's 16 bytes of a block
     bf8_t bh[4], bm[4], bl[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int r = wc * 64 + j * 16 + row16;
-      bh[j] = *reinterpret_cast<const bf8_t*>(SB + 0 * TL::B_PART + r * 64 + soff);
-      bm[j] = *reinterpret_cast<const bf8_t*>(SB + 1 * TL::B_PART + r * 64 + soff);
-      bl[j] = *reinterpret_cast<const bf8_t*>(SB + 2 * TL::B_PART + r * 64 + soff);
+      const int blk = wc * 4 + j;
+      bh[j] = *reinterpret_cast<const bf8_t*>(SB + 0 * TL::B_PART + blk * 1024 + lo);
+      bm[j] = *reinterpret_cast<const bf8_t*>(SB + 1 * TL::B_PART + blk * 1024 + lo);
+      bl[j] = *reinterpret_cast<const bf8_t*>(SB + 2 * TL::B_PART + blk * 1024 + lo);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int r = wr * 64 + i * 16 + row16;
-      const bf8_t ah = *reinterpret_cast<const bf8_t*>(S + 0 * TL::A_PART + r * 64 + soff);
-      const bf8_t am = *reinterpret_cast<const bf8_t*>(S + 1 * TL::A_PART + r * 64 + soff);
-      const bf8_t al = *reinterpret_cast<const bf8_t*>(S + 2 * TL::A_PART + r * 64 + soff);
+      const int blk = wr * 4 + i;
+      const bf8_t ah = *reinterpret_cast<const bf8_t*>(S + 0 * TL::A_PART + blk * 1024 + lo);
+      const bf8_t am = *reinterpret_cast<const bf8_t*>(S + 1 * TL::A_PART + blk * 1024 + lo);
+      const bf8_t al = *reinterpret_cast<const bf8_t*>(S + 2 * TL::A_PART + blk * 1024 + lo);
 #pragma unroll
       for (int pr = 0; pr < 6; ++pr)
 #pragma unroll
@@ -247,8 +234,8 @@ void launch_ps(Exec& ex, const PsArgs& g) {
 
 SplitMat take_split(Arena& ar, int64_t rows, int64_t kpad) {
   SplitMat s;
-  s.ld = kpad;
-  s.plane = rows * kpad;
+  s.nrb = (rows + 15) / 16;
+  s.plane = s.nrb * 16 * kpad;
   s.kpad = kpad;
   s.p = ar.take<__bf16>(3 * s.plane);
   return s;
@@ -257,14 +244,14 @@ SplitMat take_split(Arena& ar, int64_t rows, int64_t kpad) {
 void split_rows(Exec& ex, const float* src, int64_t rows, int64_t K, int64_t lds, SplitMat dst) {
   if (rows <= 0 || !launch_ok(ex)) return;
   hipLaunchKernelGGL(k_split_rows, dim3(grid_for(rows * (dst.kpad / 2))), dim3(TPB), 0, ex.stream, src, rows, K, lds,
-                     dst.kpad, reinterpret_cast<uint32_t*>(dst.p), dst.ld, dst.plane);
+                     dst.kpad, reinterpret_cast<uint32_t*>(dst.p), dst.nrb, dst.plane);
 }
 
 void split_transpose(Exec& ex, const float* src, int64_t R, int64_t Cc, int64_t lds, SplitMat dst) {
   if (Cc <= 0 || !launch_ok(ex)) return;
   const int64_t blocks = ((dst.kpad + 63) / 64) * ((Cc + 63) / 64);
   hipLaunchKernelGGL(k_split_transpose, dim3((unsigned)blocks), dim3(256), 0, ex.stream, src, R, Cc, lds, dst.kpad,
-                     reinterpret_cast<uint32_t*>(dst.p), dst.ld, dst.plane);
+                     reinterpret_cast<uint32_t*>(dst.p), dst.nrb, dst.plane);
 }
 
 void gemm_presplit(Exec& ex, int64_t M, int64_t N, const SplitMat& A, const SplitMat& B, float alpha, float beta,
@@ -272,8 +259,8 @@ void gemm_presplit(Exec& ex, int64_t M, int64_t N, const SplitMat& A, const Spli
   if (M <= 0 || N <= 0) return;
   if (!launch_ok(ex)) return;
   PsArgs g;
-  g.A = A.p; g.lda = A.ld; g.pa = A.plane;
-  g.B = B.p; g.ldb = B.ld; g.pb = B.plane;
+  g.A = A.p; g.nrba = A.nrb; g.pa = A.plane;
+  g.B = B.p; g.nrbb = B.nrb; g.pb = B.plane;
   g.M = M; g.N = N; g.K = A.kpad;
   g.C = C; g.scm = ldc; g.scn = 1;
   g.alpha = alpha; g.beta = beta;

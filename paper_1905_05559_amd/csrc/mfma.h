@@ -83,6 +83,15 @@ __device__ __forceinline__ void split3x8(const float (&v)[8], bf8_t& h, bf8_t& m
   l = bf8_t{ll[0][0], ll[0][1], ll[1][0], ll[1][1], ll[2][0], ll[2][1], ll[3][0], ll[3][1]};
 }
 
+// Element (row, k) of one BF16 plane of a pre-split operand (the split-product GEMM on
+// pre-split operands): blocks of 16 rows x 32 k (1 KB), block (row / 16, k / 32) at
+// ((k / 32) nrb + row / 16) 512, nrb = row blocks; inside a block, lane l = 16 (k % 32 / 8) +
+// row % 16 holds k % 8 = 0..7 at 8 l .. 8 l + 7, the operand order of
+// v_mfma_f32_16x16x32_bf16, so that a block is copied and read 16 bytes a lane, in order.
+__device__ __forceinline__ int64_t ps_off(int64_t row, int64_t k, int64_t nrb) {
+  return (((k >> 5) * nrb + (row >> 4)) << 9) + ((((k & 31) >> 3) * 16 + (row & 15)) << 3) + (k & 7);
+}
+
 // Map a dispatch-order workgroup id to a logical tile id so that each of the 8
 // XCDs (which receive workgroups round-robin) works on one contiguous range of
 // logical tiles; neighbouring tiles then share operand panels in that XCD's L2.
