@@ -120,7 +120,21 @@ struct KrgArgs {
   // the FP32 columns in every wavefront; nullptr: split in the tile.
   const uint32_t* bparts = nullptr;
   int32_t bp_nblk = 0;
+  // Per column tile (128 columns) the examples with a nonzero weight for some pair of the
+  // tile, in increasing order: klist[t * ldl + i] for i < kcnt[t], padded with example 0
+  // to whole chunks of 32 (ldl a multiple of 32, at least N rounded up).  With split products
+  // on a symmetric pair-weighted contraction the tile then sums over those examples only
+  // (the others contribute exact zeros); nullptr: every example.
+  const int32_t* klist = nullptr;
+  const int64_t* kcnt = nullptr;
+  int64_t ldl = 0;
 };
+// The example lists above for a pair-weighted contraction, from its weights: flags (column
+// units x N bytes) marks the examples of each column unit with a nonzero weight for some row
+// unit, then each column tile gathers the examples flagged for any of its units.
+int64_t krg_list_tiles(const KrgArgs<float, float>& a);
+void krg_build_lists(Exec& ex, const KrgArgs<float, float>& a, uint8_t* flags, int32_t* lists, int64_t* cnt,
+                     int64_t ldl);
 // Pair-diagonal contraction (KRG_PAIR_DIAG, FP32) as one product instead of tiles:
 // out[row(u, s)][col(u, b)] (+)= scale * sum_n w[u][n] r.src[n][s] c.src[n][b] for units
 // u < min(r.n_units, c.n_units), through Y[n][u len_r + s] = w[u][n] r.src[n][s] (N x U len_r),

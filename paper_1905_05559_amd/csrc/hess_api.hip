@@ -472,6 +472,11 @@ struct HOps {
   T* D1T = nullptr;               // sigma'^(m) transposed, operand precision
   uint32_t* bparts = nullptr;     // split products: column source of layer m split in BF16 parts
   float* pdws = nullptr;          // pair-diagonal blocks as one product (FP32 operands)
+  // split products on a ReLU column layer: per column tile the examples with a nonzero weight
+  uint8_t* lflags = nullptr;
+  int32_t* lists = nullptr;
+  int64_t* lcnt = nullptr;
+  int64_t ldl = 0;
 };
 
 int64_t pairdiag_block_floats(const Model& m, int64_t N, int mm) {
@@ -484,6 +489,14 @@ static bool presplit_layer(const Model& m, int mm) {
   const int64_t pad = rup(m.T[mm - 2] + 1, 16);
   return pad % 32 == 0 && pad >= 128;
 }
+
+// Column layers whose within-layer block sums, under split products, over per-tile example
+// lists: ReLU hidden layers (an inactive unit has exact-zero weights) of at least 128 padded
+// slots per unit (two units per tile side).
+static bool list_layer(const Model& m, int mm) {
+  return mm < m.L && m.act[mm - 2] == HESS_RELU && rup(m.T[mm - 2] + 1, 16) >= 128;
+}
+static int64_t list_tiles(const Model& m, int mm) { return (m.T[mm - 1] * rup(m.T[mm - 2] + 1, 16) + 127) / 128; }
 
 // Bytes per example of the factor region of hess_exact (max over column layers): the FP64
 // factors, their operand-precision copies and sigma' of the column layer, the pre-split
@@ -509,6 +522,10 @@ static int64_t factor_bytes_per_example(const Model& m, bool same_type, bool spl
     for (int mm = 2; mm <= L; ++mm) {
       if (split && presplit_layer(m, mm)) extra = std::max(extra, 6 * rup(m.T[mm - 2] + 1, 32));
     }
+    int64_t lb = 0;  // example lists and flags
+    for (int mm = 2; mm <= L; ++mm)
+      if (split && list_layer(m, mm)) lb = std::max(lb, 4 * list_tiles(m, mm) + m.T[mm - 1]);
+    extra += lb;
     int64_t pd = 0;
     for (int mm = 2; mm <= L - 1; ++mm) pd = std::max(pd, 4 * m.T[mm - 1] * m.T[mm]);
     extra += pd;
@@ -564,6 +581,19 @@ size_t plan_exact(const Model& m, int64_t N, int64_t Nc, void* ws, Prep& p, HOps
     for (int mm = 2; mm <= L; ++mm)
       if (presplit_layer(m, mm)) dw = std::max(dw, bsplit_dwords(Nc, (int32_t)rup(m.T[mm - 2] + 1, 16)));
     if (dw > 0) ops.bparts = ar.take<uint32_t>((size_t)dw);
+    int64_t nl = 0, nf = 0, nt = 0;
+    for (int mm = 2; mm <= L; ++mm) {
+      if (!list_layer(m, mm)) continue;
+      nt = std::max(nt, list_tiles(m, mm));
+      nl = std::max(nl, list_tiles(m, mm) * rup(Nc, 32));
+      nf = std::max(nf, m.T[mm - 1] * Nc);
+    }
+    if (nl > 0) {
+      ops.ldl = rup(Nc, 32);
+      ops.lists = ar.take<int32_t>((size_t)nl);
+      ops.lcnt = ar.take<int64_t>((size_t)nt);
+      ops.lflags = ar.take<uint8_t>((size_t)nf);
+    }
   }
   if (!same_type) {
     int64_t pf = 0;
@@ -681,6 +711,14 @@ void run_exact(Exec& ex, const Model& m, int64_t N, int64_t Nc, Prep& p, HOps<T>
         a.mirror = 1;
         a.scale = 1.0 / (double)N;
         a.N = nc;
+        if constexpr (sizeof(T) == 4) {
+          if (ex.split && l == mm && ops.lists && list_layer(m, mm)) {
+            krg_build_lists(ex, a, ops.lflags, ops.lists, ops.lcnt, ops.ldl);
+            a.klist = ops.lists;
+            a.kcnt = ops.lcnt;
+            a.ldl = ops.ldl;
+          }
+        }
         krg<T, TOut>(ex, a);
       }
       // term 2 (l > m): delta^(l)_{i'} abar^(m-1)_j weighted by K^(l-1,m)[j', i]

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "mfma.h"
 
@@ -321,11 +322,14 @@ constexpr int DLD = 132;
 // as BF16 parts in MFMA operand order; A rows are unpadded (128-bit reads of 16 lanes
 // cover 256 contiguous bytes) and the pair weights go to registers, so that two
 // workgroups (2 x 80 KB) share a CU
-template <int KC_, int NST_, bool SPLIT_ = false, bool BPS_ = false>
+// LIST: the examples of a column tile come from its list (a.klist): rows of both sources
+// and the pair weights are gathered by example index
+template <int KC_, int NST_, bool SPLIT_ = false, bool BPS_ = false, bool LIST_ = false>
 struct DmaCfg {
   static constexpr int KC = KC_, NST = NST_;
-  static constexpr bool SPLIT = SPLIT_, BPS = BPS_;
+  static constexpr bool SPLIT = SPLIT_, BPS = BPS_, LIST = LIST_;
   static_assert(!BPS || (SPLIT && KC == 32), "pre-split columns need split products on chunks of 32");
+  static_assert(!LIST || (SPLIT && !BPS && KC == 32 && NST == 2), "example lists: split products in the tile");
 };
 using DmaDefault = DmaCfg<16, 2>;  // measured: (16, 2) 131, (16, 3) 129, (32, 2) 126 TFLOP/s
 
@@ -397,6 +401,13 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
   const int ur_hi = (int)min((int64_t)a.r.n_units - 1, (r0 + BM - 1) / a.r.pad);
   const int uc_hi = (int)min((int64_t)a.c.n_units - 1, (c0 + BN - 1) / a.c.pad);
   if (WMODE == KRG_PAIR_DIAG && (ur_hi < uc_lo || uc_hi < ur_lo)) return;
+  // examples summed by this tile: all N, or (LIST) the column tile's list
+  int64_t NE = a.N;
+  const int32_t* klist = nullptr;
+  if constexpr (C::LIST) {
+    klist = a.klist + tc * a.ldl;
+    NE = a.kcnt[tc];
+  }
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -410,8 +421,8 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
     const int k = (DKC / 4) * wave + (m >> 1);
     const int64_t r = r0 + (m & 1) * 64 + lane, c = c0 + (m & 1) * 64 + lane;
     const int sr = (int)mn64(r % a.r.pad, a.r.len - 1), sc = (int)mn64(c % a.c.pad, a.c.len - 1);
-    voffA[m] = (int)((k * a.r.ld + sr) * 4);
-    voffB[m] = (int)((k * a.c.ld + sc) * 4);
+    voffA[m] = (int)(((C::LIST ? 0 : k) * a.r.ld + sr) * 4);  // LIST: the example rides in the scalar offset
+    voffB[m] = (int)(((C::LIST ? 0 : k) * a.c.ld + sc) * 4);
   }
   // BPS: byte offsets of the tile's four 32-column groups (column half h, group g) in a
   // pre-split chunk.  With BPS, block j of a wavefront holds its columns 16 j .. 16 j + 15,
@@ -437,7 +448,7 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
     wlive[x] = g < SM::WI && e < SM::WN1;
     int off = 0;
     if (WMODE == KRG_PAIR_FULL) {
-      const int p = e / DKC, k = e % DKC;
+      const int p = e / DKC, k = C::LIST ? 0 : e % DKC;  // LIST: example e % DKC added at the copy
       const int ur = min(ur_lo + p / MAXU, a.r.n_units - 1), uc = min(uc_lo + p % MAXU, a.c.n_units - 1);
       off = (int)((((int64_t)(ur - ur_lo) * a.c.n_units + (uc - uc_lo)) * a.ldw + k) * 4);
     } else if (WMODE == KRG_PAIR_DIAG) {
@@ -463,9 +474,34 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
   if (WMODE == KRG_PAIR_DIAG) wtot = ((int64_t)min(a.r.n_units, a.c.n_units) - 1) * a.ldw + a.N;
 
   // ---- one chunk's copies into stage st ----
+  // LIST: example indices of the chunk being copied, lane l holding entry l % 32
+  int ixv = 0;
   auto issue = [&](int st, int64_t n0) {
-    const int kv = (int)mn64(DKC, a.N - n0);
     float* S = smem + st * SM::STAGE;
+    if constexpr (C::LIST) {
+      // copy row k of the chunk is example klist[n0 + k]: its row offset in the scalar operand
+      // (the buffers span all N rows, every index is below N), the slot in the vector offset;
+      // weight lane e takes example e % 32 of the chunk
+      static_assert(WMODE == KRG_PAIR_FULL, "example lists are built for pair weights");
+      const __amdgpu_buffer_rsrc_t ga = rsrc_of(a.r.src, a.N * a.r.ld), gb = rsrc_of(a.c.src, a.N * a.c.ld);
+#pragma unroll
+      for (int m = 0; m < KH; ++m) {
+        const int k = (DKC / 4) * wave + (m >> 1);
+        const int ex = __builtin_amdgcn_readlane(ixv, k);
+        copy_lds_s(ga, S + k * SM::ALD + (m & 1) * 64, voffA[m], (int)((int64_t)ex * a.r.ld * 4));
+        copy_lds_s(gb, S + SM::AB + k * DLD + (m & 1) * 64, voffB[m], (int)((int64_t)ex * a.c.ld * 4));
+      }
+      const int64_t base = ((int64_t)ur_lo * a.c.n_units + uc_lo) * a.ldw;
+      const __amdgpu_buffer_rsrc_t rw = rsrc_of(a.wts + base, wtot - base);
+      float* W = S + SM::WOFF;
+#pragma unroll
+      for (int x = 0; x < SM::WPW; ++x) {
+        const int g = wave + 4 * x;
+        if (g < SM::WI && wlive[x]) copy_lds(rw, W + g * 64, voffW[x] + 4 * ixv);
+      }
+      return;
+    }
+    const int kv = (int)mn64(DKC, a.N - n0);
     const __amdgpu_buffer_rsrc_t ra = rsrc_of(a.r.src + n0 * a.r.ld, (int64_t)kv * a.r.ld);
     const __amdgpu_buffer_rsrc_t rb = rsrc_of(a.c.src + n0 * a.c.ld, (int64_t)kv * a.c.ld);
     if constexpr (C::BPS) {
@@ -558,7 +594,7 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
 #pragma unroll
   for (int i = 0; i < 4; ++i) ur_blk[i] = (int)((r0 + wr * 64 + 16 * i) / a.r.pad) - ur_lo;
 
-  const int64_t nk = (a.N + DKC - 1) / DKC;
+  const int64_t nk = (NE + DKC - 1) / DKC;
   // BPS: this lane's pair weights of examples n0 + 8 q .. n0 + 8 q + 7 for its row unit and
   // column unit u (relative), read straight into registers through one wavefront-uniform
   // buffer that starts at the tile's first unit pair (the lane's pair is in the offset, as
@@ -587,6 +623,11 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
 #pragma unroll
       for (int ps = 0; ps < NPB; ++ps) wload(0, ubase + ps, wnxt[ps]);
     }
+    int ixn = 0;  // LIST: indices of the next chunk to copy, loaded a chunk ahead
+    if constexpr (C::LIST) {
+      if (nk > 0) ixv = klist[lane & 31];
+      if (nk > 1) ixn = klist[DKC + (lane & 31)];
+    }
 #pragma unroll
     for (int c = 0; c < DST - 1; ++c)
       if (c < nk) issue(c, (int64_t)c * DKC);
@@ -596,7 +637,15 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
       // every wavefront's copies of this chunk have landed and its reads of the stage
       // about to be refilled are complete
       asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-      if (kc + DST - 1 < nk) issue((int)((kc + DST - 1) % DST), (kc + DST - 1) * DKC);
+      if constexpr (C::LIST) {
+        if (kc + 1 < nk) {
+          ixv = ixn;
+          issue((int)((kc + 1) % DST), (kc + 1) * DKC);
+          if (kc + 2 < nk) ixn = klist[(kc + 2) * DKC + (lane & 31)];
+        }
+      } else if (kc + DST - 1 < nk) {
+        issue((int)((kc + DST - 1) % DST), (kc + DST - 1) * DKC);
+      }
       if constexpr (C::BPS) {  // this chunk's weights landed with its copies; fetch the next
 #pragma unroll
         for (int ps = 0; ps < NPB; ++ps)
@@ -611,7 +660,7 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
       const float* As = smem + st * SM::STAGE;
       const float* Bs = As + SM::AB;
       const float* W = As + SM::WOFF;
-      const int kv = (int)mn64(DKC, a.N - kc * DKC);
+      const int kv = (int)mn64(DKC, NE - kc * DKC);
       if constexpr (C::BPS) {
         // The columns arrive split: 12 fragment reads (lane = 16 q + row16 holds examples
         // 8 q .. 8 q + 7 of column 16 j + row16).  The rows are weighted and split here,
@@ -1006,6 +1055,88 @@ void launch_cfg(Exec& ex, const KrgArgs<T, TOut>& a, dim3 grid, int64_t tc, int6
 // variant: 0 = default for the precision; register-staged tile 1 = (KC 16, 1 stage), 2 = (16, 2),
 // 3 = (32, 1), 4 = (32, 2); FP32 LDS-staged tile 5 = (32 examples, 2 stages), 6 = (16, 3);
 // split products 7 = columns split in the tile, 8 = pre-split columns (needs a.bparts)
+// ---------------------------------------------------------------------------
+// Example lists of a pair-weighted contraction.  flags[u][n] = 1 when some row unit has a
+// nonzero weight with column unit u at example n; a column tile lists, in increasing order,
+// the examples flagged for any unit its 128 columns touch.  (With ReLU units the weights of
+// an inactive column unit are exact zeros, about half of them.)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_list_flags(const float* __restrict__ w, int64_t ldw, int32_t nr,
+                                                    int32_t nu, int64_t N, uint8_t* __restrict__ flags) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int u = blockIdx.y;
+  if (n >= N) return;
+  bool f = false;
+  for (int r = 0; r < nr; ++r) f |= w[((int64_t)r * nu + u) * ldw + n] != 0.f;
+  flags[(int64_t)u * N + n] = f ? 1 : 0;
+}
+
+// one workgroup per column tile: ordered compaction of the flagged examples (a wavefront
+// ballot for positions within 64 examples, the four wavefronts' counts through LDS), then
+// example 0 up to the next multiple of 32
+__global__ __launch_bounds__(256) void k_list_build(const uint8_t* __restrict__ flags, int64_t N, int32_t pad,
+                                                    int32_t nu, int64_t ldl, int32_t* __restrict__ lists,
+                                                    int64_t* __restrict__ cnt) {
+  __shared__ int wsum[4];
+  const int64_t t = blockIdx.x;
+  const int u0 = (int)(t * BN / pad), u1 = (int)min((int64_t)nu - 1, (t * BN + BN - 1) / pad);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t* L = lists + t * ldl;
+  int64_t base = 0;
+  for (int64_t n0 = 0; n0 < N; n0 += 256) {
+    const int64_t n = n0 + threadIdx.x;
+    const bool f = n < N && (flags[(int64_t)u0 * N + n] | flags[(int64_t)u1 * N + n]);
+    const unsigned long long b = __ballot(f);
+    const int before = __popcll(b & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wave] = __popcll(b);
+    __syncthreads();
+    int off = 0;
+    for (int x = 0; x < wave; ++x) off += wsum[x];
+    const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (f) L[base + off + before] = (int32_t)n;
+    base += tot;
+    __syncthreads();
+  }
+  const int64_t end = (base + 31) / 32 * 32;
+  for (int64_t i = base + threadIdx.x; i < end; i += 256) L[i] = 0;
+  if (threadIdx.x == 0) cnt[t] = base;
+}
+
+int64_t krg_list_tiles(const KrgArgs<float, float>& a) { return ((int64_t)a.c.n_units * a.c.pad + BN - 1) / BN; }
+
+void krg_build_lists(Exec& ex, const KrgArgs<float, float>& a, uint8_t* flags, int32_t* lists, int64_t* cnt,
+                     int64_t ldl) {
+  const int64_t tc = krg_list_tiles(a);
+  if (tc <= 0 || a.N <= 0 || !launch_ok(ex)) return;
+  hipLaunchKernelGGL(k_list_flags, dim3((unsigned)((a.N + 255) / 256), (unsigned)a.c.n_units), dim3(256), 0,
+                     ex.stream, a.wts, a.ldw, a.r.n_units, a.c.n_units, a.N, flags);
+  hipLaunchKernelGGL(k_list_build, dim3((unsigned)tc), dim3(256), 0, ex.stream, flags, a.N, a.c.pad, a.c.n_units,
+                     ldl, lists, cnt);
+}
+
+// Share of the full example sum that the listed tiles compute: per column tile, its count
+// over N weighted by the tile's entries on or below the diagonal (valid slots only).  Reads
+// the counts back (the profile's flop count only).
+double krg_list_share(Exec& ex, const KrgArgs<float, float>& a) {
+  const int64_t tcn = krg_list_tiles(a);
+  std::vector<int64_t> cnt((size_t)tcn);
+  if (hipMemcpyAsync(cnt.data(), a.kcnt, tcn * sizeof(int64_t), hipMemcpyDeviceToHost, ex.stream) != hipSuccess ||
+      hipStreamSynchronize(ex.stream) != hipSuccess)
+    return 1.0;
+  const int64_t cols = (int64_t)a.c.n_units * a.c.pad;
+  // valid[i] for padded index i; entries of column c = valid rows r >= c
+  std::vector<int64_t> above((size_t)cols + 1, 0);
+  for (int64_t i = cols - 1; i >= 0; --i) above[i] = above[i + 1] + ((i % a.c.pad) < a.c.len ? 1 : 0);
+  double all = 0, done = 0;
+  for (int64_t c = 0; c < cols; ++c) {
+    if ((c % a.c.pad) >= a.c.len) continue;
+    const double e = (double)above[c];
+    all += e;
+    done += e * (double)cnt[c / BN] / (double)std::max<int64_t>(1, a.N);
+  }
+  return all > 0 ? done / all : 1.0;
+}
+
 template <typename T, typename TOut>
 void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
   const int64_t rows = (int64_t)a.r.n_units * a.r.pad, cols = (int64_t)a.c.n_units * a.c.pad;
@@ -1042,7 +1173,9 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
       auto go = [&](int cfg, dim3 g, int64_t ntl) {
         auto run = [&](auto c) {
           using C = decltype(c);
-          if constexpr (C::BPS) {  // only the pair-weighted form, two column units per tile
+          if constexpr (C::LIST) {  // symmetric pair-weighted form, two units per tile side
+            launch_dma_one<KRG_PAIR_FULL, true, 2, C>(ex, a, g, tc, ntl);
+          } else if constexpr (C::BPS) {  // only the pair-weighted form, two column units per tile
             if (a.symmetric) launch_dma_one<KRG_PAIR_FULL, true, 2, C>(ex, a, g, tc, ntl);
             else if (maxu == 2) launch_dma_one<KRG_PAIR_FULL, false, 2, C>(ex, a, g, tc, ntl);
             else launch_dma_one<KRG_PAIR_FULL, false, 5, C>(ex, a, g, tc, ntl);
@@ -1056,6 +1189,7 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
         else if (cfg == 2) run(DmaCfg<32, 2>());
         else if (cfg == 3) run(DmaCfg<32, 2, true>());
         else if (cfg == 4) run(DmaCfg<32, 2, true, true>());
+        else if (cfg == 5) run(DmaCfg<32, 2, true, false, true>());
         else run(DmaDefault());
       };
       int cfg = variant == 5 ? 2 : (variant == 6 ? 1 : (variant >= 7 || ex.split ? 3 : 0));
@@ -1064,7 +1198,19 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
       const bool bps = a.bparts && a.wmode == KRG_PAIR_FULL && a.c.pad >= 128 && a.c.pad % 32 == 0 &&
                        (maxu == 2 || (maxu == 5 && !a.symmetric)) && a.bp_nblk == a.c.pad / 32 &&
                        (ks == 1 || a.kslice % 32 == 0);
-      if (cfg == 3 && bps && variant != 7) cfg = 4;
+      // split products over the column tiles' example lists (their gathered row offsets and
+      // weight offsets stay below 2^31 bytes)
+      const int64_t lim = 0x7fff0000;
+      const bool lst = a.klist && a.kcnt && a.wmode == KRG_PAIR_FULL && a.symmetric && maxu == 2 && ks == 1 &&
+                       a.N * std::max(a.r.ld, a.c.ld) * 4 <= lim &&
+                       (((int64_t)a.c.n_units + 2) * a.ldw + a.N) * 4 <= lim;
+      double done = 1.0;  // share of the examples the tiles sum over (profile only)
+      if (cfg == 3 && lst && variant != 7) {
+        cfg = 5;
+        if (ex.ctx->profile) done = krg_list_share(ex, a);
+      } else if (cfg == 3 && bps && variant != 7) {
+        cfg = 4;
+      }
       if (cfg >= 3 && label.compare(0, 7, "krg_f32") == 0) label = "krg_bf16x6" + label.substr(7);
       // Probes write into the output, which the full launch then overwrites; a launch that
       // accumulates into its output keeps the default configuration.
@@ -1085,7 +1231,7 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
         static const char* const cfgs[3] = {"chunk16x2", "chunk16x3", "chunk32x2"};
         cfg = autotune_pick(ex, key, 3, cfgs, [&](int i) { go(i, gp, ntp); });
       }
-      const int tok = prof_begin(ex, label.c_str(), 2.0 * a.N * entries, src + wbytes + obytes * ks);
+      const int tok = prof_begin(ex, label.c_str(), 2.0 * a.N * entries * done, src * done + wbytes + obytes * ks);
       go(cfg, grid, nt);
       prof_end(ex, tok);
       return;
