@@ -171,6 +171,29 @@ def test_presplit_columns_exact(api, T, acts, N, seed):
     assert report("H   %s f32_split (pre-split columns)" % T, H, Href) <= TOL["f32_split"]
 
 
+@pytest.mark.parametrize("T,N,seed,dead", [
+    ([127, 24, 10], 300, 31, 12),   # 128 slots per unit: one unit per column tile
+    ([223, 12, 5], 97, 32, 4),      # 224 slots: column tiles that straddle two units
+])
+def test_relu_example_lists_with_dead_units(api, T, N, seed, dead):
+    # Split products on a ReLU column layer sum each column tile over the examples where one of
+    # its units has a nonzero weight.  The first `dead` hidden units never fire (bias -1e3), so
+    # the tiles of their columns have empty lists: those rows of H must come out exactly zero,
+    # and the rest must match the oracle.
+    print("case relu example lists, dead units T=%s N=%d dead=%d" % (T, N, dead), flush=True)
+    w = workloads.mlp_gaussian(T, ["relu"], N, seed, dtype="float32")
+    w.b[0][:dead] = -1e3
+    model, X, Y = to_dev(api, w, w.dtype)
+    om, Xo, Yo = oracle_of(w)
+    Href = mlp.hessian(om, Xo, Yo, block=256)
+    H = api.hess_exact(model, X, Y, "f32_split").double().cpu().numpy()
+    T0, T1 = T[0], T[1]
+    rows = [j * T0 + i for j in range(dead) for i in range(T0)] + [T1 * T0 + j for j in range(dead)]
+    assert not np.any(H[rows, :]) and not np.any(Href[rows, :])
+    assert np.array_equal(H, H.T)
+    assert report("H   %s f32_split (example lists, %d dead units)" % (T, dead), H, Href) <= TOL["f32_split"]
+
+
 @pytest.mark.parametrize("T,acts,N,seed", [
     ([127, 24, 10], ["relu"], 97, 13),
     ([150, 20, 5], ["tanh"], 300, 14),
