@@ -123,8 +123,8 @@ struct KrgArgs {
   // Per column tile (128 columns) the examples with a nonzero weight for some pair of the
   // tile, in increasing order: klist[t * ldl + i] for i < kcnt[t], padded with example 0
   // to whole chunks of 32 (ldl a multiple of 32, at least N rounded up).  With split products
-  // on a symmetric pair-weighted contraction the tile then sums over those examples only
-  // (the others contribute exact zeros); nullptr: every example.
+  // on a pair-weighted contraction the tile then sums over those examples only (the others
+  // contribute exact zeros); nullptr: every example.
   const int32_t* klist = nullptr;
   const int64_t* kcnt = nullptr;
   int64_t ldl = 0;

@@ -490,9 +490,9 @@ static bool presplit_layer(const Model& m, int mm) {
   return pad % 32 == 0 && pad >= 128;
 }
 
-// Column layers whose within-layer block sums, under split products, over per-tile example
-// lists: ReLU hidden layers (an inactive unit has exact-zero weights) of at least 128 padded
-// slots per unit (two units per tile side).
+// Column layers whose weighted-Gram blocks (term 1) sum, under split products, over per-tile
+// example lists: ReLU hidden layers (an inactive unit has exact-zero weights in every block of
+// its column) of at least 128 padded slots per unit (two units per column tile).
 static bool list_layer(const Model& m, int mm) {
   return mm < m.L && m.act[mm - 2] == HESS_RELU && rup(m.T[mm - 2] + 1, 16) >= 128;
 }
@@ -712,7 +712,7 @@ void run_exact(Exec& ex, const Model& m, int64_t N, int64_t Nc, Prep& p, HOps<T>
         a.scale = 1.0 / (double)N;
         a.N = nc;
         if constexpr (sizeof(T) == 4) {
-          if (ex.split && l == mm && ops.lists && list_layer(m, mm)) {
+          if (ex.split && ops.lists && list_layer(m, mm)) {
             krg_build_lists(ex, a, ops.lflags, ops.lists, ops.lcnt, ops.ldl);
             a.klist = ops.lists;
             a.kcnt = ops.lcnt;

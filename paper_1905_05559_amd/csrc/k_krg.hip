@@ -336,7 +336,10 @@ using DmaDefault = DmaCfg<16, 2>;  // measured: (16, 2) 131, (16, 3) 129, (32, 2
 template <int WMODE, int MAXU, class C = DmaDefault>
 struct DmaSmem {
   static constexpr int DKC = C::KC;
-  static constexpr int ALD = C::BPS ? 128 : DLD;  // A row stride (floats)
+  // row strides (floats) of A and B: unpadded where every read is a 128-bit read of 16 lanes
+  // on 256 contiguous bytes (pre-split columns, example lists), DLD otherwise
+  static constexpr int ALD = (C::BPS || C::LIST) ? 128 : DLD;
+  static constexpr int BLD = C::LIST ? 128 : DLD;
   static constexpr int AB = DKC * ALD;
   static constexpr int WN1 = WMODE == KRG_PAIR_FULL ? MAXU * MAXU * DKC : MAXU * DKC;  // floats per weight array
   static constexpr int NW = WMODE == KRG_RANK1 ? 2 : 1;                              // weight arrays
@@ -489,7 +492,7 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
         const int k = (DKC / 4) * wave + (m >> 1);
         const int ex = __builtin_amdgcn_readlane(ixv, k);
         copy_lds_s(ga, S + k * SM::ALD + (m & 1) * 64, voffA[m], (int)((int64_t)ex * a.r.ld * 4));
-        copy_lds_s(gb, S + SM::AB + k * DLD + (m & 1) * 64, voffB[m], (int)((int64_t)ex * a.c.ld * 4));
+        copy_lds_s(gb, S + SM::AB + k * SM::BLD + (m & 1) * 64, voffB[m], (int)((int64_t)ex * a.c.ld * 4));
       }
       const int64_t base = ((int64_t)ur_lo * a.c.n_units + uc_lo) * a.ldw;
       const __amdgpu_buffer_rsrc_t rw = rsrc_of(a.wts + base, wtot - base);
@@ -531,7 +534,7 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
     } else {
 #pragma unroll
       for (int m = 0; m < KH; ++m)
-        copy_lds(rb, S + SM::AB + ((DKC / 4) * wave + (m >> 1)) * DLD + (m & 1) * 64, voffB[m]);
+        copy_lds(rb, S + SM::AB + ((DKC / 4) * wave + (m >> 1)) * SM::BLD + (m & 1) * 64, voffB[m]);
     }
     float* W = S + SM::WOFF;
     if (C::BPS) {
@@ -717,8 +720,8 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
         for (int s = 0; s < 8; ++s) {
           const int k = 8 * q + s;
           const float ws = s < 4 ? wlo[s] : whi[s - 4];
-          const f4_t a4 = *(const f4_t*)&As[k * DLD + wr * 64 + 4 * row16] * ws;
-          const f4_t b4 = *(const f4_t*)&Bs[k * DLD + wc * 64 + 4 * row16];
+          const f4_t a4 = *(const f4_t*)&As[k * SM::ALD + wr * 64 + 4 * row16] * ws;
+          const f4_t b4 = *(const f4_t*)&Bs[k * SM::BLD + wc * 64 + 4 * row16];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             av[i][s] = a4[i];
@@ -747,8 +750,8 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
             const int k = k0 + 4 * q + s;
-            const f4_t av = *(const f4_t*)&As[k * DLD + wr * 64 + 4 * row16] * w[s];
-            const f4_t bv = *(const f4_t*)&Bs[k * DLD + wc * 64 + 4 * row16];
+            const f4_t av = *(const f4_t*)&As[k * SM::ALD + wr * 64 + 4 * row16] * w[s];
+            const f4_t bv = *(const f4_t*)&Bs[k * SM::BLD + wc * 64 + 4 * row16];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -762,10 +765,10 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
             const int k = k0 + 4 * q + s;
-            const f4_t bv = *(const f4_t*)&Bs[k * DLD + wc * 64 + 4 * row16];
+            const f4_t bv = *(const f4_t*)&Bs[k * SM::BLD + wc * 64 + 4 * row16];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const float av = As[k * DLD + wr * 64 + 16 * i + row16];
+              const float av = As[k * SM::ALD + wr * 64 + 16 * i + row16];
               const f4_t bw = bv * w[i][s];
 #pragma unroll
               for (int j = 0; j < 4; ++j)
@@ -1115,8 +1118,8 @@ void krg_build_lists(Exec& ex, const KrgArgs<float, float>& a, uint8_t* flags, i
 }
 
 // Share of the full example sum that the listed tiles compute: per column tile, its count
-// over N weighted by the tile's entries on or below the diagonal (valid slots only).  Reads
-// the counts back (the profile's flop count only).
+// over N weighted by the tile's entries (valid slots; on or below the diagonal when
+// symmetric).  Reads the counts back (the profile's flop count only).
 double krg_list_share(Exec& ex, const KrgArgs<float, float>& a) {
   const int64_t tcn = krg_list_tiles(a);
   std::vector<int64_t> cnt((size_t)tcn);
@@ -1124,13 +1127,14 @@ double krg_list_share(Exec& ex, const KrgArgs<float, float>& a) {
       hipStreamSynchronize(ex.stream) != hipSuccess)
     return 1.0;
   const int64_t cols = (int64_t)a.c.n_units * a.c.pad;
-  // valid[i] for padded index i; entries of column c = valid rows r >= c
+  // valid[i] for padded index i; entries of column c = valid rows r >= c (symmetric) or all
+  // valid rows
   std::vector<int64_t> above((size_t)cols + 1, 0);
   for (int64_t i = cols - 1; i >= 0; --i) above[i] = above[i + 1] + ((i % a.c.pad) < a.c.len ? 1 : 0);
   double all = 0, done = 0;
   for (int64_t c = 0; c < cols; ++c) {
     if ((c % a.c.pad) >= a.c.len) continue;
-    const double e = (double)above[c];
+    const double e = a.symmetric ? (double)above[c] : 1.0;
     all += e;
     done += e * (double)cnt[c / BN] / (double)std::max<int64_t>(1, a.N);
   }
@@ -1173,8 +1177,10 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
       auto go = [&](int cfg, dim3 g, int64_t ntl) {
         auto run = [&](auto c) {
           using C = decltype(c);
-          if constexpr (C::LIST) {  // symmetric pair-weighted form, two units per tile side
-            launch_dma_one<KRG_PAIR_FULL, true, 2, C>(ex, a, g, tc, ntl);
+          if constexpr (C::LIST) {  // pair-weighted form: symmetric with two units per tile side, or not
+            if (a.symmetric) launch_dma_one<KRG_PAIR_FULL, true, 2, C>(ex, a, g, tc, ntl);
+            else if (maxu == 2) launch_dma_one<KRG_PAIR_FULL, false, 2, C>(ex, a, g, tc, ntl);
+            else launch_dma_one<KRG_PAIR_FULL, false, 5, C>(ex, a, g, tc, ntl);
           } else if constexpr (C::BPS) {  // only the pair-weighted form, two column units per tile
             if (a.symmetric) launch_dma_one<KRG_PAIR_FULL, true, 2, C>(ex, a, g, tc, ntl);
             else if (maxu == 2) launch_dma_one<KRG_PAIR_FULL, false, 2, C>(ex, a, g, tc, ntl);
@@ -1201,7 +1207,8 @@ void krg_variant(Exec& ex, const KrgArgs<T, TOut>& a, int variant) {
       // split products over the column tiles' example lists (their gathered row offsets and
       // weight offsets stay below 2^31 bytes)
       const int64_t lim = 0x7fff0000;
-      const bool lst = a.klist && a.kcnt && a.wmode == KRG_PAIR_FULL && a.symmetric && maxu == 2 && ks == 1 &&
+      const bool lst = a.klist && a.kcnt && a.wmode == KRG_PAIR_FULL && ks == 1 &&
+                       (a.symmetric ? maxu == 2 : (maxu == 2 || maxu == 5)) &&
                        a.N * std::max(a.r.ld, a.c.ld) * 4 <= lim &&
                        (((int64_t)a.c.n_units + 2) * a.ldw + a.N) * 4 <= lim;
       double done = 1.0;  // share of the examples the tiles sum over (profile only)
