@@ -128,6 +128,11 @@ struct KrgArgs {
   const int32_t* klist = nullptr;
   const int64_t* kcnt = nullptr;
   int64_t ldl = 0;
+  // Symmetric contractions: per unit pair (u >= v, index u (u + 1) / 2 + v) the examples with
+  // a nonzero weight w[u][v][n], same layout (row stride ldl); a tile whose rows lie in one
+  // unit and columns in one unit sums over its pair's list instead; nullptr: column lists only.
+  const int32_t* plist = nullptr;
+  const int64_t* pcnt = nullptr;
 };
 // The example lists above for a pair-weighted contraction, from its weights: flags (column
 // units x N bytes) marks the examples of each column unit with a nonzero weight for some row
@@ -135,6 +140,8 @@ struct KrgArgs {
 int64_t krg_list_tiles(const KrgArgs<float, float>& a);
 void krg_build_lists(Exec& ex, const KrgArgs<float, float>& a, uint8_t* flags, int32_t* lists, int64_t* cnt,
                      int64_t ldl);
+// The unit-pair lists above (symmetric contraction: r and c the same units).
+void krg_build_pair_lists(Exec& ex, const KrgArgs<float, float>& a, int32_t* lists, int64_t* cnt, int64_t ldl);
 // Pair-diagonal contraction (KRG_PAIR_DIAG, FP32) as one product instead of tiles:
 // out[row(u, s)][col(u, b)] (+)= scale * sum_n w[u][n] r.src[n][s] c.src[n][b] for units
 // u < min(r.n_units, c.n_units), through Y[n][u len_r + s] = w[u][n] r.src[n][s] (N x U len_r),

@@ -477,6 +477,8 @@ struct HOps {
   int32_t* lists = nullptr;
   int64_t* lcnt = nullptr;
   int64_t ldl = 0;
+  int32_t* plists = nullptr;  // per unit pair of the within-layer block
+  int64_t* pcnt = nullptr;
 };
 
 int64_t pairdiag_block_floats(const Model& m, int64_t N, int mm) {
@@ -524,7 +526,8 @@ static int64_t factor_bytes_per_example(const Model& m, bool same_type, bool spl
     }
     int64_t lb = 0;  // example lists and flags
     for (int mm = 2; mm <= L; ++mm)
-      if (split && list_layer(m, mm)) lb = std::max(lb, 4 * list_tiles(m, mm) + m.T[mm - 1]);
+      if (split && list_layer(m, mm))
+        lb = std::max(lb, 4 * list_tiles(m, mm) + m.T[mm - 1] + 4 * m.T[mm - 1] * (m.T[mm - 1] + 1) / 2);
     extra += lb;
     int64_t pd = 0;
     for (int mm = 2; mm <= L - 1; ++mm) pd = std::max(pd, 4 * m.T[mm - 1] * m.T[mm]);
@@ -581,18 +584,21 @@ size_t plan_exact(const Model& m, int64_t N, int64_t Nc, void* ws, Prep& p, HOps
     for (int mm = 2; mm <= L; ++mm)
       if (presplit_layer(m, mm)) dw = std::max(dw, bsplit_dwords(Nc, (int32_t)rup(m.T[mm - 2] + 1, 16)));
     if (dw > 0) ops.bparts = ar.take<uint32_t>((size_t)dw);
-    int64_t nl = 0, nf = 0, nt = 0;
+    int64_t nl = 0, nf = 0, nt = 0, npr = 0;
     for (int mm = 2; mm <= L; ++mm) {
       if (!list_layer(m, mm)) continue;
       nt = std::max(nt, list_tiles(m, mm));
       nl = std::max(nl, list_tiles(m, mm) * rup(Nc, 32));
       nf = std::max(nf, m.T[mm - 1] * Nc);
+      npr = std::max(npr, m.T[mm - 1] * (m.T[mm - 1] + 1) / 2);
     }
     if (nl > 0) {
       ops.ldl = rup(Nc, 32);
       ops.lists = ar.take<int32_t>((size_t)nl);
       ops.lcnt = ar.take<int64_t>((size_t)nt);
       ops.lflags = ar.take<uint8_t>((size_t)nf);
+      ops.plists = ar.take<int32_t>((size_t)(npr * ops.ldl));
+      ops.pcnt = ar.take<int64_t>((size_t)npr);
     }
   }
   if (!same_type) {
@@ -717,6 +723,11 @@ void run_exact(Exec& ex, const Model& m, int64_t N, int64_t Nc, Prep& p, HOps<T>
             a.klist = ops.lists;
             a.kcnt = ops.lcnt;
             a.ldl = ops.ldl;
+            if (l == mm) {  // within-layer block: also the unit-pair lists
+              krg_build_pair_lists(ex, a, ops.plists, ops.pcnt, ops.ldl);
+              a.plist = ops.plists;
+              a.pcnt = ops.pcnt;
+            }
           }
         }
         krg<T, TOut>(ex, a);

@@ -408,8 +408,14 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
   int64_t NE = a.N;
   const int32_t* klist = nullptr;
   if constexpr (C::LIST) {
-    klist = a.klist + tc * a.ldl;
-    NE = a.kcnt[tc];
+    if (SYM && a.plist && ur_lo == ur_hi && uc_lo == uc_hi) {  // one unit pair: its own list
+      const int64_t pi = (int64_t)ur_lo * (ur_lo + 1) / 2 + uc_lo;
+      klist = a.plist + pi * a.ldl;
+      NE = a.pcnt[pi];
+    } else {
+      klist = a.klist + tc * a.ldl;
+      NE = a.kcnt[tc];
+    }
   }
 
   const int lane = threadIdx.x & 63;
@@ -1105,6 +1111,46 @@ __global__ __launch_bounds__(256) void k_list_build(const uint8_t* __restrict__ 
   if (threadIdx.x == 0) cnt[t] = base;
 }
 
+// one workgroup per unit pair (u >= v): ordered compaction of the examples with w[u][v][n] != 0
+__global__ __launch_bounds__(256) void k_pair_list_build(const float* __restrict__ w, int64_t ldw, int32_t nu,
+                                                         int64_t N, int64_t ldl, int32_t* __restrict__ lists,
+                                                         int64_t* __restrict__ cnt) {
+  __shared__ int wsum[4];
+  const int64_t pi = blockIdx.x;
+  int u = (int)((sqrt(8.0 * (double)pi + 1.0) - 1.0) * 0.5);
+  while ((int64_t)u * (u + 1) / 2 > pi) --u;
+  while ((int64_t)(u + 1) * (u + 2) / 2 <= pi) ++u;
+  const int v = (int)(pi - (int64_t)u * (u + 1) / 2);
+  const float* wr = w + ((int64_t)u * nu + v) * ldw;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t* L = lists + pi * ldl;
+  int64_t base = 0;
+  for (int64_t n0 = 0; n0 < N; n0 += 256) {
+    const int64_t n = n0 + threadIdx.x;
+    const bool f = n < N && wr[n] != 0.f;
+    const unsigned long long b = __ballot(f);
+    const int before = __popcll(b & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wave] = __popcll(b);
+    __syncthreads();
+    int off = 0;
+    for (int x = 0; x < wave; ++x) off += wsum[x];
+    const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (f) L[base + off + before] = (int32_t)n;
+    base += tot;
+    __syncthreads();
+  }
+  const int64_t end = (base + 31) / 32 * 32;
+  for (int64_t i = base + threadIdx.x; i < end; i += 256) L[i] = 0;
+  if (threadIdx.x == 0) cnt[pi] = base;
+}
+
+void krg_build_pair_lists(Exec& ex, const KrgArgs<float, float>& a, int32_t* lists, int64_t* cnt, int64_t ldl) {
+  const int64_t np = (int64_t)a.c.n_units * (a.c.n_units + 1) / 2;
+  if (np <= 0 || a.N <= 0 || !launch_ok(ex)) return;
+  hipLaunchKernelGGL(k_pair_list_build, dim3((unsigned)np), dim3(256), 0, ex.stream, a.wts, a.ldw, a.c.n_units, a.N,
+                     ldl, lists, cnt);
+}
+
 int64_t krg_list_tiles(const KrgArgs<float, float>& a) { return ((int64_t)a.c.n_units * a.c.pad + BN - 1) / BN; }
 
 void krg_build_lists(Exec& ex, const KrgArgs<float, float>& a, uint8_t* flags, int32_t* lists, int64_t* cnt,
@@ -1117,27 +1163,43 @@ void krg_build_lists(Exec& ex, const KrgArgs<float, float>& a, uint8_t* flags, i
                      ldl, lists, cnt);
 }
 
-// Share of the full example sum that the listed tiles compute: per column tile, its count
-// over N weighted by the tile's entries (valid slots; on or below the diagonal when
-// symmetric).  Reads the counts back (the profile's flop count only).
+// Share of the full example sum that the listed tiles compute: each tile's list length over N,
+// weighted by the tile's entries (valid slots; on or below the diagonal when symmetric).
+// Reads the counts back (the profile's flop count only).
 double krg_list_share(Exec& ex, const KrgArgs<float, float>& a) {
   const int64_t tcn = krg_list_tiles(a);
-  std::vector<int64_t> cnt((size_t)tcn);
+  const int64_t np = a.plist ? (int64_t)a.c.n_units * (a.c.n_units + 1) / 2 : 0;
+  std::vector<int64_t> cnt((size_t)tcn), pc((size_t)np);
   if (hipMemcpyAsync(cnt.data(), a.kcnt, tcn * sizeof(int64_t), hipMemcpyDeviceToHost, ex.stream) != hipSuccess ||
+      (np > 0 && hipMemcpyAsync(pc.data(), a.pcnt, np * sizeof(int64_t), hipMemcpyDeviceToHost, ex.stream) !=
+                     hipSuccess) ||
       hipStreamSynchronize(ex.stream) != hipSuccess)
     return 1.0;
-  const int64_t cols = (int64_t)a.c.n_units * a.c.pad;
-  // valid[i] for padded index i; entries of column c = valid rows r >= c (symmetric) or all
-  // valid rows
-  std::vector<int64_t> above((size_t)cols + 1, 0);
-  for (int64_t i = cols - 1; i >= 0; --i) above[i] = above[i + 1] + ((i % a.c.pad) < a.c.len ? 1 : 0);
+  // valid slots of a 128-wide tile of one side
+  auto valid = [](const KrgSide<float>& sd, int64_t t0) {
+    int64_t v = 0;
+    for (int64_t i = t0; i < std::min<int64_t>(t0 + BM, (int64_t)sd.n_units * sd.pad); ++i) v += (i % sd.pad) < sd.len;
+    return v;
+  };
+  const int64_t trn = ((int64_t)a.r.n_units * a.r.pad + BM - 1) / BM;
+  std::vector<int64_t> vr((size_t)trn), vc((size_t)tcn);
+  for (int64_t t = 0; t < trn; ++t) vr[t] = valid(a.r, t * BM);
+  for (int64_t t = 0; t < tcn; ++t) vc[t] = valid(a.c, t * BN);
+  const double N = (double)std::max<int64_t>(1, a.N);
   double all = 0, done = 0;
-  for (int64_t c = 0; c < cols; ++c) {
-    if ((c % a.c.pad) >= a.c.len) continue;
-    const double e = a.symmetric ? (double)above[c] : 1.0;
-    all += e;
-    done += e * (double)cnt[c / BN] / (double)std::max<int64_t>(1, a.N);
-  }
+  for (int64_t tr = 0; tr < trn; ++tr)
+    for (int64_t tc = 0; tc < (a.symmetric ? tr + 1 : tcn); ++tc) {
+      const double e = (a.symmetric && tr == tc) ? 0.5 * vr[tr] * (vr[tr] + 1) : (double)vr[tr] * vc[tc];
+      int64_t c = cnt[tc];
+      if (np > 0) {
+        const int64_t r0 = tr * BM, c0 = tc * BN;
+        const int64_t ul = r0 / a.r.pad, uh = std::min<int64_t>(a.r.n_units - 1, (r0 + BM - 1) / a.r.pad);
+        const int64_t vl = c0 / a.c.pad, vh = std::min<int64_t>(a.c.n_units - 1, (c0 + BN - 1) / a.c.pad);
+        if (ul == uh && vl == vh) c = pc[ul * (ul + 1) / 2 + vl];
+      }
+      all += e;
+      done += e * (double)c / N;
+    }
   return all > 0 ? done / all : 1.0;
 }
 
