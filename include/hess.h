@@ -179,7 +179,11 @@ hess_status hess_workspace_size(hess_ctx* ctx, int op, const hess_mlp* m, const 
  * floats, where that stays within 2 GiB).  With HESS_P_F32_SPLIT it also holds one
  * layer's inputs at a time split into BF16 parts, sized for the largest layer that
  * qualifies (inputs plus bias padded to a multiple of 32 and at least 128): about
- * 6 N (T_{m-1} + 1) bytes. */
+ * 6 N (T_{m-1} + 1) bytes.  For a ReLU hidden layer m of that kind it also holds, per
+ * 128-column tile and per unit pair, the list of examples with a nonzero curvature weight
+ * (about 4 N (T_m (T_{m-1} + 1) / 128 + T_m (T_m + 1) / 2) + N T_m bytes): the weighted
+ * sums of those blocks skip the examples where a unit is inactive, whose weights are
+ * exact zeros (the result changes only by the grouping of FP32 additions). */
 hess_status hess_exact(hess_ctx* ctx, const hess_mlp* m, const hess_data* d, int prec,
                        void* H, void* ws, size_t ws_bytes);
 
