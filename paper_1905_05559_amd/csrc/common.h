@@ -133,6 +133,11 @@ struct KrgArgs {
   // unit and columns in one unit sums over its pair's list instead; nullptr: column lists only.
   const int32_t* plist = nullptr;
   const int64_t* pcnt = nullptr;
+  // Symmetric contractions: per row tile the examples where one of its row units has a
+  // nonzero weight with some column unit (same layout); a tile that spans two units on a side
+  // sums over the shorter of its row tile's and column tile's lists; nullptr: column lists.
+  const int32_t* rlist = nullptr;
+  const int64_t* rcnt = nullptr;
 };
 // The example lists above for a pair-weighted contraction, from its weights: flags (column
 // units x N bytes) marks the examples of each column unit with a nonzero weight for some row
@@ -140,6 +145,9 @@ struct KrgArgs {
 int64_t krg_list_tiles(const KrgArgs<float, float>& a);
 void krg_build_lists(Exec& ex, const KrgArgs<float, float>& a, uint8_t* flags, int32_t* lists, int64_t* cnt,
                      int64_t ldl);
+// The row-tile lists above (symmetric contraction: r and c the same units), through flags.
+void krg_build_row_lists(Exec& ex, const KrgArgs<float, float>& a, uint8_t* flags, int32_t* lists, int64_t* cnt,
+                         int64_t ldl);
 // The unit-pair lists above (symmetric contraction: r and c the same units).
 void krg_build_pair_lists(Exec& ex, const KrgArgs<float, float>& a, int32_t* lists, int64_t* cnt, int64_t ldl);
 // Pair-diagonal contraction (KRG_PAIR_DIAG, FP32) as one product instead of tiles:

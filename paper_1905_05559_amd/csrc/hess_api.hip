@@ -479,6 +479,8 @@ struct HOps {
   int64_t ldl = 0;
   int32_t* plists = nullptr;  // per unit pair of the within-layer block
   int64_t* pcnt = nullptr;
+  int32_t* rlists = nullptr;  // per row tile of the within-layer block
+  int64_t* rcnt = nullptr;
 };
 
 int64_t pairdiag_block_floats(const Model& m, int64_t N, int mm) {
@@ -527,7 +529,7 @@ static int64_t factor_bytes_per_example(const Model& m, bool same_type, bool spl
     int64_t lb = 0;  // example lists and flags
     for (int mm = 2; mm <= L; ++mm)
       if (split && list_layer(m, mm))
-        lb = std::max(lb, 4 * list_tiles(m, mm) + m.T[mm - 1] + 4 * m.T[mm - 1] * (m.T[mm - 1] + 1) / 2);
+        lb = std::max(lb, 8 * list_tiles(m, mm) + m.T[mm - 1] + 4 * m.T[mm - 1] * (m.T[mm - 1] + 1) / 2);
     extra += lb;
     int64_t pd = 0;
     for (int mm = 2; mm <= L - 1; ++mm) pd = std::max(pd, 4 * m.T[mm - 1] * m.T[mm]);
@@ -599,6 +601,8 @@ size_t plan_exact(const Model& m, int64_t N, int64_t Nc, void* ws, Prep& p, HOps
       ops.lflags = ar.take<uint8_t>((size_t)nf);
       ops.plists = ar.take<int32_t>((size_t)(npr * ops.ldl));
       ops.pcnt = ar.take<int64_t>((size_t)npr);
+      ops.rlists = ar.take<int32_t>((size_t)nl);
+      ops.rcnt = ar.take<int64_t>((size_t)nt);
     }
   }
   if (!same_type) {
@@ -723,10 +727,13 @@ void run_exact(Exec& ex, const Model& m, int64_t N, int64_t Nc, Prep& p, HOps<T>
             a.klist = ops.lists;
             a.kcnt = ops.lcnt;
             a.ldl = ops.ldl;
-            if (l == mm) {  // within-layer block: also the unit-pair lists
+            if (l == mm) {  // within-layer block: also the unit-pair and row-tile lists
               krg_build_pair_lists(ex, a, ops.plists, ops.pcnt, ops.ldl);
+              krg_build_row_lists(ex, a, ops.lflags, ops.rlists, ops.rcnt, ops.ldl);
               a.plist = ops.plists;
               a.pcnt = ops.pcnt;
+              a.rlist = ops.rlists;
+              a.rcnt = ops.rcnt;
             }
           }
         }

@@ -412,6 +412,9 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
       const int64_t pi = (int64_t)ur_lo * (ur_lo + 1) / 2 + uc_lo;
       klist = a.plist + pi * a.ldl;
       NE = a.pcnt[pi];
+    } else if (SYM && a.rlist && a.rcnt[tr] < a.kcnt[tc]) {  // the row tile's list is shorter
+      klist = a.rlist + tr * a.ldl;
+      NE = a.rcnt[tr];
     } else {
       klist = a.klist + tc * a.ldl;
       NE = a.kcnt[tc];
@@ -1070,13 +1073,17 @@ void launch_cfg(Exec& ex, const KrgArgs<T, TOut>& a, dim3 grid, int64_t tc, int6
 // the examples flagged for any unit its 128 columns touch.  (With ReLU units the weights of
 // an inactive column unit are exact zeros, about half of them.)
 // ---------------------------------------------------------------------------
+// rows = 0: flags[u][n] = some row unit r has w[r][u][n] != 0 (u a column unit, nr row
+// units); rows = 1: flags[u][n] = some column unit v has w[u][v][n] != 0 (u a row unit, nr
+// column units)
 __global__ __launch_bounds__(256) void k_list_flags(const float* __restrict__ w, int64_t ldw, int32_t nr,
-                                                    int32_t nu, int64_t N, uint8_t* __restrict__ flags) {
+                                                    int32_t nu, int64_t N, int rows, uint8_t* __restrict__ flags) {
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int u = blockIdx.y;
   if (n >= N) return;
   bool f = false;
-  for (int r = 0; r < nr; ++r) f |= w[((int64_t)r * nu + u) * ldw + n] != 0.f;
+  for (int r = 0; r < nr; ++r)
+    f |= w[(rows ? (int64_t)u * nr + r : (int64_t)r * nu + u) * ldw + n] != 0.f;
   flags[(int64_t)u * N + n] = f ? 1 : 0;
 }
 
@@ -1144,6 +1151,16 @@ __global__ __launch_bounds__(256) void k_pair_list_build(const float* __restrict
   if (threadIdx.x == 0) cnt[pi] = base;
 }
 
+void krg_build_row_lists(Exec& ex, const KrgArgs<float, float>& a, uint8_t* flags, int32_t* lists, int64_t* cnt,
+                         int64_t ldl) {
+  const int64_t tr = ((int64_t)a.r.n_units * a.r.pad + BM - 1) / BM;
+  if (tr <= 0 || a.N <= 0 || !launch_ok(ex)) return;
+  hipLaunchKernelGGL(k_list_flags, dim3((unsigned)((a.N + 255) / 256), (unsigned)a.r.n_units), dim3(256), 0,
+                     ex.stream, a.wts, a.ldw, a.c.n_units, a.c.n_units, a.N, 1, flags);
+  hipLaunchKernelGGL(k_list_build, dim3((unsigned)tr), dim3(256), 0, ex.stream, flags, a.N, a.r.pad, a.r.n_units,
+                     ldl, lists, cnt);
+}
+
 void krg_build_pair_lists(Exec& ex, const KrgArgs<float, float>& a, int32_t* lists, int64_t* cnt, int64_t ldl) {
   const int64_t np = (int64_t)a.c.n_units * (a.c.n_units + 1) / 2;
   if (np <= 0 || a.N <= 0 || !launch_ok(ex)) return;
@@ -1158,7 +1175,7 @@ void krg_build_lists(Exec& ex, const KrgArgs<float, float>& a, uint8_t* flags, i
   const int64_t tc = krg_list_tiles(a);
   if (tc <= 0 || a.N <= 0 || !launch_ok(ex)) return;
   hipLaunchKernelGGL(k_list_flags, dim3((unsigned)((a.N + 255) / 256), (unsigned)a.c.n_units), dim3(256), 0,
-                     ex.stream, a.wts, a.ldw, a.r.n_units, a.c.n_units, a.N, flags);
+                     ex.stream, a.wts, a.ldw, a.r.n_units, a.c.n_units, a.N, 0, flags);
   hipLaunchKernelGGL(k_list_build, dim3((unsigned)tc), dim3(256), 0, ex.stream, flags, a.N, a.c.pad, a.c.n_units,
                      ldl, lists, cnt);
 }
@@ -1169,9 +1186,12 @@ void krg_build_lists(Exec& ex, const KrgArgs<float, float>& a, uint8_t* flags, i
 double krg_list_share(Exec& ex, const KrgArgs<float, float>& a) {
   const int64_t tcn = krg_list_tiles(a);
   const int64_t np = a.plist ? (int64_t)a.c.n_units * (a.c.n_units + 1) / 2 : 0;
-  std::vector<int64_t> cnt((size_t)tcn), pc((size_t)np);
+  const int64_t trn0 = ((int64_t)a.r.n_units * a.r.pad + BM - 1) / BM, nr = a.rlist ? trn0 : 0;
+  std::vector<int64_t> cnt((size_t)tcn), pc((size_t)np), rc((size_t)nr);
   if (hipMemcpyAsync(cnt.data(), a.kcnt, tcn * sizeof(int64_t), hipMemcpyDeviceToHost, ex.stream) != hipSuccess ||
       (np > 0 && hipMemcpyAsync(pc.data(), a.pcnt, np * sizeof(int64_t), hipMemcpyDeviceToHost, ex.stream) !=
+                     hipSuccess) ||
+      (nr > 0 && hipMemcpyAsync(rc.data(), a.rcnt, nr * sizeof(int64_t), hipMemcpyDeviceToHost, ex.stream) !=
                      hipSuccess) ||
       hipStreamSynchronize(ex.stream) != hipSuccess)
     return 1.0;
@@ -1196,6 +1216,7 @@ double krg_list_share(Exec& ex, const KrgArgs<float, float>& a) {
         const int64_t ul = r0 / a.r.pad, uh = std::min<int64_t>(a.r.n_units - 1, (r0 + BM - 1) / a.r.pad);
         const int64_t vl = c0 / a.c.pad, vh = std::min<int64_t>(a.c.n_units - 1, (c0 + BN - 1) / a.c.pad);
         if (ul == uh && vl == vh) c = pc[ul * (ul + 1) / 2 + vl];
+        else if (nr > 0 && rc[tr] < c) c = rc[tr];
       }
       all += e;
       done += e * (double)c / N;
