@@ -322,8 +322,8 @@ constexpr int DLD = 132;
 // as BF16 parts in MFMA operand order; A rows are unpadded (128-bit reads of 16 lanes
 // cover 256 contiguous bytes) and the pair weights go to registers, so that two
 // workgroups (2 x 80 KB) share a CU
-// LIST: the examples of a column tile come from its list (a.klist): rows of both sources
-// and the pair weights are gathered by example index
+// LIST: the tile sums over an example list (its unit pair's, its row tile's or its column
+// tile's; see KrgArgs): rows of both sources and the pair weights are gathered by example index
 template <int KC_, int NST_, bool SPLIT_ = false, bool BPS_ = false, bool LIST_ = false>
 struct DmaCfg {
   static constexpr int KC = KC_, NST = NST_;
@@ -404,7 +404,9 @@ __device__ __forceinline__ void krg_tile_dma(const KrgArgs<float, float>& a, int
   const int ur_hi = (int)min((int64_t)a.r.n_units - 1, (r0 + BM - 1) / a.r.pad);
   const int uc_hi = (int)min((int64_t)a.c.n_units - 1, (c0 + BN - 1) / a.c.pad);
   if (WMODE == KRG_PAIR_DIAG && (ur_hi < uc_lo || uc_hi < ur_lo)) return;
-  // examples summed by this tile: all N, or (LIST) the column tile's list
+  // examples summed by this tile: all N, or (LIST) its unit pair's list when its rows and its
+  // columns each lie in one unit (symmetric), else the shorter of its row tile's (symmetric)
+  // and column tile's lists
   int64_t NE = a.N;
   const int32_t* klist = nullptr;
   if constexpr (C::LIST) {
